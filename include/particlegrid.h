@@ -1,0 +1,201 @@
+/*
+ * particlegrid.h -- C ABI of the MI355X (gfx950) atoms -> density-grid library.
+ *
+ * The operation (ParticleGrid, §III-A "Voxel-filling Function", Eq. 1, and
+ * the §V programming interface `coord_to_grid`): given atoms (xyz plus an
+ * element type), a per-type Gaussian width sigma_t, and a grid (origin,
+ * spacing, dimensions), produce a dense multi-channel grid
+ *
+ *     G[b][c][z][y][x] = sum over atoms a of structure b with type c of
+ *                        exp(-|r(z,y,x) - mu_a|^2 / (2 sigma_c^2)),
+ *
+ * with r the voxel centre origin + (i + 1/2) * spacing on each axis, one
+ * channel per element type (§III-A), the squared distance replaced by the
+ * nearest-image distance for an orthorhombic periodic cell (§III-A, text
+ * after Eq. 1), and each atom truncated to a cube of half-width
+ * rc_t = fl32(cutoff_k * sigma_t) (threshold truncation, §VI-B): a voxel
+ * is inside iff |r_alpha - mu_alpha| <= rc_t on every axis, decided exactly
+ * on the float inputs.  The Gaussian is the un-normalised point sample at
+ * the voxel centre (the paper's Eq. 2-5 voxel integral is not this call).
+ *
+ * Conventions shared by every call:
+ *   - Layout: out is B x C x D x H x W, contiguous, x fastest (D = z,
+ *     H = y, W = x), i.e. NCDHW as a 3-D convolution consumes it.
+ *   - origin / spacing / cell are given in x, y, z order, in the same unit
+ *     as the coordinates (Angstrom in the benchmarks).
+ *   - Batches are ragged CSR: structure b owns atoms
+ *     [offsets[b], offsets[b+1]).
+ *   - All array arguments are DEVICE pointers (memory of the device the
+ *     context was created on) unless a field says "host".  The caller owns
+ *     every buffer; the library keeps no pointer after a call returns.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  The library writes every element of `out` (no pre-zeroing
+ *     needed); `out` must not alias any input.
+ *   - Every function returns a pg_status.  Host-side validation runs before
+ *     any launch; on error nothing is launched.  No exception crosses the
+ *     ABI.  Errors found in device data (a type outside [0, C), a
+ *     non-finite coordinate, a structure larger than the declared
+ *     max_atoms) cannot be reported synchronously: the atom is skipped (or
+ *     the structure's grid is written as zeros), a sticky device error word
+ *     is set, and pg_get_device_error() reports it after the stream is
+ *     synchronised.
+ */
+#ifndef PARTICLEGRID_H
+#define PARTICLEGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PG_ABI_VERSION 1
+#define PG_MAX_CHANNELS 64
+
+typedef enum pg_status {
+    PG_OK = 0,
+    PG_E_NULL = 1,         /* a required pointer is NULL */
+    PG_E_SHAPE = 2,        /* bad dims, channel count, batch sizes */
+    PG_E_PARAM = 3,        /* spacing / sigma / cutoff not positive-finite, bad enum */
+    PG_E_PERIODIC = 4,     /* periodic cell too small for the cutoff or the grid */
+    PG_E_WORKSPACE = 5,    /* workspace smaller than pg_workspace_size() */
+    PG_E_UNSUPPORTED = 6,  /* valid request this build does not serve */
+    PG_E_HIP = 7,          /* a HIP runtime call failed (see pg_last_hip_error) */
+    PG_E_DEVICE_DATA = 8,  /* device data error (pg_get_device_error) */
+    PG_E_CAPACITY = 9      /* a structure exceeded the declared max_atoms */
+} pg_status;
+
+enum { PG_OUT_F32 = 0, PG_OUT_BF16 = 1 };
+
+/* Kernel form.  AUTO lets the library choose (per-shape rule, refined by
+   pg_autotune).  PLAIN: one thread per voxel, one launch per structure (the
+   baseline form).  WINDOW: persistent cutoff-window gather, atoms staged in
+   LDS, one launch per batch.  MFMA: separable BF16 matrix-core
+   contraction per z-plane for large, dense structures. */
+enum { PG_FORM_AUTO = 0, PG_FORM_PLAIN = 1, PG_FORM_WINDOW = 2, PG_FORM_MFMA = 3 };
+
+/* Grid description (all fields host values). */
+typedef struct pg_grid_desc {
+    int32_t C, D, H, W;          /* channels (= element types) and grid dims z, y, x; >= 1 */
+    float origin[3];             /* lower grid corner, x y z; used when batch->origins == NULL */
+    float spacing[3];            /* voxel edge hx hy hz > 0; used when batch->spacings == NULL */
+    float cutoff_k;              /* cutoff in units of sigma_t (>= 0); 0 = no cutoff */
+    int32_t periodic;            /* 0/1: orthorhombic nearest image with cell[] */
+    float cell[3];               /* periodic cell edges Lx Ly Lz (periodic only) */
+    int32_t out_dtype;           /* PG_OUT_F32 or PG_OUT_BF16 (round-to-nearest-even) */
+    int32_t form;                /* PG_FORM_* */
+    float sigma[PG_MAX_CHANNELS];/* Gaussian width (standard deviation) per channel, > 0 */
+} pg_grid_desc;
+
+/* A ragged batch of structures (device arrays unless noted). */
+typedef struct pg_batch {
+    const float *xyz;            /* n_atoms x 3 float32 (x, y, z) */
+    const int32_t *types;        /* n_atoms int32 channel ids in [0, C) */
+    const int32_t *offsets;      /* n_mol + 1 int32 CSR bounds, offsets[0] = 0, non-decreasing */
+    const float *origins;        /* n_mol x 3 per-structure grid origins, or NULL */
+    const float *spacings;       /* n_mol x 3 per-structure spacings, or NULL (not with periodic) */
+    int32_t n_mol;               /* B >= 0 */
+    int32_t max_atoms;           /* host: upper bound of atoms in any one structure */
+    int64_t n_atoms;             /* host: offsets[n_mol]; 0 allowed */
+} pg_batch;
+
+typedef struct pg_ctx pg_ctx;
+
+/* Version of this ABI (PG_ABI_VERSION). */
+int pg_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *pg_status_str(int status);
+
+/* Create a context bound to HIP device `device`: it owns the sticky device
+   error word, the tuning table and the captured-graph cache.  Allocates a
+   few bytes of device memory once (not on the hot path).
+   Errors: PG_E_NULL, PG_E_HIP. */
+int pg_create(pg_ctx **ctx, int device);
+
+/* Destroy a context (waits for nothing; the caller synchronises first). */
+int pg_destroy(pg_ctx *ctx);
+
+/* Host-only validation of a request (no HIP call, no device access).
+   Checks dims, channel count, sigma/spacing/cutoff, periodic constraints
+   (rc_t < L/2 and grid extent + 2 rc_t <= 2 L on every axis, cutoff_k > 0),
+   batch sizes and non-NULL device pointers.  Returns PG_OK or the first
+   error found. */
+int pg_validate(const pg_grid_desc *desc, const pg_batch *batch);
+
+/* Bytes of caller-provided device workspace that pg_grid_forward and
+   pg_grid_backward need for this request (0 is possible).  Host only.
+   The form used is the one pg_grid_forward would pick (desc->form or the
+   AUTO rule); ctx may be NULL (then tuned choices are not consulted). */
+int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                      size_t *bytes);
+
+/* Forward map (§III-A Eq. 1 point-sampled, §V coord_to_grid): writes every
+   element of out (B x C x D x H x W of float32 or bf16 per
+   desc->out_dtype, 16-byte aligned for the vector path; any alignment is
+   accepted).  ws/ws_bytes: device workspace of at least
+   pg_workspace_size() bytes (may be NULL if that is 0).  stream: hipStream_t.
+   If the context's graph option is on, the launch sequence is captured
+   once per distinct argument set and replayed as a HIP graph.
+   Errors: validation codes, PG_E_WORKSPACE, PG_E_UNSUPPORTED, PG_E_HIP. */
+int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                    void *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint (§IV-C coordinate gradient, for the point-sampled form): given
+   grad_out = dL/dG (same shape and dtype as the forward's out), writes
+   grad_xyz[a][alpha] = sum over voxels v in the window of atom a of
+   grad_out[b][t_a][v] * g_a(v) * (r_alpha(v) - mu_alpha) / sigma_t^2,
+   with nearest-image offsets when periodic.  The cutoff edge contributes
+   nothing (derivative almost everywhere).  grad_xyz: n_atoms x 3 float32,
+   fully overwritten (skipped atoms get 0).
+   Errors: as pg_grid_forward. */
+int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                     const void *grad_out, float *grad_xyz, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Time the candidate kernel configurations (and, under AUTO, the forms)
+   for this request on `stream`, keep the fastest in the context's tuning
+   table (keyed by dims, channels, dtype, periodicity, batch size and atom
+   counts) and use it for later matching calls.  `out` is overwritten
+   (reps + 2) times per candidate.  Synchronises the stream.
+   Errors: as pg_grid_forward. */
+int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                void *out, void *ws, size_t ws_bytes, void *stream, int reps);
+
+/* Save / load the tuning table as JSON text (host file I/O only).  Loading
+   a missing or malformed file leaves the table empty and returns
+   PG_E_PARAM. */
+int pg_tuning_save(const pg_ctx *ctx, const char *path);
+int pg_tuning_load(pg_ctx *ctx, const char *path);
+
+/* Options: PG_OPT_GRAPH (0/1, default 0) -- replay captured HIP graphs for
+   repeated identical forward calls; PG_OPT_BLOCK, PG_OPT_GRID_PER_CU,
+   PG_OPT_NT_STORE -- override the window kernel's workgroup size, resident
+   workgroups per CU and non-temporal stores (-1 = tuned/default).
+   Errors: PG_E_NULL, PG_E_PARAM. */
+enum { PG_OPT_GRAPH = 1, PG_OPT_BLOCK = 2, PG_OPT_GRID_PER_CU = 3, PG_OPT_NT_STORE = 4 };
+int pg_set_option(pg_ctx *ctx, int option, int64_t value);
+
+/* Read and clear the sticky device error word (synchronises the context's
+   device).  code: PG_OK, PG_E_DEVICE_DATA or PG_E_CAPACITY; first_atom:
+   smallest global atom index (or structure index for PG_E_CAPACITY)
+   involved, -1 if none.  Errors: PG_E_NULL, PG_E_HIP. */
+int pg_get_device_error(pg_ctx *ctx, int32_t *code, int64_t *first_atom);
+
+/* The last hipError_t seen by this context (0 if none). */
+int pg_last_hip_error(const pg_ctx *ctx);
+
+/* Describe the kernel configuration pg_grid_forward would use for this
+   request: form, workgroup size, persistent workgroups, LDS bytes, vector
+   width, non-temporal stores.  Host only.  Errors: validation codes. */
+typedef struct pg_plan_info {
+    int32_t form, block, grid, lds_bytes, vec, nt_store, atom_capacity, reserved;
+} pg_plan_info;
+int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+            const void *out, pg_plan_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARTICLEGRID_H */

@@ -61,6 +61,11 @@ def _load():
     return lib
 
 
+def _f32(v) -> np.ndarray:
+    """float32-rounded values as float64."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
 def _ptr(a: Optional[np.ndarray], t):
     if a is None:
         return ctypes.cast(None, t)
@@ -81,18 +86,21 @@ class _Args:
             raise ValueError("sigma must have one entry per channel")
         self.D, self.H, self.W = (int(d) for d in dims)
         self.B = int(self.offsets.shape[0] - 1)
-        sp = np.broadcast_to(np.asarray(spacing, dtype=np.float64), (3,))
+        # Grid geometry (origin, spacing, cell) is single precision in the
+        # problem statement: the values are rounded to float32 once, then
+        # used exactly in FP64.  Coordinates stay as given (FP64 allowed, so
+        # that finite differences can perturb them).
+        sp = np.broadcast_to(_f32(spacing), (3,))
         self.spacing = np.ascontiguousarray(sp, dtype=np.float64)
-        og = np.zeros(3) if origin is None else np.broadcast_to(np.asarray(origin, dtype=np.float64), (3,))
+        og = np.zeros(3) if origin is None else np.broadcast_to(_f32(origin), (3,))
         self.origin = np.ascontiguousarray(og, dtype=np.float64)
         self.origins = None if origins is None else np.ascontiguousarray(
-            np.asarray(origins, dtype=np.float64).reshape(self.B, 3))
+            _f32(origins).reshape(self.B, 3))
         self.spacings = None if spacings is None else np.ascontiguousarray(
-            np.asarray(spacings, dtype=np.float64).reshape(self.B, 3))
+            _f32(spacings).reshape(self.B, 3))
         self.periodic = cell is not None
         self.cell = np.ascontiguousarray(
-            np.broadcast_to(np.asarray(cell if cell is not None else 0.0, dtype=np.float64), (3,)),
-            dtype=np.float64)
+            np.broadcast_to(_f32(cell if cell is not None else 0.0), (3,)), dtype=np.float64)
         self.k = float(np.float32(cutoff_k))
         if self.offsets[0] != 0 or self.offsets[-1] != self.xyz.shape[0]:
             raise ValueError("offsets must start at 0 and end at n_atoms")

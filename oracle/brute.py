@@ -47,9 +47,11 @@ def brute_fp64(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k=3.0,
     sigma = np.asarray(sigma, dtype=np.float32).reshape(-1)
     C = int(n_types if n_types is not None else sigma.shape[0])
     D, H, W = (int(d) for d in dims)
-    sp = np.broadcast_to(np.asarray(spacing, dtype=np.float64), (3,))
-    og = np.broadcast_to(np.asarray(origin, dtype=np.float64), (3,))
-    cl = None if cell is None else np.broadcast_to(np.asarray(cell, dtype=np.float64), (3,))
+    # grid geometry is single precision (rounded once), coordinates as given
+    sp = np.broadcast_to(np.asarray(spacing, dtype=np.float32).astype(np.float64), (3,))
+    og = np.broadcast_to(np.asarray(origin, dtype=np.float32).astype(np.float64), (3,))
+    cl = None if cell is None else np.broadcast_to(
+        np.asarray(cell, dtype=np.float32).astype(np.float64), (3,))
     B = offsets.shape[0] - 1
     out = np.zeros((B, C, D, H, W), dtype=np.float64)
     cut = float(np.float32(cutoff_k)) != 0.0

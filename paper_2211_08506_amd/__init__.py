@@ -1,0 +1,357 @@
+"""MI355X (gfx950) density-grid generation: atoms -> C x D x H x W Gaussian grids.
+
+Thin Python binding of the C-ABI library `libparticlegrid.so`
+(include/particlegrid.h).  It only marshals arguments: every step of the
+computation runs in the library's HIP kernels; PyTorch provides device
+memory and the stream.  Importing this package on a machine without the
+built library raises immediately -- there is no fallback path.
+
+    import torch, paper_2211_08506_amd as pg
+    g = pg.grid(xyz, types, offsets, sigma, dims=(32, 32, 32), spacing=0.5,
+                origin=(-8, -8, -8), out_dtype=torch.bfloat16)
+
+What is computed (ParticleGrid §III-A Eq. 1, point-sampled at voxel centres,
+one channel per element type, truncated per axis at fl32(k sigma_t) as in
+the threshold variant of §VI-B, nearest image for periodic cells): see the
+header for the exact definition.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence, Tuple, Union
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libparticlegrid.so")
+
+PG_OK = 0
+PG_E_NULL, PG_E_SHAPE, PG_E_PARAM, PG_E_PERIODIC = 1, 2, 3, 4
+PG_E_WORKSPACE, PG_E_UNSUPPORTED, PG_E_HIP, PG_E_DEVICE_DATA, PG_E_CAPACITY = 5, 6, 7, 8, 9
+PG_OUT_F32, PG_OUT_BF16 = 0, 1
+FORMS = {"auto": 0, "plain": 1, "window": 2, "mfma": 3}
+FORM_NAMES = {v: k for k, v in FORMS.items()}
+PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE = 1, 2, 3, 4
+MAX_CHANNELS = 64
+
+
+class PGError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _lib().pg_status_str(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_int32), ("D", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32),
+                ("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3),
+                ("cutoff_k", ctypes.c_float), ("periodic", ctypes.c_int32),
+                ("cell", ctypes.c_float * 3), ("out_dtype", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("sigma", ctypes.c_float * MAX_CHANNELS)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("types", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("origins", ctypes.c_void_p),
+                ("spacings", ctypes.c_void_p), ("n_mol", ctypes.c_int32),
+                ("max_atoms", ctypes.c_int32), ("n_atoms", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("form", "block", "grid", "lds_bytes", "vec", "nt_store", "atom_capacity",
+                 "reserved")]
+
+
+_LIB = None
+_LIB_LOCK = threading.Lock()
+
+EXPORTS = ("pg_abi_version", "pg_status_str", "pg_create", "pg_destroy", "pg_validate",
+           "pg_workspace_size", "pg_grid_forward", "pg_grid_backward", "pg_autotune",
+           "pg_tuning_save", "pg_tuning_load", "pg_set_option", "pg_get_device_error",
+           "pg_last_hip_error", "pg_plan")
+
+
+def _lib():
+    """Load libparticlegrid.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    with _LIB_LOCK:
+        if _LIB is not None:
+            return _LIB
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2211_08506_amd.build` (or __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER
+        lib.pg_abi_version.restype = ctypes.c_int
+        lib.pg_status_str.restype = ctypes.c_char_p
+        lib.pg_status_str.argtypes = [ctypes.c_int]
+        lib.pg_create.argtypes = [P(vp), ctypes.c_int]
+        lib.pg_destroy.argtypes = [vp]
+        lib.pg_validate.argtypes = [P(GridDesc), P(Batch)]
+        lib.pg_workspace_size.argtypes = [vp, P(GridDesc), P(Batch), P(ctypes.c_size_t)]
+        lib.pg_grid_forward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, ctypes.c_size_t, vp]
+        lib.pg_grid_backward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, vp, ctypes.c_size_t,
+                                         vp]
+        lib.pg_autotune.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, ctypes.c_size_t, vp,
+                                    ctypes.c_int]
+        lib.pg_tuning_save.argtypes = [vp, ctypes.c_char_p]
+        lib.pg_tuning_load.argtypes = [vp, ctypes.c_char_p]
+        lib.pg_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
+        lib.pg_get_device_error.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int64)]
+        lib.pg_last_hip_error.argtypes = [vp]
+        lib.pg_plan.argtypes = [vp, P(GridDesc), P(Batch), vp, P(PlanInfo)]
+        for name in EXPORTS:
+            getattr(lib, name).restype = ctypes.c_int if name != "pg_status_str" else ctypes.c_char_p
+        _LIB = lib
+        return lib
+
+
+def _check(status: int, what: str):
+    if status != PG_OK:
+        raise PGError(status, what)
+
+
+def _f3(v) -> Tuple[float, float, float]:
+    if isinstance(v, (int, float)):
+        return (float(v),) * 3
+    v = tuple(float(x) for x in v)
+    if len(v) != 3:
+        raise ValueError("expected a scalar or 3 values (x, y, z)")
+    return v
+
+
+def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigma=(),
+              cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32,
+              form: Union[str, int] = "auto") -> GridDesc:
+    """Build a pg_grid_desc (host struct).  dims = (D, H, W) = (z, y, x);
+    origin / spacing / cell in x, y, z order; sigma one value per channel."""
+    d = GridDesc()
+    d.C = int(C)
+    d.D, d.H, d.W = (int(x) for x in dims)
+    d.origin[:] = _f3(origin)
+    d.spacing[:] = _f3(spacing)
+    d.cutoff_k = float(cutoff_k)
+    d.periodic = 0 if cell is None else 1
+    d.cell[:] = _f3(cell if cell is not None else 0.0)
+    if out_dtype in (torch.float32, "f32", PG_OUT_F32):
+        d.out_dtype = PG_OUT_F32
+    elif out_dtype in (torch.bfloat16, "bf16", PG_OUT_BF16):
+        d.out_dtype = PG_OUT_BF16
+    else:
+        raise ValueError(f"unsupported out_dtype {out_dtype}")
+    d.form = FORMS[form] if isinstance(form, str) else int(form)
+    sig = [float(s) for s in sigma]
+    if len(sig) > MAX_CHANNELS:
+        raise ValueError(f"at most {MAX_CHANNELS} channels")
+    for i, s in enumerate(sig):
+        d.sigma[i] = s
+    return d
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class BatchView:
+    """Device-resident CSR batch plus the host facts the ABI needs.  Keeps
+    the tensors alive while the library may use them."""
+
+    def __init__(self, xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor,
+                 origins: Optional[torch.Tensor] = None, spacings: Optional[torch.Tensor] = None,
+                 max_atoms: Optional[int] = None, offsets_host=None):
+        dev = xyz.device
+        if dev.type != "cuda":
+            raise ValueError("xyz must be a device (cuda/hip) tensor")
+        self.xyz = xyz.to(torch.float32).contiguous()
+        if self.xyz.dim() != 2 or self.xyz.shape[1] != 3:
+            raise ValueError("xyz must have shape (n_atoms, 3)")
+        self.types = types.to(device=dev, dtype=torch.int32).contiguous()
+        self.offsets = offsets.to(device=dev, dtype=torch.int32).contiguous()
+        self.origins = None if origins is None else origins.to(device=dev, dtype=torch.float32).contiguous()
+        self.spacings = None if spacings is None else spacings.to(device=dev, dtype=torch.float32).contiguous()
+        self.n_mol = int(self.offsets.shape[0]) - 1
+        self.n_atoms = int(self.xyz.shape[0])
+        if self.types.shape[0] != self.n_atoms:
+            raise ValueError("types must have one entry per atom")
+        if max_atoms is None:
+            oh = offsets_host if offsets_host is not None else offsets.detach().to("cpu")
+            oh = torch.as_tensor(oh, dtype=torch.int64)
+            max_atoms = int((oh[1:] - oh[:-1]).max().item()) if self.n_mol > 0 else 0
+        self.max_atoms = int(max_atoms)
+        b = Batch()
+        b.xyz = _ptr(self.xyz)
+        b.types = _ptr(self.types)
+        b.offsets = _ptr(self.offsets)
+        b.origins = _ptr(self.origins)
+        b.spacings = _ptr(self.spacings)
+        b.n_mol = self.n_mol
+        b.max_atoms = self.max_atoms
+        b.n_atoms = self.n_atoms
+        self.c = b
+
+
+class Context:
+    """A library context on one device (error word, tuning table, graph
+    cache) plus a cached torch workspace buffer."""
+
+    def __init__(self, device: Union[int, torch.device, None] = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        if isinstance(device, torch.device):
+            device = device.index if device.index is not None else torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(_lib().pg_create(ctypes.byref(h), self.device), "pg_create")
+        self.handle = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            try:
+                _LIB.pg_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def workspace(self, nbytes: int) -> Optional[torch.Tensor]:
+        if nbytes == 0:
+            return None
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def set_option(self, option: int, value: int):
+        _check(_lib().pg_set_option(self.handle, option, int(value)), "pg_set_option")
+
+    def device_error(self) -> Tuple[int, int]:
+        code = ctypes.c_int32()
+        first = ctypes.c_int64()
+        _check(_lib().pg_get_device_error(self.handle, ctypes.byref(code), ctypes.byref(first)),
+               "pg_get_device_error")
+        return code.value, first.value
+
+    def plan(self, desc: GridDesc, batch: BatchView, out: Optional[torch.Tensor] = None) -> dict:
+        info = PlanInfo()
+        _check(_lib().pg_plan(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
+                              _ptr(out), ctypes.byref(info)), "pg_plan")
+        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_ if n != "reserved"}
+        d["form"] = FORM_NAMES.get(d["form"], d["form"])
+        return d
+
+    def workspace_size(self, desc: GridDesc, batch: BatchView) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib().pg_workspace_size(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
+                                        ctypes.byref(n)), "pg_workspace_size")
+        return int(n.value)
+
+    def forward(self, desc: GridDesc, batch: BatchView, out: torch.Tensor,
+                stream: Optional[torch.cuda.Stream] = None):
+        nbytes = self.workspace_size(desc, batch)
+        ws = self.workspace(nbytes)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(_lib().pg_grid_forward(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
+                                      _ptr(out), _ptr(ws), nbytes, s.cuda_stream),
+               "pg_grid_forward")
+        return out
+
+    def backward(self, desc: GridDesc, batch: BatchView, grad_out: torch.Tensor,
+                 grad_xyz: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(_lib().pg_grid_backward(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
+                                       _ptr(grad_out), _ptr(grad_xyz), None, 0, s.cuda_stream),
+               "pg_grid_backward")
+        return grad_xyz
+
+    def autotune(self, desc: GridDesc, batch: BatchView, out: torch.Tensor, reps: int = 5,
+                 stream: Optional[torch.cuda.Stream] = None):
+        nbytes = self.workspace_size(desc, batch)
+        ws = self.workspace(nbytes)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(_lib().pg_autotune(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
+                                  _ptr(out), _ptr(ws), nbytes, s.cuda_stream, int(reps)),
+               "pg_autotune")
+
+    def tuning_save(self, path: str):
+        _check(_lib().pg_tuning_save(self.handle, path.encode()), "pg_tuning_save")
+
+    def tuning_load(self, path: str):
+        _check(_lib().pg_tuning_load(self.handle, path.encode()), "pg_tuning_load")
+
+
+_CTX = {}
+
+
+def default_context(device=None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if isinstance(device, torch.device):
+        device = device.index if device.index is not None else torch.cuda.current_device()
+    if device not in _CTX:
+        _CTX[device] = Context(device)
+    return _CTX[device]
+
+
+def empty_grid(desc: GridDesc, n_mol: int, device) -> torch.Tensor:
+    dt = torch.bfloat16 if desc.out_dtype == PG_OUT_BF16 else torch.float32
+    return torch.empty((n_mol, desc.C, desc.D, desc.H, desc.W), dtype=dt, device=device)
+
+
+class GridFn(torch.autograd.Function):
+    """Differentiable w.r.t. xyz: forward -> pg_grid_forward, backward ->
+    pg_grid_backward (the coordinate adjoint)."""
+
+    @staticmethod
+    def forward(ctx_, xyz, types, offsets, origins, spacings, desc, max_atoms, pgctx):
+        batch = BatchView(xyz.detach(), types, offsets, origins, spacings, max_atoms=max_atoms)
+        out = empty_grid(desc, batch.n_mol, xyz.device)
+        pgctx.forward(desc, batch, out)
+        ctx_.batch = batch
+        ctx_.desc = desc
+        ctx_.pgctx = pgctx
+        return out
+
+    @staticmethod
+    def backward(ctx_, grad_out):
+        batch = ctx_.batch
+        g = grad_out.contiguous()
+        want = torch.bfloat16 if ctx_.desc.out_dtype == PG_OUT_BF16 else torch.float32
+        if g.dtype != want:
+            g = g.to(want)
+        grad_xyz = torch.empty_like(batch.xyz)
+        ctx_.pgctx.backward(ctx_.desc, batch, g, grad_xyz)
+        return grad_xyz, None, None, None, None, None, None, None
+
+
+def grid(xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor, sigma: Sequence[float], *,
+         dims: Sequence[int], spacing=0.5, origin=(0.0, 0.0, 0.0), origins=None, spacings=None,
+         cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32, form: str = "auto",
+         n_channels: Optional[int] = None, max_atoms: Optional[int] = None,
+         ctx: Optional[Context] = None) -> torch.Tensor:
+    """Density grids (B, C, D, H, W) for a ragged batch (differentiable in xyz).
+
+    xyz (n_atoms, 3) float32, types (n_atoms,) int, offsets (B+1,) int CSR,
+    all on the same device; sigma: one width per channel (C = len(sigma)
+    unless n_channels is given)."""
+    C = int(n_channels if n_channels is not None else len(sigma))
+    desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form)
+    pgctx = ctx if ctx is not None else default_context(xyz.device)
+    return GridFn.apply(xyz, types, offsets, origins, spacings, desc, max_atoms, pgctx)
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def abi_version() -> int:
+    return int(_lib().pg_abi_version())
+
+
+# fail loudly at import if the library is missing
+_lib()

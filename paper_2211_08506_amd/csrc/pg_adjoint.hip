@@ -1,0 +1,161 @@
+// pg_adjoint.hip -- coordinate adjoint of the density grid on gfx950.
+//
+// For L = sum_v U[v] G[v] and the point-sampled Gaussian of §III-A Eq. 1,
+//   dL/dmu_{a,alpha} = sum_{v in window(a)} U[b, t_a, v] g_a(v) d_alpha(v) / sigma^2,
+// with d = r - mu (nearest image when periodic) and g_a the atom's
+// separable Gaussian.  This is the point-sample counterpart of the
+// separable coordinate gradient of §IV-C (chain rule through the product
+// of per-axis factors); the cutoff edge contributes nothing (the map is
+// differentiable almost everywhere).
+//
+// One wave per atom, any structure size: the wave builds its atom's 1-D
+// factor and offset lists over the window (per-wave LDS), then its lanes
+// sweep the window with x fastest -- lanes of one window row read
+// consecutive addresses -- and the three partial sums are reduced across
+// the wave.  No atomics; each atom's gradient is written by one lane.
+#include "pg_device.hpp"
+#include "pg_launch.hpp"
+
+namespace pg {
+
+__device__ __forceinline__ int structure_of_atom(const int32_t *offsets, int n_mol, long long a)
+{
+    int lo = 0, hi = n_mol;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)offsets[mid] <= a)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+        v += __shfl_xor(v, s, 64);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const long long a = (long long)blockIdx.x * waves + wave;
+    const bool active = a < p.n_atoms;
+    const int NT = p.W + p.H + p.D;
+    // per-wave slice: idx[NT] (int) | phi[NT] | del[NT] | 3 range records
+    int *idx = (int *)(smem + (size_t)wave * (NT * 12 + 3 * sizeof(AxisRanges)));
+    float *phi = (float *)(idx + NT);
+    float *del = phi + NT;
+    AxisRanges *rg = (AxisRanges *)(del + NT);
+    const int base[3] = {0, p.W, p.W + p.H};
+    const int N[3] = {p.W, p.H, p.D};   // indexed by the compile-time axis only
+
+    float mu[3] = {0.f, 0.f, 0.f};
+    int t = -1, m = 0;
+    float o[3] = {0.f, 0.f, 0.f}, h[3] = {1.f, 1.f, 1.f};
+    if (active) {
+        mu[0] = p.xyz[3 * a];
+        mu[1] = p.xyz[3 * a + 1];
+        mu[2] = p.xyz[3 * a + 2];
+        t = p.types[a];
+        if (!atom_valid(mu[0], mu[1], mu[2], t, p.C)) {
+            if (lane == 0)
+                raise_error(p.err, PG_E_DEVICE_DATA, a);
+            t = -1;
+        } else {
+            m = structure_of_atom(p.offsets, p.n_mol, a);
+            for (int q = 0; q < 3; ++q) {
+                o[q] = p.origins ? p.origins[3 * m + q] : p.o[q];
+                h[q] = p.spacings ? p.spacings[3 * m + q] : p.h[q];
+            }
+        }
+    }
+    // lanes 0..2: window ranges of the three axes
+    if (t >= 0 && lane < 3) {
+        const int q = lane;
+        const float oq = q == 0 ? o[0] : (q == 1 ? o[1] : o[2]);
+        const float hq = q == 0 ? h[0] : (q == 1 ? h[1] : h[2]);
+        const float mq = q == 0 ? mu[0] : (q == 1 ? mu[1] : mu[2]);
+        const float Lq = q == 0 ? p.L[0] : (q == 1 ? p.L[1] : p.L[2]);
+        axis_ranges(oq, hq, N[q], mq, p.periodic != 0, Lq, p.rc[t], p.cut != 0, rg[q]);
+    }
+    __syncthreads();
+    int n[3] = {0, 0, 0};
+    if (t >= 0) {
+        for (int q = 0; q < 3; ++q) {
+            const AxisRanges &R = rg[q];
+            int k0 = 0;
+            for (int r = 0; r < R.n; ++r) {
+                const int len = R.hi[r] - R.lo[r] + 1;
+                for (int k = lane; k < len; k += 64) {
+                    const int i = R.lo[r] + k;
+                    const float d = offset_at(R.bh[r], R.bl[r], h[q], i);
+                    idx[base[q] + k0 + k] = i;
+                    del[base[q] + k0 + k] = d;
+                    phi[base[q] + k0 + k] = gauss1d(d, p.inv2s2[t]);
+                }
+                k0 += len;
+            }
+            n[q] = k0;
+        }
+    }
+    __syncthreads();
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (t >= 0) {
+        const size_t plane = (size_t)p.H * p.W;
+        const T *U = (const T *)p.out + ((size_t)m * p.C + t) * (size_t)p.D * plane;
+        const int nx = n[0], ny = n[1], nz = n[2];
+        const int total = nx * ny * nz;
+        for (int e = lane; e < total; e += 64) {
+            const int kx = e % nx;
+            const int r = e / nx;
+            const int ky = r % ny;
+            const int kz = r / ny;
+            const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
+            const float u = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
+            const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
+            const float w = u * (fx * fy * fz);
+            gx = __builtin_fmaf(w, del[kx], gx);
+            gy = __builtin_fmaf(w, del[base[1] + ky], gy);
+            gz = __builtin_fmaf(w, del[base[2] + kz], gz);
+        }
+    }
+    gx = wave_sum(gx);
+    gy = wave_sum(gy);
+    gz = wave_sum(gz);
+    if (active && lane == 0) {
+        const float s = t >= 0 ? p.invs2[t] : 0.f;
+        p.grad_xyz[3 * a + 0] = gx * s;
+        p.grad_xyz[3 * a + 1] = gy * s;
+        p.grad_xyz[3 * a + 2] = gz * s;
+    }
+}
+
+hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s)
+{
+    if (p.n_atoms == 0)
+        return hipSuccess;
+    const int block = 256, waves = block / 64;
+    const size_t lds = (size_t)waves * ((size_t)(p.W + p.H + p.D) * 12 + 3 * sizeof(AxisRanges));
+    const long long grid = (p.n_atoms + waves - 1) / waves;
+    if (grad_dtype == PG_OUT_F32) {
+        if (lds > 65536)
+            hipFuncSetAttribute((const void *)adjoint_kernel<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(adjoint_kernel<float>, dim3((unsigned)grid), dim3(block), lds, s, p);
+    } else {
+        if (lds > 65536)
+            hipFuncSetAttribute((const void *)adjoint_kernel<__bf16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(adjoint_kernel<__bf16>, dim3((unsigned)grid), dim3(block), lds, s, p);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pg

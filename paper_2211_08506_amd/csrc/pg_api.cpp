@@ -1,0 +1,725 @@
+// pg_api.cpp -- host runtime and C ABI of the gfx950 density-grid library.
+//
+// Responsibilities: request validation (host only, before any launch),
+// choice of kernel form and launch shape (per-shape rule plus a measured
+// tuning table), the captured-HIP-graph cache for repeated identical
+// calls, the sticky device error word, and the pg_* exports declared in
+// include/particlegrid.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <list>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/particlegrid.h"
+#include "pg_launch.hpp"
+#include "pg_params.hpp"
+
+using namespace pg;
+
+namespace {
+
+constexpr int kWindowMaxAtoms = 256;   // 4 x 64-bit plane masks
+constexpr int kGraphCacheSize = 32;
+
+struct Tuned {
+    int block = 0, per_cu = 0, nt = -1;
+    double us = 0.0;
+};
+
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct pg_ctx {
+    int device = 0;
+    int n_cu = 256;
+    int max_lds = 65536;
+    std::string arch;
+    DeviceError *d_err = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int last_hip = 0;
+    // options
+    int use_graph = 0;
+    int opt_block = -1, opt_per_cu = -1, opt_nt = -1;
+    std::map<std::string, Tuned> tuning;
+    std::list<GraphEntry> graphs;   // most recent first
+    std::mutex mu;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard()
+    {
+        if (changed)
+            hipSetDevice(prev);
+    }
+};
+
+int hip_fail(pg_ctx *ctx, hipError_t e)
+{
+    if (ctx)
+        ctx->last_hip = (int)e;
+    return PG_E_HIP;
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+float rc_of(const pg_grid_desc *d, int c)
+{
+    volatile float r = d->cutoff_k * d->sigma[c];   // fl32(k * sigma)
+    return r;
+}
+
+int validate(const pg_grid_desc *d, const pg_batch *b)
+{
+    if (!d || !b)
+        return PG_E_NULL;
+    if (d->C < 1 || d->C > PG_MAX_CHANNELS || d->D < 1 || d->H < 1 || d->W < 1)
+        return PG_E_SHAPE;
+    if (d->D > 32767 || d->H > 32767 || d->W > 32767)
+        return PG_E_SHAPE;
+    const double vol = (double)d->C * d->D * d->H * d->W;
+    if (vol > 2147483647.0)
+        return PG_E_SHAPE;
+    if (b->n_mol < 0 || b->n_atoms < 0 || b->max_atoms < 0)
+        return PG_E_SHAPE;
+    if (b->n_atoms > 2147483647LL)
+        return PG_E_SHAPE;
+    if (b->n_atoms > 0 && b->max_atoms == 0)
+        return PG_E_SHAPE;
+    if (b->n_atoms > 0 && b->n_mol == 0)
+        return PG_E_SHAPE;
+    if (b->max_atoms > b->n_atoms)
+        return PG_E_SHAPE;
+    if (d->out_dtype != PG_OUT_F32 && d->out_dtype != PG_OUT_BF16)
+        return PG_E_PARAM;
+    if (d->form < PG_FORM_AUTO || d->form > PG_FORM_MFMA)
+        return PG_E_PARAM;
+    for (int q = 0; q < 3; ++q) {
+        if (!finite_pos(d->spacing[q]) || !std::isfinite(d->origin[q]))
+            return PG_E_PARAM;
+    }
+    if (!std::isfinite(d->cutoff_k) || d->cutoff_k < 0.f)
+        return PG_E_PARAM;
+    for (int c = 0; c < d->C; ++c)
+        if (!finite_pos(d->sigma[c]))
+            return PG_E_PARAM;
+    if (d->periodic != 0 && d->periodic != 1)
+        return PG_E_PARAM;
+    if (d->periodic) {
+        if (d->cutoff_k == 0.f)
+            return PG_E_PERIODIC;
+        if (b->spacings)
+            return PG_E_UNSUPPORTED;
+        const int N[3] = {d->W, d->H, d->D};
+        for (int q = 0; q < 3; ++q) {
+            if (!finite_pos(d->cell[q]))
+                return PG_E_PERIODIC;
+            for (int c = 0; c < d->C; ++c) {
+                const double rc = rc_of(d, c);
+                if (!(rc < 0.5 * (double)d->cell[q]))
+                    return PG_E_PERIODIC;
+                if ((double)N[q] * d->spacing[q] + 2.0 * rc > 2.0 * (double)d->cell[q])
+                    return PG_E_PERIODIC;
+            }
+        }
+    }
+    if (b->n_mol > 0 && !b->offsets)
+        return PG_E_NULL;
+    if (b->n_atoms > 0 && (!b->xyz || !b->types))
+        return PG_E_NULL;
+    return PG_OK;
+}
+
+struct Plan {
+    int form = PG_FORM_WINDOW;
+    int block = 256, grid = 1, per_cu = 1, vec = 1, nt = 1;
+    int a_cap = 8, row_stride = 4, mask_words = 1;
+    size_t lds = 0;
+    size_t ws = 0;
+};
+
+std::string tuning_key(const pg_grid_desc *d, const pg_batch *b, int vec)
+{
+    int nb = 0;
+    while ((1 << nb) < std::max(1, b->n_mol))
+        ++nb;
+    int ma = 8;
+    while (ma < b->max_atoms)
+        ma <<= 1;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "C%d_D%d_H%d_W%d_%s_p%d_v%d_nb%d_ma%d", d->C, d->D, d->H,
+                  d->W, d->out_dtype == PG_OUT_BF16 ? "bf16" : "f32", d->periodic, vec, nb, ma);
+    return buf;
+}
+
+int pick_vec(const pg_grid_desc *d, const void *out)
+{
+    const int esz = d->out_dtype == PG_OUT_BF16 ? 2 : 4;
+    const int maxv = 16 / esz;
+    for (int v = maxv; v > 1; v >>= 1) {
+        if (d->W % v == 0 && ((uintptr_t)out % (uintptr_t)(v * esz)) == 0)
+            return v;
+    }
+    return 1;
+}
+
+bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Plan &P)
+{
+    if (b->max_atoms > kWindowMaxAtoms)
+        return false;
+    P.a_cap = std::max(8, (b->max_atoms + 7) & ~7);
+    const int W4 = (d->W + 3) & ~3;
+    P.row_stride = (W4 + d->H + d->D + 3) & ~3;
+    P.mask_words = (P.a_cap + 63) / 64;
+    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words).total;
+    const int max_lds = ctx ? ctx->max_lds : 65536;
+    return P.lds <= (size_t)max_lds;
+}
+
+int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const void *out, Plan &P)
+{
+    int s = validate(d, b);
+    if (s != PG_OK)
+        return s;
+    P.vec = pick_vec(d, out);
+    const bool fits = window_fits(ctx, d, b, P);
+    int form = d->form;
+    if (form == PG_FORM_AUTO)
+        form = fits ? PG_FORM_WINDOW : PG_FORM_MFMA;
+    P.form = form;
+    if (form == PG_FORM_MFMA)
+        return PG_E_UNSUPPORTED;
+    if (form == PG_FORM_WINDOW && !fits)
+        return PG_E_UNSUPPORTED;
+    if (form == PG_FORM_PLAIN) {
+        P.ws = (size_t)b->n_atoms * sizeof(AtomWindow);
+        P.ws = (P.ws + 255) & ~(size_t)255;
+        P.block = 256;
+        return PG_OK;
+    }
+    // window form: launch shape from options > tuning table > occupancy
+    P.ws = 0;
+    P.block = 256;
+    P.nt = 1;
+    P.per_cu = 0;
+    if (ctx) {
+        auto it = ctx->tuning.find(tuning_key(d, b, P.vec));
+        if (it != ctx->tuning.end()) {
+            P.block = it->second.block;
+            P.per_cu = it->second.per_cu;
+            P.nt = it->second.nt;
+        }
+        if (ctx->opt_block > 0)
+            P.block = ctx->opt_block;
+        if (ctx->opt_per_cu > 0)
+            P.per_cu = ctx->opt_per_cu;
+        if (ctx->opt_nt >= 0)
+            P.nt = ctx->opt_nt;
+    }
+    if (P.per_cu <= 0)
+        P.per_cu = ctx ? window_occupancy(d->out_dtype, P.vec, P.block, P.lds) : 4;
+    const int n_cu = ctx ? ctx->n_cu : 256;
+    P.grid = std::max(1, std::min(b->n_mol, n_cu * P.per_cu));
+    return PG_OK;
+}
+
+void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b,
+                 const Plan &P, void *out, void *ws)
+{
+    std::memset(&p, 0, sizeof p);
+    p.xyz = b->xyz;
+    p.types = b->types;
+    p.offsets = b->offsets;
+    p.origins = b->origins;
+    p.spacings = b->spacings;
+    p.out = out;
+    p.ws = ws;
+    p.err = ctx->d_err;
+    p.n_mol = b->n_mol;
+    p.n_atoms = b->n_atoms;
+    p.C = d->C;
+    p.D = d->D;
+    p.H = d->H;
+    p.W = d->W;
+    p.periodic = d->periodic;
+    p.cut = d->cutoff_k != 0.f;
+    p.a_cap = P.a_cap;
+    p.row_stride = P.row_stride;
+    p.mask_words = P.mask_words;
+    p.nt_store = P.nt;
+    for (int q = 0; q < 3; ++q) {
+        p.o[q] = d->origin[q];
+        p.h[q] = d->spacing[q];
+        p.L[q] = d->periodic ? d->cell[q] : 0.f;
+    }
+    for (int c = 0; c < d->C; ++c) {
+        const double s = d->sigma[c];
+        p.rc[c] = rc_of(d, c);
+        p.inv2s2[c] = (float)(1.0 / (2.0 * s * s));
+        p.invs2[c] = (float)(1.0 / (s * s));
+    }
+}
+
+hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, GridParams &p,
+                          hipStream_t s)
+{
+    if (p.n_mol == 0)
+        return hipSuccess;
+    if (P.form == PG_FORM_PLAIN) {
+        hipError_t e = launch_prep(p, s);
+        if (e != hipSuccess)
+            return e;
+        for (int m = 0; m < p.n_mol; ++m) {
+            p.mol_index = m;
+            e = launch_plain(p, d->out_dtype, s);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
+    return launch_window(p, d->out_dtype, P.vec, P.block, P.grid, P.lds, s);
+}
+
+std::string graph_key(const pg_grid_desc *d, const pg_batch *b, const Plan &P, const void *out,
+                      const void *ws, size_t ws_bytes)
+{
+    std::string k;
+    k.append((const char *)d, sizeof *d);
+    k.append((const char *)b, sizeof *b);
+    k.append((const char *)&P, sizeof P);
+    k.append((const char *)&out, sizeof out);
+    k.append((const char *)&ws, sizeof ws);
+    k.append((const char *)&ws_bytes, sizeof ws_bytes);
+    return k;
+}
+
+int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *out, void *ws,
+                 size_t ws_bytes, hipStream_t s, const Plan &P)
+{
+    if (b->n_mol > 0 && !out)
+        return PG_E_NULL;
+    if (ws_bytes < P.ws || (P.ws > 0 && !ws))
+        return PG_E_WORKSPACE;
+    GridParams p;
+    fill_params(p, ctx, d, b, P, out, ws);
+    if (!ctx->use_graph || b->n_mol == 0) {
+        hipError_t e = launch_forward(ctx, d, P, p, s);
+        return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+    }
+    const std::string key = graph_key(d, b, P, out, ws, ws_bytes);
+    auto it = std::find_if(ctx->graphs.begin(), ctx->graphs.end(),
+                           [&](const GraphEntry &g) { return g.key == key; });
+    if (it == ctx->graphs.end()) {
+        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+        hipError_t le = launch_forward(ctx, d, P, p, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g)
+                hipGraphDestroy(g);
+            return hip_fail(ctx, le != hipSuccess ? le : e);
+        }
+        GraphEntry ent;
+        ent.key = key;
+        e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+        ctx->graphs.push_front(std::move(ent));
+        if ((int)ctx->graphs.size() > kGraphCacheSize) {
+            hipGraphExecDestroy(ctx->graphs.back().exec);
+            ctx->graphs.pop_back();
+        }
+        it = ctx->graphs.begin();
+    } else if (it != ctx->graphs.begin()) {
+        ctx->graphs.splice(ctx->graphs.begin(), ctx->graphs, it);
+        it = ctx->graphs.begin();
+    }
+    hipError_t e = hipGraphLaunch(it->exec, s);
+    return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+}
+
+void drop_graphs(pg_ctx *ctx)
+{
+    for (auto &g : ctx->graphs)
+        hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int pg_abi_version(void) { return PG_ABI_VERSION; }
+
+const char *pg_status_str(int status)
+{
+    switch (status) {
+    case PG_OK: return "ok";
+    case PG_E_NULL: return "required pointer is NULL";
+    case PG_E_SHAPE: return "invalid dimensions, channel count or batch sizes";
+    case PG_E_PARAM: return "invalid parameter (spacing, sigma, cutoff, dtype or form)";
+    case PG_E_PERIODIC: return "periodic cell too small for the cutoff or the grid";
+    case PG_E_WORKSPACE: return "workspace too small";
+    case PG_E_UNSUPPORTED: return "request not supported by this build";
+    case PG_E_HIP: return "HIP runtime error";
+    case PG_E_DEVICE_DATA: return "invalid device data (atom type out of range or non-finite coordinate)";
+    case PG_E_CAPACITY: return "a structure exceeds the declared max_atoms";
+    default: return "unknown status";
+    }
+}
+
+int pg_create(pg_ctx **out, int device)
+{
+    if (!out)
+        return PG_E_NULL;
+    *out = nullptr;
+    pg_ctx *ctx = new pg_ctx();
+    ctx->device = device;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return PG_E_HIP;
+    }
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        lds > 0)
+        ctx->max_lds = lds;
+    e = hipMalloc((void **)&ctx->d_err, sizeof(DeviceError));
+    if (e == hipSuccess) {
+        DeviceError z = {0u, 0u, ~0ull};
+        e = hipMemcpy(ctx->d_err, &z, sizeof z, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (ctx->d_err)
+            hipFree(ctx->d_err);
+        delete ctx;
+        return PG_E_HIP;
+    }
+    *out = ctx;
+    return PG_OK;
+}
+
+int pg_destroy(pg_ctx *ctx)
+{
+    if (!ctx)
+        return PG_E_NULL;
+    {
+        DeviceGuard g(ctx->device);
+        drop_graphs(ctx);
+        if (ctx->cap_stream)
+            hipStreamDestroy(ctx->cap_stream);
+        if (ctx->d_err)
+            hipFree(ctx->d_err);
+    }
+    delete ctx;
+    return PG_OK;
+}
+
+int pg_validate(const pg_grid_desc *desc, const pg_batch *batch) { return validate(desc, batch); }
+
+int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                      size_t *bytes)
+{
+    if (!bytes)
+        return PG_E_NULL;
+    *bytes = 0;
+    Plan P;
+    int s = make_plan(ctx, desc, batch, nullptr, P);
+    if (s != PG_OK)
+        return s;
+    *bytes = P.ws;
+    return PG_OK;
+}
+
+int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, const void *out,
+            pg_plan_info *info)
+{
+    if (!info)
+        return PG_E_NULL;
+    Plan P;
+    int s = make_plan(ctx, desc, batch, out, P);
+    if (s != PG_OK)
+        return s;
+    info->form = P.form;
+    info->block = P.block;
+    info->grid = P.form == PG_FORM_PLAIN ? batch->n_mol : P.grid;
+    info->lds_bytes = (int32_t)P.lds;
+    info->vec = P.vec;
+    info->nt_store = P.nt;
+    info->atom_capacity = P.a_cap;
+    info->reserved = 0;
+    return PG_OK;
+}
+
+int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, void *out,
+                    void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Plan P;
+    int s = make_plan(ctx, desc, batch, out, P);
+    if (s != PG_OK)
+        return s;
+    DeviceGuard g(ctx->device);
+    return forward_impl(ctx, desc, batch, out, ws, ws_bytes, (hipStream_t)stream, P);
+}
+
+int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                     const void *grad_out, float *grad_xyz, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)ws;
+    (void)ws_bytes;
+    if (!ctx)
+        return PG_E_NULL;
+    int s = validate(desc, batch);
+    if (s != PG_OK)
+        return s;
+    if (batch->n_atoms > 0 && (!grad_out || !grad_xyz))
+        return PG_E_NULL;
+    if (batch->n_atoms == 0)
+        return PG_OK;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    Plan P;
+    P.a_cap = 0;
+    GridParams p;
+    fill_params(p, ctx, desc, batch, P, const_cast<void *>(grad_out), nullptr);
+    p.grad_xyz = grad_xyz;
+    hipError_t e = launch_adjoint(p, desc->out_dtype, (hipStream_t)stream);
+    return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+}
+
+int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, void *out, void *ws,
+                size_t ws_bytes, void *stream, int reps)
+{
+    if (!ctx)
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Plan base;
+    int s = make_plan(ctx, desc, batch, out, base);
+    if (s != PG_OK)
+        return s;
+    if (base.form != PG_FORM_WINDOW || batch->n_mol == 0)
+        return PG_OK;   // nothing tunable for this request
+    if (reps < 1)
+        reps = 1;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return PG_E_HIP;
+    const int blocks[] = {128, 256, 512};
+    const int nts[] = {1, 0};
+    Tuned best;
+    best.us = 1e30;
+    int rc = PG_OK;
+    for (int blk : blocks) {
+        Plan P = base;
+        P.block = blk;
+        const int occ = window_occupancy(desc->out_dtype, P.vec, blk, P.lds);
+        std::vector<int> pcs;
+        for (int v : {1, 2, 4, 8, 16})
+            if (v <= occ)
+                pcs.push_back(v);
+        if (std::find(pcs.begin(), pcs.end(), occ) == pcs.end())
+            pcs.push_back(occ);
+        for (int pc : pcs) {
+            for (int nt : nts) {
+                P.per_cu = pc;
+                P.nt = nt;
+                P.grid = std::max(1, std::min(batch->n_mol, ctx->n_cu * pc));
+                GridParams p;
+                fill_params(p, ctx, desc, batch, P, out, ws);
+                hipError_t e = hipSuccess;
+                for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                    e = launch_forward(ctx, desc, P, p, st);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    e = launch_forward(ctx, desc, P, p, st);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, st);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = hip_fail(ctx, e);
+                    break;
+                }
+                const double us = 1000.0 * ms / reps;
+                if (us < best.us) {
+                    best.us = us;
+                    best.block = blk;
+                    best.per_cu = pc;
+                    best.nt = nt;
+                }
+            }
+            if (rc != PG_OK)
+                break;
+        }
+        if (rc != PG_OK)
+            break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc == PG_OK && best.block > 0) {
+        ctx->tuning[tuning_key(desc, batch, base.vec)] = best;
+        drop_graphs(ctx);
+    }
+    return rc;
+}
+
+int pg_tuning_save(const pg_ctx *ctx, const char *path)
+{
+    if (!ctx || !path)
+        return PG_E_NULL;
+    std::ofstream f(path);
+    if (!f)
+        return PG_E_PARAM;
+    f << "{\"version\": 1, \"arch\": \"" << ctx->arch << "\", \"entries\": [";
+    bool first = true;
+    for (const auto &kv : ctx->tuning) {
+        f << (first ? "\n" : ",\n") << "  {\"key\": \"" << kv.first << "\", \"block\": "
+          << kv.second.block << ", \"per_cu\": " << kv.second.per_cu << ", \"nt\": "
+          << kv.second.nt << ", \"us\": " << kv.second.us << "}";
+        first = false;
+    }
+    f << "\n]}\n";
+    return f.good() ? PG_OK : PG_E_PARAM;
+}
+
+int pg_tuning_load(pg_ctx *ctx, const char *path)
+{
+    if (!ctx || !path)
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuning.clear();
+    drop_graphs(ctx);
+    std::ifstream f(path);
+    if (!f)
+        return PG_E_PARAM;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    if (txt.find("\"version\": 1") == std::string::npos)
+        return PG_E_PARAM;
+    std::map<std::string, Tuned> tab;
+    size_t pos = 0;
+    while ((pos = txt.find("{\"key\": \"", pos)) != std::string::npos) {
+        pos += 9;
+        const size_t q = txt.find('"', pos);
+        if (q == std::string::npos)
+            return PG_E_PARAM;
+        const std::string key = txt.substr(pos, q - pos);
+        Tuned t;
+        if (std::sscanf(txt.c_str() + q, "\", \"block\": %d, \"per_cu\": %d, \"nt\": %d, \"us\": %lf",
+                        &t.block, &t.per_cu, &t.nt, &t.us) != 4)
+            return PG_E_PARAM;
+        if (t.block < 64 || t.block > 1024 || t.block % 64 || t.per_cu < 1 || t.per_cu > 64 ||
+            t.nt < 0 || t.nt > 1)
+            return PG_E_PARAM;
+        tab[key] = t;
+        pos = q;
+    }
+    ctx->tuning = std::move(tab);
+    return PG_OK;
+}
+
+int pg_set_option(pg_ctx *ctx, int option, int64_t value)
+{
+    if (!ctx)
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    switch (option) {
+    case PG_OPT_GRAPH:
+        if (value != 0 && value != 1)
+            return PG_E_PARAM;
+        ctx->use_graph = (int)value;
+        if (!value)
+            drop_graphs(ctx);
+        return PG_OK;
+    case PG_OPT_BLOCK:
+        if (value != -1 && (value < 64 || value > 1024 || value % 64))
+            return PG_E_PARAM;
+        ctx->opt_block = (int)value;
+        break;
+    case PG_OPT_GRID_PER_CU:
+        if (value != -1 && (value < 1 || value > 64))
+            return PG_E_PARAM;
+        ctx->opt_per_cu = (int)value;
+        break;
+    case PG_OPT_NT_STORE:
+        if (value < -1 || value > 1)
+            return PG_E_PARAM;
+        ctx->opt_nt = (int)value;
+        break;
+    default:
+        return PG_E_PARAM;
+    }
+    drop_graphs(ctx);
+    return PG_OK;
+}
+
+int pg_get_device_error(pg_ctx *ctx, int32_t *code, int64_t *first_atom)
+{
+    if (!ctx || !code || !first_atom)
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    DeviceError h;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(&h, ctx->d_err, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    DeviceError z = {0u, 0u, ~0ull};
+    e = hipMemcpy(ctx->d_err, &z, sizeof z, hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    *code = PG_OK;
+    if (h.flags & (1u << PG_E_DEVICE_DATA))
+        *code = PG_E_DEVICE_DATA;
+    else if (h.flags & (1u << PG_E_CAPACITY))
+        *code = PG_E_CAPACITY;
+    *first_atom = h.flags ? (int64_t)h.first : -1;
+    return PG_OK;
+}
+
+int pg_last_hip_error(const pg_ctx *ctx) { return ctx ? ctx->last_hip : 0; }
+
+}  // extern "C"

@@ -1,0 +1,288 @@
+// pg_device.hpp -- device-side building blocks shared by the gfx950 kernels.
+//
+//  * exact cutoff-window bounds per atom and axis, from error-free FP32
+//    transforms (no FP64 on the GPU);
+//  * nearest-image ranges for orthorhombic periodic cells;
+//  * accurate per-axis offsets and 1-D Gaussian factors;
+//  * bf16 conversion and vector stores.
+//
+// The voxel value is the point-sampled Gaussian of §III-A Eq. 1 (without
+// its normalising prefactor), truncated per axis at rc_t = fl32(k sigma_t)
+// (the threshold truncation suggested in §VI-B).  Because the Gaussian and
+// the cube cutoff are both separable (§III-A; §IV-C relies on the same
+// property), one atom's grid is the outer product of three 1-D factors
+// phi_x(ix) phi_y(iy) phi_z(iz), which is what every kernel here evaluates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pg_params.hpp"
+
+namespace pg {
+
+// ---------------------------------------------------------------------------
+// Error-free transforms (Knuth TwoSum, FMA-based TwoProd).  The library is
+// compiled with -ffp-contract=off so these are evaluated as written.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(float a, float b, float &p, float &e)
+{
+    p = a * b;
+    e = __builtin_fmaf(a, b, -p);
+}
+
+// Sign (-1, 0, +1) of the exact real sum of N float terms.  Grow-expansion
+// (Shewchuk 1997): the running sum is kept as a non-overlapping expansion
+// of increasing magnitude, so the sign is that of its largest non-zero
+// component.
+template <int N>
+__device__ __forceinline__ int exact_sign(const float (&t)[N])
+{
+    float e[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        float q = t[k];
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+            float s, h;
+            two_sum(q, e[j], s, h);
+            e[j] = h;
+            q = s;
+        }
+        e[k] = q;
+    }
+    int sgn = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        sgn = (e[j] > 0.f) ? 1 : ((e[j] < 0.f) ? -1 : sgn);
+    return sgn;
+}
+
+// sign(o + (i + 1/2) h - mu - n L + r), exactly.
+__device__ __forceinline__ int side(float o, float h, int i, float mu, int n, float L, float r)
+{
+    float p, pe, q = 0.f, qe = 0.f;
+    two_prod((float)i + 0.5f, h, p, pe);
+    if (n != 0)
+        two_prod((float)n, L, q, qe);
+    const float t[7] = {o, p, pe, -mu, -q, -qe, r};
+    return exact_sign(t);
+}
+
+// Inside indices of one atom along one axis: up to MAX_IMAGES disjoint
+// ranges [lo, hi] (one per periodic image that reaches the grid), each with
+// the float-float base offset o - mu - n L.
+constexpr int MAX_IMAGES = 3;
+
+struct AxisRanges {
+    int n;
+    int lo[MAX_IMAGES], hi[MAX_IMAGES];
+    float bh[MAX_IMAGES], bl[MAX_IMAGES];
+};
+
+// Bounds for image n: smallest i with offset >= -rc, largest with
+// offset <= rc, clipped to [0, N).  The FP32 estimate is corrected with the
+// exact sign test; for coordinates within 2^20 voxels of the grid the
+// estimate is already within one index, so the correction loops run at
+// most a couple of times (they are bounded regardless).
+__device__ __forceinline__ void image_range(float o, float h, int N, float mu, int n, float L,
+                                            float rc, bool cut, int &lo_out, int &hi_out)
+{
+    if (!cut) {
+        lo_out = 0;
+        hi_out = N - 1;
+        return;
+    }
+    const float c = (n != 0) ? __builtin_fmaf((float)n, L, mu) : mu;
+    const float f = (c - o) / h - 0.5f;
+    const float r = rc / h;
+    const float lim_lo = -4.f, lim_hi = (float)N + 4.f;
+    float flo = fminf(fmaxf(ceilf(f - r), lim_lo), lim_hi);
+    float fhi = fminf(fmaxf(floorf(f + r), lim_lo), lim_hi);
+    int lo = (int)flo, hi = (int)fhi;
+    const int ilo = -4, ihi = N + 4;
+    for (int it = 0; it < 8 && lo > ilo && side(o, h, lo - 1, mu, n, L, rc) >= 0; ++it)
+        --lo;
+    for (int it = 0; it < 8 && lo < ihi && side(o, h, lo, mu, n, L, rc) < 0; ++it)
+        ++lo;
+    for (int it = 0; it < 8 && hi < ihi && side(o, h, hi + 1, mu, n, L, -rc) <= 0; ++it)
+        ++hi;
+    for (int it = 0; it < 8 && hi > ilo && side(o, h, hi, mu, n, L, -rc) > 0; ++it)
+        --hi;
+    lo_out = lo < 0 ? 0 : lo;
+    hi_out = hi > N - 1 ? N - 1 : hi;
+}
+
+__device__ __forceinline__ void base_offset(float o, float mu, int n, float L, float &bh, float &bl)
+{
+    float s1, e1;
+    two_sum(o, -mu, s1, e1);
+    if (n == 0) {
+        bh = s1;
+        bl = e1;
+        return;
+    }
+    float q, qe, s2, e2;
+    two_prod((float)n, L, q, qe);
+    two_sum(s1, -q, s2, e2);
+    bh = s2;
+    bl = (e1 + e2) - qe;
+}
+
+// All ranges of one atom on one axis.  Far-away coordinates give n = 0.
+__device__ __forceinline__ void axis_ranges(float o, float h, int N, float mu, bool periodic,
+                                            float L, float rc, bool cut, AxisRanges &R)
+{
+    R.n = 0;
+    // an atom more than 2^20 voxels away cannot reach the grid
+    const float span = 1048576.f * h;
+    if (!(fabsf(mu - o) < span))
+        return;
+    if (!periodic) {
+        int lo, hi;
+        image_range(o, h, N, mu, 0, L, rc, cut, lo, hi);
+        if (lo <= hi) {
+            R.lo[0] = lo;
+            R.hi[0] = hi;
+            base_offset(o, mu, 0, L, R.bh[0], R.bl[0]);
+            R.n = 1;
+        }
+        return;
+    }
+    // images n whose cutoff interval can reach the voxel centres of the grid
+    const float ext = (float)N * h;
+    const int n_min = (int)floorf((o - rc - mu) / L) - 1;
+    const int n_max = (int)ceilf((o + ext + rc - mu) / L) + 1;
+    for (int n = n_min; n <= n_max && R.n < MAX_IMAGES; ++n) {
+        int lo, hi;
+        image_range(o, h, N, mu, n, L, rc, cut, lo, hi);
+        if (lo <= hi) {
+            float bh, bl;
+            base_offset(o, mu, n, L, bh, bl);
+            // insert at slot R.n without dynamic register indexing
+#pragma unroll
+            for (int s = 0; s < MAX_IMAGES; ++s) {
+                if (s == R.n) {
+                    R.lo[s] = lo;
+                    R.hi[s] = hi;
+                    R.bh[s] = bh;
+                    R.bl[s] = bl;
+                }
+            }
+            R.n++;
+        }
+    }
+}
+
+// Offset r_i - mu (nearest image via the range's base), rounded once from
+// a float-float sum: |error| <= ulp(offset)/2 + 2^-48 |base|.
+__device__ __forceinline__ float offset_at(float bh, float bl, float h, int i)
+{
+    float p, pe;
+    two_prod((float)i + 0.5f, h, p, pe);
+    float s, e;
+    two_sum(bh, p, s, e);
+    return s + ((e + pe) + bl);
+}
+
+// exp(-d^2 / (2 sigma^2)) with inv2s2 = fl32(1 / (2 sigma^2)).
+__device__ __forceinline__ float gauss1d(float d, float inv2s2)
+{
+    return expf(-(d * d) * inv2s2);
+}
+
+// ---------------------------------------------------------------------------
+// Output conversion and vector stores
+// ---------------------------------------------------------------------------
+template <typename T> struct OutTraits;
+template <> struct OutTraits<float> {
+    static constexpr int bytes = 4;
+};
+template <> struct OutTraits<__bf16> {
+    static constexpr int bytes = 2;
+};
+
+// Store VEC accumulated values (float) to p as T (bf16: round to nearest
+// even via the gfx950 conversion instruction).
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec(T *p, const float (&v)[VEC], bool nt)
+{
+    constexpr int BYTES = VEC * OutTraits<T>::bytes;
+    uint32_t w[(BYTES + 3) / 4];
+    if constexpr (OutTraits<T>::bytes == 4) {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            w[k] = __builtin_bit_cast(uint32_t, v[k]);
+    } else {
+        if constexpr (VEC == 1) {
+            __bf16 b = (__bf16)v[0];
+            unsigned short s = __builtin_bit_cast(unsigned short, b);
+            if (nt)
+                __builtin_nontemporal_store(s, (unsigned short *)p);
+            else
+                *(unsigned short *)p = s;
+            return;
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC / 2; ++k) {
+                __bf16 lo = (__bf16)v[2 * k], hi = (__bf16)v[2 * k + 1];
+                w[k] = (uint32_t)__builtin_bit_cast(unsigned short, lo) |
+                       ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+            }
+        }
+    }
+    if constexpr (BYTES == 16) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        u4 x = {w[0], w[1], w[2], w[3]};
+        if (nt)
+            __builtin_nontemporal_store(x, (u4 *)p);
+        else
+            *(u4 *)p = x;
+    } else if constexpr (BYTES == 8) {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        u2 x = {w[0], w[1]};
+        if (nt)
+            __builtin_nontemporal_store(x, (u2 *)p);
+        else
+            *(u2 *)p = x;
+    } else if constexpr (BYTES == 4) {
+        if (nt)
+            __builtin_nontemporal_store(w[0], (uint32_t *)p);
+        else
+            *(uint32_t *)p = w[0];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ float load_as_float(const T *p);
+template <>
+__device__ __forceinline__ float load_as_float<float>(const float *p) { return *p; }
+template <>
+__device__ __forceinline__ float load_as_float<__bf16>(const __bf16 *p)
+{
+    unsigned short s = *(const unsigned short *)p;
+    return __builtin_bit_cast(float, (uint32_t)s << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Sticky device error word
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void raise_error(DeviceError *err, int code, long long index)
+{
+    atomicOr(&err->flags, 1u << code);
+    atomicMin(&err->first, (unsigned long long)index);
+}
+
+__device__ __forceinline__ bool atom_valid(float x, float y, float z, int t, int C)
+{
+    return t >= 0 && t < C && isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+}  // namespace pg

@@ -1,0 +1,32 @@
+// pg_launch.hpp -- host-side launchers of the gfx950 kernels (one per .hip
+// translation unit), called by the C-ABI runtime in pg_api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "pg_params.hpp"
+
+namespace pg {
+
+// Byte offsets of the window kernel's dynamic LDS regions.
+struct WindowLds {
+    size_t rows, ranges, masks, types, total;
+};
+
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words);
+
+// Persistent molecule window kernel (pg_window.hip).
+hipError_t launch_window(const GridParams &p, int out_dtype, int vec, int block, int grid,
+                         size_t lds, hipStream_t s);
+int window_occupancy(int out_dtype, int vec, int block, size_t lds);
+
+// Per-atom window table into the workspace (pg_plain.hip).
+hipError_t launch_prep(const GridParams &p, hipStream_t s);
+// One structure (p.mol_index), one thread per output element (pg_plain.hip).
+hipError_t launch_plain(const GridParams &p, int out_dtype, hipStream_t s);
+
+// Coordinate adjoint, one wave per atom (pg_adjoint.hip).
+hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s);
+
+}  // namespace pg

@@ -1,0 +1,134 @@
+// pg_plain.hip -- the baseline ("plain") form on gfx950.
+//
+// prep:  one thread per atom computes the atom's exact per-axis window
+//        ranges (and nearest-image bases) into the workspace.
+// plain: one launch per structure, one thread per output element; each
+//        thread visits every atom of its structure, tests the three axis
+//        windows and adds the 3-D Gaussian exp(-|r - mu|^2 / (2 sigma^2))
+//        (§III-A Eq. 1, point-sampled, without the prefactor).  This is the
+//        straightforward GPU transcription of the definition; the batched
+//        window kernel is measured against it.
+#include "pg_device.hpp"
+#include "pg_launch.hpp"
+
+namespace pg {
+
+__device__ __forceinline__ int structure_of(const int32_t *offsets, int n_mol, long long a)
+{
+    // last m with offsets[m] <= a (that structure is non-empty and holds a)
+    int lo = 0, hi = n_mol;   // invariant: offsets[lo] <= a < offsets[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)offsets[mid] <= a)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) prep_kernel(GridParams p)
+{
+    const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= p.n_atoms)
+        return;
+    AtomWindow *w = (AtomWindow *)p.ws + a;
+    const float mu[3] = {p.xyz[3 * a], p.xyz[3 * a + 1], p.xyz[3 * a + 2]};
+    const int t = p.types[a];
+    const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.C);
+    if (!ok)
+        raise_error(p.err, PG_E_DEVICE_DATA, a);
+    const int m = ok ? structure_of(p.offsets, p.n_mol, a) : 0;
+    w->type = ok ? t : -1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        AxisRanges R;
+        R.n = 0;
+        if (ok) {
+            const float o = p.origins ? p.origins[3 * m + q] : p.o[q];
+            const float h = p.spacings ? p.spacings[3 * m + q] : p.h[q];
+            const int N = q == 0 ? p.W : (q == 1 ? p.H : p.D);
+            axis_ranges(o, h, N, mu[q], p.periodic != 0, p.L[q], p.rc[t], p.cut != 0, R);
+        }
+        w->n[q] = R.n;
+#pragma unroll
+        for (int r = 0; r < MAX_IMAGES; ++r) {
+            const bool u = r < R.n;
+            w->lo[q][r] = u ? R.lo[r] : 0;
+            w->hi[q][r] = u ? R.hi[r] : -1;
+            w->bh[q][r] = u ? R.bh[r] : 0.f;
+            w->bl[q][r] = u ? R.bl[r] : 0.f;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) plain_kernel(GridParams p)
+{
+    const int m = p.mol_index;
+    const size_t plane = (size_t)p.H * p.W, vol = (size_t)p.D * plane;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)p.C * vol)
+        return;
+    const int c = (int)(e / vol);
+    const size_t r0 = e - (size_t)c * vol;
+    const int iz = (int)(r0 / plane);
+    const size_t r1 = r0 - (size_t)iz * plane;
+    const int iy = (int)(r1 / p.W);
+    const int ix = (int)(r1 - (size_t)iy * p.W);
+    const int idx[3] = {ix, iy, iz};
+    float h[3];
+    for (int q = 0; q < 3; ++q)
+        h[q] = p.spacings ? p.spacings[3 * m + q] : p.h[q];
+    const AtomWindow *tab = (const AtomWindow *)p.ws;
+    int a0 = p.offsets[m], a1 = p.offsets[m + 1];
+    if (a0 < 0 || a1 < a0 || (long long)a1 > p.n_atoms)
+        a0 = a1 = 0;   // malformed offsets: nothing is read
+    const float inv2s2 = p.inv2s2[c];
+    float acc = 0.f;
+    for (int a = a0; a < a1; ++a) {
+        if (tab[a].type != c)
+            continue;
+        float d2 = 0.f;
+        bool inside = true;
+        for (int q = 0; q < 3 && inside; ++q) {
+            bool hit = false;
+            for (int r = 0; r < tab[a].n[q]; ++r) {
+                if (idx[q] >= tab[a].lo[q][r] && idx[q] <= tab[a].hi[q][r]) {
+                    const float d = offset_at(tab[a].bh[q][r], tab[a].bl[q][r], h[q], idx[q]);
+                    d2 = __builtin_fmaf(d, d, d2);
+                    hit = true;
+                }
+            }
+            inside = hit;
+        }
+        if (inside)
+            acc += expf(-d2 * inv2s2);
+    }
+    const float v[1] = {acc};
+    store_vec<T, 1>((T *)p.out + (size_t)m * p.C * vol + e, v, false);
+}
+
+hipError_t launch_prep(const GridParams &p, hipStream_t s)
+{
+    if (p.n_atoms == 0)
+        return hipSuccess;
+    const int block = 256;
+    const long long grid = (p.n_atoms + block - 1) / block;
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(block), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const GridParams &p, int out_dtype, hipStream_t s)
+{
+    const size_t n = (size_t)p.C * p.D * p.H * p.W;
+    const int block = 256;
+    const size_t grid = (n + block - 1) / block;
+    if (out_dtype == PG_OUT_F32)
+        hipLaunchKernelGGL(plain_kernel<float>, dim3((unsigned)grid), dim3(block), 0, s, p);
+    else
+        hipLaunchKernelGGL(plain_kernel<__bf16>, dim3((unsigned)grid), dim3(block), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace pg

@@ -1,0 +1,159 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every function
+declared in include/particlegrid.h, and its host-side validation, workspace
+sizing and planning behave as documented.  No call here touches a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2211_08506_amd as pg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "particlegrid.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(pg.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in particlegrid.h but not exported"
+    assert set(names) == set(pg.EXPORTS)
+
+
+def test_abi_version_and_status_strings():
+    assert pg.abi_version() == 1
+    lib = pg._lib()
+    for s in range(0, 10):
+        assert lib.pg_status_str(s)
+    assert lib.pg_status_str(12345) == b"unknown status"
+
+
+def desc_ok(**kw):
+    d = pg.make_desc(kw.pop("C", 5), kw.pop("dims", (32, 32, 32)), kw.pop("spacing", 0.5),
+                     kw.pop("origin", (-8, -8, -8)), kw.pop("sigma", [0.4, 0.475, 0.55, 0.625, 0.7]),
+                     kw.pop("cutoff_k", 3.0), kw.pop("cell", None), kw.pop("out_dtype", "f32"),
+                     kw.pop("form", "auto"))
+    assert not kw
+    return d
+
+
+def batch_ok(n_mol=4, n_atoms=40, max_atoms=12, fake=0x1000):
+    b = pg.Batch()
+    b.xyz = fake
+    b.types = fake
+    b.offsets = fake
+    b.origins = None
+    b.spacings = None
+    b.n_mol = n_mol
+    b.n_atoms = n_atoms
+    b.max_atoms = max_atoms
+    return b
+
+
+def validate(d, b):
+    return pg._lib().pg_validate(ctypes.byref(d), ctypes.byref(b))
+
+
+def test_validate_accepts_good_request():
+    assert validate(desc_ok(), batch_ok()) == pg.PG_OK
+    assert validate(desc_ok(out_dtype="bf16"), batch_ok()) == pg.PG_OK
+    assert validate(desc_ok(cutoff_k=0.0), batch_ok()) == pg.PG_OK
+    assert validate(desc_ok(), batch_ok(n_mol=0, n_atoms=0, max_atoms=0)) == pg.PG_OK
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("C", 0, pg.PG_E_SHAPE), ("C", 65, pg.PG_E_SHAPE), ("D", 0, pg.PG_E_SHAPE),
+    ("W", -3, pg.PG_E_SHAPE), ("cutoff_k", -1.0, pg.PG_E_PARAM),
+    ("cutoff_k", float("nan"), pg.PG_E_PARAM), ("out_dtype", 7, pg.PG_E_PARAM),
+    ("form", 9, pg.PG_E_PARAM),
+])
+def test_validate_rejects_bad_desc(field, value, code):
+    d = desc_ok()
+    setattr(d, field, value)
+    assert validate(d, batch_ok()) == code
+
+
+def test_validate_rejects_bad_params():
+    d = desc_ok()
+    d.spacing[1] = 0.0
+    assert validate(d, batch_ok()) == pg.PG_E_PARAM
+    d = desc_ok()
+    d.sigma[3] = -0.1
+    assert validate(d, batch_ok()) == pg.PG_E_PARAM
+    d = desc_ok()
+    d.origin[0] = float("inf")
+    assert validate(d, batch_ok()) == pg.PG_E_PARAM
+
+
+def test_validate_batch_sizes_and_nulls():
+    d = desc_ok()
+    assert validate(d, batch_ok(n_mol=-1)) == pg.PG_E_SHAPE
+    assert validate(d, batch_ok(max_atoms=0)) == pg.PG_E_SHAPE      # atoms but no bound
+    assert validate(d, batch_ok(max_atoms=41)) == pg.PG_E_SHAPE     # bound above n_atoms
+    assert validate(d, batch_ok(n_mol=0)) == pg.PG_E_SHAPE          # atoms without structures
+    b = batch_ok()
+    b.offsets = None
+    assert validate(d, b) == pg.PG_E_NULL
+    b = batch_ok()
+    b.xyz = None
+    assert validate(d, b) == pg.PG_E_NULL
+    assert pg._lib().pg_validate(None, ctypes.byref(batch_ok())) == pg.PG_E_NULL
+
+
+def test_validate_periodic_constraints():
+    sig = [0.4 + 0.3 * i / 7 for i in range(8)]
+    ok = desc_ok(C=8, dims=(128, 128, 128), spacing=0.16, origin=(0, 0, 0), sigma=sig,
+                 cell=20.0)
+    assert validate(ok, batch_ok()) == pg.PG_OK
+    small = desc_ok(C=8, dims=(16, 16, 16), spacing=0.16, origin=(0, 0, 0), sigma=sig, cell=4.0)
+    assert validate(small, batch_ok()) == pg.PG_E_PERIODIC        # rc = 2.1 >= L/2
+    wide = desc_ok(C=8, dims=(300, 128, 128), spacing=0.16, origin=(0, 0, 0), sigma=sig,
+                   cell=20.0)
+    assert validate(wide, batch_ok()) == pg.PG_E_PERIODIC         # extent 48 > 2 L - 2 rc
+    nocut = desc_ok(C=8, dims=(128, 128, 128), spacing=0.16, origin=(0, 0, 0), sigma=sig,
+                    cell=20.0, cutoff_k=0.0)
+    assert validate(nocut, batch_ok()) == pg.PG_E_PERIODIC
+    b = batch_ok()
+    b.spacings = 0x2000
+    assert validate(ok, b) == pg.PG_E_UNSUPPORTED
+
+
+def test_workspace_and_plan_host_only():
+    lib = pg._lib()
+    n = ctypes.c_size_t(123)
+    d = desc_ok(form="window")
+    assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(batch_ok()), ctypes.byref(n)) == 0
+    assert n.value == 0
+    d = desc_ok(form="plain")
+    assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(batch_ok()), ctypes.byref(n)) == 0
+    assert n.value >= 40 * 100 and n.value % 256 == 0
+    info = pg.PlanInfo()
+    d = desc_ok(out_dtype="bf16")
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok()), 0x10000, ctypes.byref(info)) == 0
+    assert info.form == pg.FORMS["window"] and info.vec == 8 and info.atom_capacity == 16
+    # misaligned output pointer falls back to narrower stores
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok()), 0x10002, ctypes.byref(info)) == 0
+    assert info.vec == 1
+    # structures larger than the window kernel's LDS capacity need the large-structure path
+    d = desc_ok(form="window")
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok(n_atoms=4000, max_atoms=1000)),
+                       0x10000, ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = pg._lib()
+    d = desc_ok()
+    b = batch_ok()
+    assert lib.pg_grid_forward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, None, 0, None) == pg.PG_E_NULL
+    assert lib.pg_grid_backward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, 0x1000, None, 0, None) == pg.PG_E_NULL
+    assert lib.pg_set_option(None, 1, 1) == pg.PG_E_NULL
+    assert lib.pg_destroy(None) == pg.PG_E_NULL
+    assert lib.pg_create(None, 0) == pg.PG_E_NULL

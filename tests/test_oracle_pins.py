@@ -52,7 +52,10 @@ def test_P3_lattice_sum_poisson(sigma, h):
     sig = np.float32(sigma)
     xyz, t, off = one_atom(mu)
     g = oracle.grid_fp64(xyz, t, off, [sig], (n, n, n), h, o, cutoff_k=0.0)
-    expect = np.prod([poisson_axis_sum(mu[q], o[q], h, float(sig)) for q in range(3)])
+    # the geometry enters as float32 values (h = 0.35 is not exact)
+    h32 = float(np.float32(h))
+    o32 = [float(np.float32(v)) for v in o]
+    expect = np.prod([poisson_axis_sum(mu[q], o32[q], h32, float(sig)) for q in range(3)])
     assert abs(g.sum() / expect - 1.0) < 1e-12
 
 
@@ -150,9 +153,9 @@ def test_P5_cube_cutoff_mass_separable():
     computed here in 1-D with the cutoff applied per axis; and it is within
     edge discretisation of erf(3/sqrt 2)^3 (2 pi sigma^2)^{3/2} / h^3."""
     rng = np.random.default_rng(8)
-    h = 0.35
+    h = float(np.float32(0.35))             # geometry enters as float32 values
     n = 48
-    o = (-8.4, -8.4, -8.4)
+    o = (float(np.float32(-8.4)),) * 3
     sig = np.float32(0.55)
     s = float(sig)
     rc = float(np.float32(3.0) * sig)
