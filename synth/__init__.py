@@ -183,6 +183,25 @@ class Workload:
         return (n, self.n_types) + tuple(self.dims)
 
 
+def sample_voxel_indices(rng: np.random.Generator, batch: Batch, shape, origin, spacing,
+                         n_random: int, n_near: int) -> np.ndarray:
+    """Voxel sample rows (b, c, z, y, x) for spot checks of a batch of grids
+    of `shape` (B, C, D, H, W): n_random uniform voxels plus n_near voxels
+    within 3 voxels of randomly chosen atoms, in the atom's channel."""
+    B, C, D, H, W = shape
+    rnd = np.stack([rng.integers(0, s, n_random) for s in shape], axis=1)
+    if batch.n_atoms == 0 or n_near == 0:
+        return rnd.astype(np.int64)
+    a = rng.integers(0, batch.n_atoms, n_near)
+    b = np.searchsorted(batch.offsets, a, side="right") - 1
+    o = np.asarray(origin, dtype=np.float64)
+    idx = np.floor((batch.xyz[a].astype(np.float64) - o) / spacing).astype(np.int64)
+    idx += rng.integers(-3, 4, size=idx.shape)
+    near = np.stack([b, batch.types[a], np.clip(idx[:, 2], 0, D - 1),
+                     np.clip(idx[:, 1], 0, H - 1), np.clip(idx[:, 0], 0, W - 1)], axis=1)
+    return np.concatenate([rnd, near]).astype(np.int64)
+
+
 def _centered_origin(n: int, h: float) -> Tuple[float, float, float]:
     e = -0.5 * n * h
     return (e, e, e)

@@ -40,16 +40,4 @@ def worst_molecule(got: np.ndarray, ref: np.ndarray):
     return w
 
 
-def sample_voxels(rng, batch, shape, wl_origin, spacing, n_random, n_near):
-    """Sample (b, c, z, y, x) rows: uniform random voxels plus voxels next to
-    atoms (where values are non-zero)."""
-    B, C, D, H, W = shape
-    rnd = np.stack([rng.integers(0, s, n_random) for s in shape], axis=1)
-    a = rng.integers(0, batch.n_atoms, n_near)
-    b = np.searchsorted(batch.offsets, a, side="right") - 1
-    o = np.asarray(wl_origin)
-    idx = np.floor((batch.xyz[a].astype(np.float64) - o) / spacing).astype(np.int64)
-    idx += rng.integers(-3, 4, size=idx.shape)
-    near = np.stack([b, batch.types[a], np.clip(idx[:, 2], 0, D - 1),
-                     np.clip(idx[:, 1], 0, H - 1), np.clip(idx[:, 0], 0, W - 1)], axis=1)
-    return np.concatenate([rnd, near]).astype(np.int64)
+sample_voxels = synth.sample_voxel_indices
