@@ -91,6 +91,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain fp32 baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the shipped tuning table only (for profiler runs)")
+    ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
+    ap.add_argument("--save-tuning", default=None, help="write the tuning table to this path")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,11 +131,12 @@ def main():
                         wl.cell, out_dt, "window")
     out = pg.empty_grid(desc, B, dev)
 
-    log("[bench] autotuning the window kernel")
-    ctx.autotune(desc, bv, out, reps=3)
+    if not args.no_autotune:
+        log("[bench] autotuning the window kernel")
+        ctx.autotune(desc, bv, out, reps=3)
     plan = ctx.plan(desc, bv, out)
     log(f"[bench] plan {plan}")
-    ctx.set_option(pg.PG_OPT_GRAPH, 1)
+    ctx.set_option(pg.PG_OPT_GRAPH, 0 if args.no_graph else 1)
 
     def step():
         ctx.forward(desc, bv, out, stream)
@@ -169,7 +174,10 @@ def main():
     desc32 = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
                           torch.float32, "window")
     out32 = pg.empty_grid(desc32, B, dev)
-    ctx.autotune(desc32, bv, out32, reps=3)
+    if not args.no_autotune:
+        ctx.autotune(desc32, bv, out32, reps=3)
+    if args.save_tuning:
+        ctx.tuning_save(args.save_tuning)
     w32, e32, _ = timed_steps(lambda: ctx.forward(desc32, bv, out32, stream),
                               max(5, args.steps // 5), 2, torch, stream)
     extra["batched_fp32"] = {"grids_per_s": B / (w32 / 1e3), "ms_per_step": w32,
@@ -225,7 +233,8 @@ def main():
         "config": {"workload": f"{wl.name}: {B} molecules of {wl.atoms[0]}-{wl.atoms[1]} atoms "
                                f"(H/C/N/O/F p=0.5/0.3/0.1/0.08/0.02, {wl.box:g} A box), "
                                f"{C}x{D}x{H}x{W} grid at {wl.spacing} A, cutoff {wl.cutoff_k:g} "
-                               f"sigma, {wl.out_dtype} out, window form, HIP graph",
+                               f"sigma, {wl.out_dtype} out, window form, "
+                               f"{'direct launch' if args.no_graph else 'HIP graph'}",
                    "batch": B, "grid": [C, D, H, W], "n_atoms": int(b.n_atoms),
                    "plan": plan},
         "hbm_gbs": achieved,

@@ -26,6 +26,8 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libparticlegrid.so")
+# launch shapes measured by pg_autotune on an MI355X, loaded by every Context
+SHIPPED_TUNING = os.path.join(_HERE, "tuning_gfx950.json")
 
 PG_OK = 0
 PG_E_NULL, PG_E_SHAPE, PG_E_PARAM, PG_E_PERIODIC = 1, 2, 3, 4
@@ -33,7 +35,8 @@ PG_E_WORKSPACE, PG_E_UNSUPPORTED, PG_E_HIP, PG_E_DEVICE_DATA, PG_E_CAPACITY = 5,
 PG_OUT_F32, PG_OUT_BF16 = 0, 1
 FORMS = {"auto": 0, "plain": 1, "window": 2, "mfma": 3}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
-PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE = 1, 2, 3, 4
+(PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL, PG_OPT_GROUP,
+ PG_OPT_PREP_WAVES) = 1, 2, 3, 4, 5, 6, 7
 MAX_CHANNELS = 64
 
 
@@ -63,7 +66,7 @@ class Batch(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("form", "block", "grid", "lds_bytes", "vec", "nt_store", "atom_capacity",
-                 "reserved")]
+                 "unroll", "group", "prep_waves")]
 
 
 _LIB = None
@@ -200,7 +203,8 @@ class Context:
     """A library context on one device (error word, tuning table, graph
     cache) plus a cached torch workspace buffer."""
 
-    def __init__(self, device: Union[int, torch.device, None] = None):
+    def __init__(self, device: Union[int, torch.device, None] = None,
+                 tuning: Optional[str] = "shipped"):
         if device is None:
             device = torch.cuda.current_device()
         if isinstance(device, torch.device):
@@ -210,6 +214,10 @@ class Context:
         _check(_lib().pg_create(ctypes.byref(h), self.device), "pg_create")
         self.handle = h
         self._ws = None
+        if tuning == "shipped":
+            tuning = SHIPPED_TUNING if os.path.exists(SHIPPED_TUNING) else None
+        if tuning:
+            self.tuning_load(tuning)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -241,7 +249,7 @@ class Context:
         info = PlanInfo()
         _check(_lib().pg_plan(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
                               _ptr(out), ctypes.byref(info)), "pg_plan")
-        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_ if n != "reserved"}
+        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_}
         d["form"] = FORM_NAMES.get(d["form"], d["form"])
         return d
 

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <list>
@@ -32,7 +33,7 @@ constexpr int kWindowMaxAtoms = 256;   // 4 x 64-bit plane masks
 constexpr int kGraphCacheSize = 32;
 
 struct Tuned {
-    int block = 0, per_cu = 0, nt = -1;
+    int block = 0, per_cu = 0, nt = -1, unroll = 0, group = 1, prep = 1;
     double us = 0.0;
 };
 
@@ -53,7 +54,8 @@ struct pg_ctx {
     int last_hip = 0;
     // options
     int use_graph = 0;
-    int opt_block = -1, opt_per_cu = -1, opt_nt = -1;
+    int opt_block = -1, opt_per_cu = -1, opt_nt = -1, opt_unroll = -1, opt_group = -1,
+        opt_prep = -1;
     std::map<std::string, Tuned> tuning;
     std::list<GraphEntry> graphs;   // most recent first
     std::mutex mu;
@@ -155,7 +157,7 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
 
 struct Plan {
     int form = PG_FORM_WINDOW;
-    int block = 256, grid = 1, per_cu = 1, vec = 1, nt = 1;
+    int block = 256, grid = 1, per_cu = 1, vec = 1, nt = 1, unroll = 1, group = 1, prep = 1;
     int a_cap = 8, row_stride = 4, mask_words = 1;
     size_t lds = 0;
     size_t ws = 0;
@@ -186,6 +188,32 @@ int pick_vec(const pg_grid_desc *d, const void *out)
     return 1;
 }
 
+// Structures staged per prep pass: as asked, reduced until the LDS fits.
+void set_group(const pg_ctx *ctx, const pg_grid_desc *d, Plan &P, int group)
+{
+    const int max_lds = ctx ? ctx->max_lds : 65536;
+    int g = std::max(1, group);
+    while (g > 1 && window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words, g).total >
+                        (size_t)max_lds)
+        g >>= 1;
+    P.group = g;
+    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words, g).total;
+}
+
+int window_grid(const pg_batch *b, const Plan &P, int n_cu)
+{
+    const int items = (b->n_mol + P.group - 1) / P.group;
+    return std::max(1, std::min(items, n_cu * P.per_cu));
+}
+
+// Runs per lane per pass: enough to cover a plane in one pass when it is
+// small, at most 4.
+int default_unroll(const pg_grid_desc *d, int vec)
+{
+    const long runs = ((long)d->H * d->W / vec + 63) / 64;
+    return runs >= 4 ? 4 : (runs >= 2 ? 2 : 1);
+}
+
 bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Plan &P)
 {
     if (b->max_atoms > kWindowMaxAtoms)
@@ -194,7 +222,8 @@ bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Pl
     const int W4 = (d->W + 3) & ~3;
     P.row_stride = (W4 + d->H + d->D + 3) & ~3;
     P.mask_words = (P.a_cap + 63) / 64;
-    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words).total;
+    P.group = 1;
+    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words, 1).total;
     const int max_lds = ctx ? ctx->max_lds : 65536;
     return P.lds <= (size_t)max_lds;
 }
@@ -225,13 +254,24 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
     P.block = 256;
     P.nt = 1;
     P.per_cu = 0;
+    P.unroll = default_unroll(d, P.vec);
     if (ctx) {
         auto it = ctx->tuning.find(tuning_key(d, b, P.vec));
         if (it != ctx->tuning.end()) {
             P.block = it->second.block;
             P.per_cu = it->second.per_cu;
             P.nt = it->second.nt;
+            P.unroll = it->second.unroll;
+            P.group = it->second.group;
+            P.prep = it->second.prep;
         }
+        if (ctx->opt_prep > 0)
+            P.prep = ctx->opt_prep;
+        if (ctx->opt_group > 0)
+            P.group = ctx->opt_group;
+        set_group(ctx, d, P, P.group);
+        if (ctx->opt_unroll > 0)
+            P.unroll = ctx->opt_unroll;
         if (ctx->opt_block > 0)
             P.block = ctx->opt_block;
         if (ctx->opt_per_cu > 0)
@@ -240,9 +280,11 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
             P.nt = ctx->opt_nt;
     }
     if (P.per_cu <= 0)
-        P.per_cu = ctx ? window_occupancy(d->out_dtype, P.vec, P.block, P.lds) : 4;
+        P.per_cu = ctx ? window_occupancy(d->out_dtype, P.vec, P.unroll, P.block, P.lds) : 4;
+    P.block = std::max(P.block, 128);
+    P.prep = std::max(1, std::min(P.prep, P.block / 64 - 1));
     const int n_cu = ctx ? ctx->n_cu : 256;
-    P.grid = std::max(1, std::min(b->n_mol, n_cu * P.per_cu));
+    P.grid = window_grid(b, P, n_cu);
     return PG_OK;
 }
 
@@ -270,6 +312,8 @@ void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const 
     p.row_stride = P.row_stride;
     p.mask_words = P.mask_words;
     p.nt_store = P.nt;
+    p.group = P.group;
+    p.prep_waves = P.prep;
     for (int q = 0; q < 3; ++q) {
         p.o[q] = d->origin[q];
         p.h[q] = d->spacing[q];
@@ -300,7 +344,7 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         }
         return hipSuccess;
     }
-    return launch_window(p, d->out_dtype, P.vec, P.block, P.grid, P.lds, s);
+    return launch_window(p, d->out_dtype, P.vec, P.unroll, P.block, P.grid, P.lds, s);
 }
 
 std::string graph_key(const pg_grid_desc *d, const pg_batch *b, const Plan &P, const void *out,
@@ -479,7 +523,9 @@ int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, 
     info->vec = P.vec;
     info->nt_store = P.nt;
     info->atom_capacity = P.a_cap;
-    info->reserved = 0;
+    info->unroll = P.form == PG_FORM_WINDOW ? P.unroll : 0;
+    info->group = P.form == PG_FORM_WINDOW ? P.group : 0;
+    info->prep_waves = P.form == PG_FORM_WINDOW ? P.prep : 0;
     return PG_OK;
 }
 
@@ -541,7 +587,9 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return PG_E_HIP;
-    const int blocks[] = {128, 256, 512};
+    const char *venv = std::getenv("PG_AUTOTUNE_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
+    const int blocks[] = {256, 512, 1024};
     const int nts[] = {1, 0};
     Tuned best;
     best.us = 1e30;
@@ -549,18 +597,38 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
     for (int blk : blocks) {
         Plan P = base;
         P.block = blk;
-        const int occ = window_occupancy(desc->out_dtype, P.vec, blk, P.lds);
+        // resident workgroups per CU from 1 up to one workgroup per structure
+        // (a grid larger than what stays resident is scheduled by the
+        // hardware as workgroups retire, overlapping one structure's prep
+        // phase with another's stores)
         std::vector<int> pcs;
-        for (int v : {1, 2, 4, 8, 16})
-            if (v <= occ)
-                pcs.push_back(v);
-        if (std::find(pcs.begin(), pcs.end(), occ) == pcs.end())
-            pcs.push_back(occ);
+        const int per_cu_all = (batch->n_mol + ctx->n_cu - 1) / ctx->n_cu;
+        for (int v = 1; v <= 64; v *= 2) {
+            if (v >= per_cu_all) {
+                pcs.push_back(std::max(1, per_cu_all));
+                break;
+            }
+            pcs.push_back(v);
+        }
         for (int pc : pcs) {
-            for (int nt : nts) {
+            for (int nt : nts)
+            for (int un : {1, 2})
+            for (int gr : {1, 2, 4})
+            for (int pw : {1, 2}) {
+                set_group(ctx, desc, P, gr);
+                if (P.group != gr)
+                    continue;
+                P.prep = pw;
                 P.per_cu = pc;
                 P.nt = nt;
-                P.grid = std::max(1, std::min(batch->n_mol, ctx->n_cu * pc));
+                P.unroll = un;
+                P.grid = window_grid(batch, P, ctx->n_cu);
+                if (pc > 1) {
+                    Plan Q = P;
+                    Q.per_cu = pc / 2;
+                    if (window_grid(batch, Q, ctx->n_cu) == P.grid)
+                        continue;   // same launch as a smaller per_cu
+                }
                 GridParams p;
                 fill_params(p, ctx, desc, batch, P, out, ws);
                 hipError_t e = hipSuccess;
@@ -582,11 +650,20 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
                     break;
                 }
                 const double us = 1000.0 * ms / reps;
+                if (verbose)
+                    std::fprintf(stderr,
+                                 "pg_autotune %s block %d per_cu %d grid %d nt %d unroll %d group %d "
+                                 "prep %d: %.2f us\n",
+                                 tuning_key(desc, batch, base.vec).c_str(), blk, pc, P.grid, nt, un,
+                                 gr, pw, us);
                 if (us < best.us) {
                     best.us = us;
                     best.block = blk;
                     best.per_cu = pc;
                     best.nt = nt;
+                    best.unroll = un;
+                    best.group = gr;
+                    best.prep = pw;
                 }
             }
             if (rc != PG_OK)
@@ -616,7 +693,9 @@ int pg_tuning_save(const pg_ctx *ctx, const char *path)
     for (const auto &kv : ctx->tuning) {
         f << (first ? "\n" : ",\n") << "  {\"key\": \"" << kv.first << "\", \"block\": "
           << kv.second.block << ", \"per_cu\": " << kv.second.per_cu << ", \"nt\": "
-          << kv.second.nt << ", \"us\": " << kv.second.us << "}";
+          << kv.second.nt << ", \"unroll\": " << kv.second.unroll << ", \"group\": "
+          << kv.second.group << ", \"prep\": " << kv.second.prep << ", \"us\": " << kv.second.us
+          << "}";
         first = false;
     }
     f << "\n]}\n";
@@ -647,11 +726,14 @@ int pg_tuning_load(pg_ctx *ctx, const char *path)
             return PG_E_PARAM;
         const std::string key = txt.substr(pos, q - pos);
         Tuned t;
-        if (std::sscanf(txt.c_str() + q, "\", \"block\": %d, \"per_cu\": %d, \"nt\": %d, \"us\": %lf",
-                        &t.block, &t.per_cu, &t.nt, &t.us) != 4)
+        if (std::sscanf(txt.c_str() + q,
+                        "\", \"block\": %d, \"per_cu\": %d, \"nt\": %d, \"unroll\": %d, "
+                        "\"group\": %d, \"prep\": %d, \"us\": %lf",
+                        &t.block, &t.per_cu, &t.nt, &t.unroll, &t.group, &t.prep, &t.us) != 7)
             return PG_E_PARAM;
         if (t.block < 64 || t.block > 1024 || t.block % 64 || t.per_cu < 1 || t.per_cu > 64 ||
-            t.nt < 0 || t.nt > 1)
+            t.nt < 0 || t.nt > 1 || (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) ||
+            t.group < 1 || t.group > 64 || t.prep < 1 || t.prep > 15)
             return PG_E_PARAM;
         tab[key] = t;
         pos = q;
@@ -687,6 +769,21 @@ int pg_set_option(pg_ctx *ctx, int option, int64_t value)
         if (value < -1 || value > 1)
             return PG_E_PARAM;
         ctx->opt_nt = (int)value;
+        break;
+    case PG_OPT_GROUP:
+        if (value != -1 && (value < 1 || value > 64))
+            return PG_E_PARAM;
+        ctx->opt_group = (int)value;
+        break;
+    case PG_OPT_PREP_WAVES:
+        if (value != -1 && (value < 1 || value > 15))
+            return PG_E_PARAM;
+        ctx->opt_prep = (int)value;
+        break;
+    case PG_OPT_UNROLL:
+        if (value != -1 && value != 1 && value != 2 && value != 4)
+            return PG_E_PARAM;
+        ctx->opt_unroll = (int)value;
         break;
     default:
         return PG_E_PARAM;

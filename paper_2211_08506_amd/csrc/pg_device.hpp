@@ -65,14 +65,25 @@ __device__ __forceinline__ int exact_sign(const float (&t)[N])
     return sgn;
 }
 
-// sign(o + (i + 1/2) h - mu - n L + r), exactly.
+// sign(o + (i + 1/2) h - mu - n L + r), exactly.  A plain FP32 evaluation
+// decides when it is far from zero: with M the sum of the terms' magnitudes,
+// the five roundings below move the result by at most 5 * 2^-24 * M (plus
+// the same again for the rounding of M itself), so |s| > 2^-20 M fixes the
+// sign.  Otherwise the exact expansion decides.
 __device__ __forceinline__ int side(float o, float h, int i, float mu, int n, float L, float r)
 {
-    float p, pe, q = 0.f, qe = 0.f;
-    two_prod((float)i + 0.5f, h, p, pe);
+    const float fi = (float)i + 0.5f;
+    const float p = fi * h;
+    const float q = (float)n * L;
+    const float s = (((o - mu) + p) - q) + r;
+    const float M = (((fabsf(o) + fabsf(mu)) + fabsf(p)) + fabsf(q)) + fabsf(r);
+    if (fabsf(s) > M * 0x1p-20f)
+        return s > 0.f ? 1 : -1;
+    float pp, pe, qq = 0.f, qe = 0.f;
+    two_prod(fi, h, pp, pe);
     if (n != 0)
-        two_prod((float)n, L, q, qe);
-    const float t[7] = {o, p, pe, -mu, -q, -qe, r};
+        two_prod((float)n, L, qq, qe);
+    const float t[7] = {o, pp, pe, -mu, -qq, -qe, r};
     return exact_sign(t);
 }
 

@@ -224,18 +224,20 @@ def test_capacity_overflow_reports_and_zeroes(pg, dev):
     xyz = rng.uniform(-3, 3, size=(off[-1], 3)).astype(np.float32)
     b = synth.Batch(xyz, rng.integers(0, 5, off[-1]).astype(np.int32), off)
     wl = synth.WORKLOADS["mol256"]
-    ctx = pg.Context(0)
-    g = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, form="window", ctx=ctx,
-            max_atoms=8)                       # capacity rounds to 8 atoms
-    code, first = ctx.device_error()
-    assert code == pg.PG_E_CAPACITY and first == 1
     ref = ref_grid(b, wl.sigma(), wl.dims, wl.spacing, wl.origin)
-    for m in range(4):
-        if counts[m] > 8:
-            assert not g[m].any()
-        else:
-            rel, _ = errors(g[m].double().cpu().numpy(), ref[m])
-            assert rel <= F32_TOL
+    for group in (1, 4):
+        ctx = pg.Context(0)
+        ctx.set_option(pg.PG_OPT_GROUP, group)
+        g = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, form="window", ctx=ctx,
+                max_atoms=8)                   # capacity rounds to 8 atoms
+        code, first = ctx.device_error()
+        assert code == pg.PG_E_CAPACITY and first == 1
+        for m in range(4):
+            if counts[m] > 8:
+                assert not g[m].any()
+            else:
+                rel, _ = errors(g[m].double().cpu().numpy(), ref[m])
+                assert rel <= F32_TOL
 
 
 def test_determinism_across_launch_shapes(pg, dev):
@@ -248,12 +250,15 @@ def test_determinism_across_launch_shapes(pg, dev):
     base = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, torch.bfloat16, ctx=ctx)
     again = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, torch.bfloat16, ctx=ctx)
     assert torch.equal(base, again)
-    for blk, pc, nt in ((64, 1, 0), (512, 2, 1), (1024, 1, 1), (128, 8, 0)):
+    for blk, pc, nt, un, gr in ((64, 1, 0, 1, 1), (512, 2, 1, 2, 4), (1024, 1, 1, 4, 8),
+                                (128, 8, 0, 2, 3), (256, 1, 1, 1, 64)):
         ctx.set_option(pg.PG_OPT_BLOCK, blk)
         ctx.set_option(pg.PG_OPT_GRID_PER_CU, pc)
         ctx.set_option(pg.PG_OPT_NT_STORE, nt)
+        ctx.set_option(pg.PG_OPT_UNROLL, un)
+        ctx.set_option(pg.PG_OPT_GROUP, gr)
         g = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, torch.bfloat16, ctx=ctx)
-        assert torch.equal(base, g), (blk, pc, nt)
+        assert torch.equal(base, g), (blk, pc, nt, un, gr)
 
 
 def test_permutation_invariance(pg, dev):
