@@ -95,6 +95,7 @@ def main():
                     help="use the shipped tuning table only (for profiler runs)")
     ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
     ap.add_argument("--save-tuning", default=None, help="write the tuning table to this path")
+    ap.add_argument("--tuning", default=None, help="load this tuning table (instead of the shipped one)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -124,7 +125,7 @@ def main():
     D, H, W = wl.dims
     vox = C * D * H * W
 
-    ctx = pg.Context(0)
+    ctx = pg.Context(0, tuning=args.tuning or "shipped")
     out_dt = torch.bfloat16 if wl.out_dtype == "bf16" else torch.float32
     esize = 2 if out_dt == torch.bfloat16 else 4
     desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k,

@@ -170,17 +170,15 @@ int pg_tuning_save(const pg_ctx *ctx, const char *path);
 int pg_tuning_load(pg_ctx *ctx, const char *path);
 
 /* Options: PG_OPT_GRAPH (0/1, default 0) -- replay captured HIP graphs for
-   repeated identical forward calls; PG_OPT_BLOCK, PG_OPT_GRID_PER_CU,
-   PG_OPT_NT_STORE, PG_OPT_UNROLL, PG_OPT_GROUP, PG_OPT_PREP_WAVES --
-   override the window kernel's workgroup size (>= 128), workgroups per CU,
-   non-temporal stores, output runs per lane per pass (1, 2 or 4),
-   structures per work item (1..64, reduced until the LDS fits) and waves
-   of the workgroup that prepare the next item while the others store
-   (1..15, fewer than the workgroup's waves) (-1 = tuned/default).
-   Changing an option drops the captured graphs.
-   Errors: PG_E_NULL, PG_E_PARAM. */
+   repeated identical forward calls.  PG_OPT_BLOCK, PG_OPT_GRID_PER_CU,
+   PG_OPT_UNROLL, PG_OPT_NT_STORE -- override the window form's workgroup
+   size (64..1024, a multiple of 64), persistent workgroups per CU (1..64),
+   16-byte output runs per lane per pass (1, 2 or 4) and non-temporal
+   stores (0/1); -1 restores the tuned/default choice.  Changing an option
+   drops the captured graphs.
+   Errors: PG_E_NULL, PG_E_PARAM (unknown option or value). */
 enum { PG_OPT_GRAPH = 1, PG_OPT_BLOCK = 2, PG_OPT_GRID_PER_CU = 3, PG_OPT_NT_STORE = 4,
-       PG_OPT_UNROLL = 5, PG_OPT_GROUP = 6, PG_OPT_PREP_WAVES = 7 };
+       PG_OPT_UNROLL = 5 };
 int pg_set_option(pg_ctx *ctx, int option, int64_t value);
 
 /* Read and clear the sticky device error word (synchronises the context's
@@ -193,12 +191,13 @@ int pg_get_device_error(pg_ctx *ctx, int32_t *code, int64_t *first_atom);
 int pg_last_hip_error(const pg_ctx *ctx);
 
 /* Describe the kernel configuration pg_grid_forward would use for this
-   request: form, workgroup size, workgroups launched, LDS bytes, vector
-   width, non-temporal stores, atom capacity per structure and runs per
-   lane per pass (window form).  Host only.  Errors: validation codes. */
+   request: form, workgroup size, workgroups launched (per launch; the
+   plain form launches one per structure), dynamic LDS bytes, output vector
+   width, non-temporal stores, atom capacity per structure, runs per lane
+   per pass and persistent workgroups per CU (window form).  Host only.
+   Errors: validation codes. */
 typedef struct pg_plan_info {
-    int32_t form, block, grid, lds_bytes, vec, nt_store, atom_capacity, unroll, group,
-        prep_waves;
+    int32_t form, block, grid, lds_bytes, vec, nt_store, atom_capacity, unroll, per_cu, reserved;
 } pg_plan_info;
 int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
             const void *out, pg_plan_info *info);

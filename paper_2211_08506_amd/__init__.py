@@ -35,8 +35,7 @@ PG_E_WORKSPACE, PG_E_UNSUPPORTED, PG_E_HIP, PG_E_DEVICE_DATA, PG_E_CAPACITY = 5,
 PG_OUT_F32, PG_OUT_BF16 = 0, 1
 FORMS = {"auto": 0, "plain": 1, "window": 2, "mfma": 3}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
-(PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL, PG_OPT_GROUP,
- PG_OPT_PREP_WAVES) = 1, 2, 3, 4, 5, 6, 7
+PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL = 1, 2, 3, 4, 5
 MAX_CHANNELS = 64
 
 
@@ -66,7 +65,7 @@ class Batch(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("form", "block", "grid", "lds_bytes", "vec", "nt_store", "atom_capacity",
-                 "unroll", "group", "prep_waves")]
+                 "unroll", "per_cu", "reserved")]
 
 
 _LIB = None
@@ -249,7 +248,7 @@ class Context:
         info = PlanInfo()
         _check(_lib().pg_plan(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
                               _ptr(out), ctypes.byref(info)), "pg_plan")
-        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_}
+        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_ if n != "reserved"}
         d["form"] = FORM_NAMES.get(d["form"], d["form"])
         return d
 

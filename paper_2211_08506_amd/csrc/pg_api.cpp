@@ -33,7 +33,7 @@ constexpr int kWindowMaxAtoms = 256;   // 4 x 64-bit plane masks
 constexpr int kGraphCacheSize = 32;
 
 struct Tuned {
-    int block = 0, per_cu = 0, nt = -1, unroll = 0, group = 1, prep = 1;
+    int block = 0, per_cu = 0, nt = -1, unroll = 0;
     double us = 0.0;
 };
 
@@ -54,8 +54,7 @@ struct pg_ctx {
     int last_hip = 0;
     // options
     int use_graph = 0;
-    int opt_block = -1, opt_per_cu = -1, opt_nt = -1, opt_unroll = -1, opt_group = -1,
-        opt_prep = -1;
+    int opt_block = -1, opt_per_cu = -1, opt_nt = -1, opt_unroll = -1;
     std::map<std::string, Tuned> tuning;
     std::list<GraphEntry> graphs;   // most recent first
     std::mutex mu;
@@ -157,10 +156,10 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
 
 struct Plan {
     int form = PG_FORM_WINDOW;
-    int block = 256, grid = 1, per_cu = 1, vec = 1, nt = 1, unroll = 1, group = 1, prep = 1;
+    int block = 256, grid = 1, per_cu = 0, vec = 1, nt = 1, unroll = 1;
     int a_cap = 8, row_stride = 4, mask_words = 1;
-    size_t lds = 0;
-    size_t ws = 0;
+    size_t lds = 0;           // dynamic LDS bytes of one workgroup
+    size_t ws = 0;            // workspace bytes
 };
 
 std::string tuning_key(const pg_grid_desc *d, const pg_batch *b, int vec)
@@ -188,30 +187,17 @@ int pick_vec(const pg_grid_desc *d, const void *out)
     return 1;
 }
 
-// Structures staged per prep pass: as asked, reduced until the LDS fits.
-void set_group(const pg_ctx *ctx, const pg_grid_desc *d, Plan &P, int group)
-{
-    const int max_lds = ctx ? ctx->max_lds : 65536;
-    int g = std::max(1, group);
-    while (g > 1 && window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words, g).total >
-                        (size_t)max_lds)
-        g >>= 1;
-    P.group = g;
-    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words, g).total;
-}
-
-int window_grid(const pg_batch *b, const Plan &P, int n_cu)
-{
-    const int items = (b->n_mol + P.group - 1) / P.group;
-    return std::max(1, std::min(items, n_cu * P.per_cu));
-}
-
 // Runs per lane per pass: enough to cover a plane in one pass when it is
 // small, at most 4.
 int default_unroll(const pg_grid_desc *d, int vec)
 {
     const long runs = ((long)d->H * d->W / vec + 63) / 64;
     return runs >= 4 ? 4 : (runs >= 2 ? 2 : 1);
+}
+
+int window_grid(const pg_batch *b, const Plan &P, int n_cu)
+{
+    return std::max(1, std::min(b->n_mol, n_cu * P.per_cu));
 }
 
 bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Plan &P)
@@ -222,8 +208,8 @@ bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Pl
     const int W4 = (d->W + 3) & ~3;
     P.row_stride = (W4 + d->H + d->D + 3) & ~3;
     P.mask_words = (P.a_cap + 63) / 64;
-    P.group = 1;
-    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words, 1).total;
+    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words).total;
+    P.ws = 0;
     const int max_lds = ctx ? ctx->max_lds : 65536;
     return P.lds <= (size_t)max_lds;
 }
@@ -247,13 +233,13 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
         P.ws = (size_t)b->n_atoms * sizeof(AtomWindow);
         P.ws = (P.ws + 255) & ~(size_t)255;
         P.block = 256;
+        P.lds = 0;
         return PG_OK;
     }
-    // window form: launch shape from options > tuning table > occupancy
-    P.ws = 0;
-    P.block = 256;
-    P.nt = 1;
-    P.per_cu = 0;
+    // window form: launch shape from options > tuning table > default
+    P.block = 512;
+    P.per_cu = 2;
+    P.nt = 0;
     P.unroll = default_unroll(d, P.vec);
     if (ctx) {
         auto it = ctx->tuning.find(tuning_key(d, b, P.vec));
@@ -262,14 +248,7 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
             P.per_cu = it->second.per_cu;
             P.nt = it->second.nt;
             P.unroll = it->second.unroll;
-            P.group = it->second.group;
-            P.prep = it->second.prep;
         }
-        if (ctx->opt_prep > 0)
-            P.prep = ctx->opt_prep;
-        if (ctx->opt_group > 0)
-            P.group = ctx->opt_group;
-        set_group(ctx, d, P, P.group);
         if (ctx->opt_unroll > 0)
             P.unroll = ctx->opt_unroll;
         if (ctx->opt_block > 0)
@@ -279,10 +258,6 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
         if (ctx->opt_nt >= 0)
             P.nt = ctx->opt_nt;
     }
-    if (P.per_cu <= 0)
-        P.per_cu = ctx ? window_occupancy(d->out_dtype, P.vec, P.unroll, P.block, P.lds) : 4;
-    P.block = std::max(P.block, 128);
-    P.prep = std::max(1, std::min(P.prep, P.block / 64 - 1));
     const int n_cu = ctx ? ctx->n_cu : 256;
     P.grid = window_grid(b, P, n_cu);
     return PG_OK;
@@ -309,11 +284,9 @@ void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const 
     p.periodic = d->periodic;
     p.cut = d->cutoff_k != 0.f;
     p.a_cap = P.a_cap;
+    p.nt_store = P.nt;
     p.row_stride = P.row_stride;
     p.mask_words = P.mask_words;
-    p.nt_store = P.nt;
-    p.group = P.group;
-    p.prep_waves = P.prep;
     for (int q = 0; q < 3; ++q) {
         p.o[q] = d->origin[q];
         p.h[q] = d->spacing[q];
@@ -367,6 +340,7 @@ int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *ou
         return PG_E_NULL;
     if (ws_bytes < P.ws || (P.ws > 0 && !ws))
         return PG_E_WORKSPACE;
+
     GridParams p;
     fill_params(p, ctx, d, b, P, out, ws);
     if (!ctx->use_graph || b->n_mol == 0) {
@@ -520,12 +494,12 @@ int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, 
     info->block = P.block;
     info->grid = P.form == PG_FORM_PLAIN ? batch->n_mol : P.grid;
     info->lds_bytes = (int32_t)P.lds;
-    info->vec = P.vec;
-    info->nt_store = P.nt;
-    info->atom_capacity = P.a_cap;
+    info->vec = P.form == PG_FORM_PLAIN ? 1 : P.vec;
+    info->nt_store = P.form == PG_FORM_PLAIN ? 0 : P.nt;
+    info->atom_capacity = P.form == PG_FORM_PLAIN ? 0 : P.a_cap;
     info->unroll = P.form == PG_FORM_WINDOW ? P.unroll : 0;
-    info->group = P.form == PG_FORM_WINDOW ? P.group : 0;
-    info->prep_waves = P.form == PG_FORM_WINDOW ? P.prep : 0;
+    info->per_cu = P.form == PG_FORM_WINDOW ? P.per_cu : 0;
+    info->reserved = 0;
     return PG_OK;
 }
 
@@ -589,89 +563,66 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
         return PG_E_HIP;
     const char *venv = std::getenv("PG_AUTOTUNE_VERBOSE");
     const bool verbose = venv && venv[0] == '1';
-    const int blocks[] = {256, 512, 1024};
-    const int nts[] = {1, 0};
     Tuned best;
     best.us = 1e30;
     int rc = PG_OK;
-    for (int blk : blocks) {
-        Plan P = base;
-        P.block = blk;
-        // resident workgroups per CU from 1 up to one workgroup per structure
-        // (a grid larger than what stays resident is scheduled by the
-        // hardware as workgroups retire, overlapping one structure's prep
-        // phase with another's stores)
-        std::vector<int> pcs;
-        const int per_cu_all = (batch->n_mol + ctx->n_cu - 1) / ctx->n_cu;
-        for (int v = 1; v <= 64; v *= 2) {
-            if (v >= per_cu_all) {
-                pcs.push_back(std::max(1, per_cu_all));
-                break;
-            }
-            pcs.push_back(v);
-        }
-        for (int pc : pcs) {
-            for (int nt : nts)
-            for (int un : {1, 2})
-            for (int gr : {1, 2, 4})
-            for (int pw : {1, 2}) {
-                set_group(ctx, desc, P, gr);
-                if (P.group != gr)
-                    continue;
-                P.prep = pw;
-                P.per_cu = pc;
-                P.nt = nt;
-                P.unroll = un;
-                P.grid = window_grid(batch, P, ctx->n_cu);
-                if (pc > 1) {
-                    Plan Q = P;
-                    Q.per_cu = pc / 2;
-                    if (window_grid(batch, Q, ctx->n_cu) == P.grid)
-                        continue;   // same launch as a smaller per_cu
-                }
-                GridParams p;
-                fill_params(p, ctx, desc, batch, P, out, ws);
-                hipError_t e = hipSuccess;
-                for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                    e = launch_forward(ctx, desc, P, p, st);
-                if (e == hipSuccess)
-                    e = hipEventRecord(e0, st);
-                for (int r = 0; r < reps && e == hipSuccess; ++r)
-                    e = launch_forward(ctx, desc, P, p, st);
-                if (e == hipSuccess)
-                    e = hipEventRecord(e1, st);
-                if (e == hipSuccess)
-                    e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess)
-                    e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) {
-                    rc = hip_fail(ctx, e);
-                    break;
-                }
-                const double us = 1000.0 * ms / reps;
-                if (verbose)
-                    std::fprintf(stderr,
-                                 "pg_autotune %s block %d per_cu %d grid %d nt %d unroll %d group %d "
-                                 "prep %d: %.2f us\n",
-                                 tuning_key(desc, batch, base.vec).c_str(), blk, pc, P.grid, nt, un,
-                                 gr, pw, us);
-                if (us < best.us) {
-                    best.us = us;
-                    best.block = blk;
-                    best.per_cu = pc;
-                    best.nt = nt;
-                    best.unroll = un;
-                    best.group = gr;
-                    best.prep = pw;
-                }
-            }
-            if (rc != PG_OK)
-                break;
-        }
-        if (rc != PG_OK)
+    // candidates: workgroup size, resident workgroups per CU (up to one
+    // workgroup per structure), runs per lane per pass, store mode
+    std::vector<int> pcs;
+    const int per_cu_all = (batch->n_mol + ctx->n_cu - 1) / ctx->n_cu;
+    for (int v = 1; v <= 64; v *= 2) {
+        if (v >= per_cu_all) {
+            pcs.push_back(std::max(1, per_cu_all));
             break;
+        }
+        pcs.push_back(v);
     }
+    for (int blk : {256, 512, 1024})
+        for (int pc : pcs)
+            for (int un : {1, 2, 4})
+                for (int nt : {0, 1}) {
+                    if (rc != PG_OK)
+                        break;
+                    Plan P = base;
+                    P.block = blk;
+                    P.per_cu = pc;
+                    P.unroll = un;
+                    P.nt = nt;
+                    P.grid = window_grid(batch, P, ctx->n_cu);
+                    GridParams p;
+                    fill_params(p, ctx, desc, batch, P, out, ws);
+                    hipError_t e = hipSuccess;
+                    for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                        e = launch_forward(ctx, desc, P, p, st);
+                    if (e == hipSuccess)
+                        e = hipEventRecord(e0, st);
+                    for (int r = 0; r < reps && e == hipSuccess; ++r)
+                        e = launch_forward(ctx, desc, P, p, st);
+                    if (e == hipSuccess)
+                        e = hipEventRecord(e1, st);
+                    if (e == hipSuccess)
+                        e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess)
+                        e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        rc = hip_fail(ctx, e);
+                        break;
+                    }
+                    const double us = 1000.0 * ms / reps;
+                    if (verbose)
+                        std::fprintf(stderr,
+                                     "pg_autotune %s block %d per_cu %d grid %d unroll %d nt %d: %.2f us\n",
+                                     tuning_key(desc, batch, base.vec).c_str(), blk, pc, P.grid, un,
+                                     nt, us);
+                    if (us < best.us) {
+                        best.us = us;
+                        best.block = blk;
+                        best.per_cu = pc;
+                        best.nt = nt;
+                        best.unroll = un;
+                    }
+                }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc == PG_OK && best.block > 0) {
@@ -692,9 +643,8 @@ int pg_tuning_save(const pg_ctx *ctx, const char *path)
     bool first = true;
     for (const auto &kv : ctx->tuning) {
         f << (first ? "\n" : ",\n") << "  {\"key\": \"" << kv.first << "\", \"block\": "
-          << kv.second.block << ", \"per_cu\": " << kv.second.per_cu << ", \"nt\": "
-          << kv.second.nt << ", \"unroll\": " << kv.second.unroll << ", \"group\": "
-          << kv.second.group << ", \"prep\": " << kv.second.prep << ", \"us\": " << kv.second.us
+          << kv.second.block << ", \"per_cu\": " << kv.second.per_cu << ", \"unroll\": "
+          << kv.second.unroll << ", \"nt\": " << kv.second.nt << ", \"us\": " << kv.second.us
           << "}";
         first = false;
     }
@@ -727,13 +677,11 @@ int pg_tuning_load(pg_ctx *ctx, const char *path)
         const std::string key = txt.substr(pos, q - pos);
         Tuned t;
         if (std::sscanf(txt.c_str() + q,
-                        "\", \"block\": %d, \"per_cu\": %d, \"nt\": %d, \"unroll\": %d, "
-                        "\"group\": %d, \"prep\": %d, \"us\": %lf",
-                        &t.block, &t.per_cu, &t.nt, &t.unroll, &t.group, &t.prep, &t.us) != 7)
+                        "\", \"block\": %d, \"per_cu\": %d, \"unroll\": %d, \"nt\": %d, \"us\": %lf",
+                        &t.block, &t.per_cu, &t.unroll, &t.nt, &t.us) != 5)
             return PG_E_PARAM;
-        if (t.block < 64 || t.block > 1024 || t.block % 64 || t.per_cu < 1 || t.per_cu > 64 ||
-            t.nt < 0 || t.nt > 1 || (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) ||
-            t.group < 1 || t.group > 64 || t.prep < 1 || t.prep > 15)
+        if (t.block < 64 || t.block > 1024 || t.block % 64 || t.nt < 0 || t.nt > 1 ||
+            (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) || t.per_cu < 1 || t.per_cu > 64)
             return PG_E_PARAM;
         tab[key] = t;
         pos = q;
@@ -760,25 +708,15 @@ int pg_set_option(pg_ctx *ctx, int option, int64_t value)
             return PG_E_PARAM;
         ctx->opt_block = (int)value;
         break;
-    case PG_OPT_GRID_PER_CU:
-        if (value != -1 && (value < 1 || value > 64))
-            return PG_E_PARAM;
-        ctx->opt_per_cu = (int)value;
-        break;
     case PG_OPT_NT_STORE:
         if (value < -1 || value > 1)
             return PG_E_PARAM;
         ctx->opt_nt = (int)value;
         break;
-    case PG_OPT_GROUP:
+    case PG_OPT_GRID_PER_CU:
         if (value != -1 && (value < 1 || value > 64))
             return PG_E_PARAM;
-        ctx->opt_group = (int)value;
-        break;
-    case PG_OPT_PREP_WAVES:
-        if (value != -1 && (value < 1 || value > 15))
-            return PG_E_PARAM;
-        ctx->opt_prep = (int)value;
+        ctx->opt_per_cu = (int)value;
         break;
     case PG_OPT_UNROLL:
         if (value != -1 && value != 1 && value != 2 && value != 4)

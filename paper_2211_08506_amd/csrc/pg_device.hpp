@@ -65,6 +65,18 @@ __device__ __forceinline__ int exact_sign(const float (&t)[N])
     return sgn;
 }
 
+// Exact sign of o + fi h - mu - n L + r by expansion arithmetic.  Kept out
+// of line: it runs only for offsets within ~2^-20 of the cutoff edge.
+__device__ __forceinline__ int side_exact(float o, float h, float fi, float mu, int n, float L, float r)
+{
+    float pp, pe, qq = 0.f, qe = 0.f;
+    two_prod(fi, h, pp, pe);
+    if (n != 0)
+        two_prod((float)n, L, qq, qe);
+    const float t[7] = {o, pp, pe, -mu, -qq, -qe, r};
+    return exact_sign(t);
+}
+
 // sign(o + (i + 1/2) h - mu - n L + r), exactly.  A plain FP32 evaluation
 // decides when it is far from zero: with M the sum of the terms' magnitudes,
 // the five roundings below move the result by at most 5 * 2^-24 * M (plus
@@ -79,12 +91,7 @@ __device__ __forceinline__ int side(float o, float h, int i, float mu, int n, fl
     const float M = (((fabsf(o) + fabsf(mu)) + fabsf(p)) + fabsf(q)) + fabsf(r);
     if (fabsf(s) > M * 0x1p-20f)
         return s > 0.f ? 1 : -1;
-    float pp, pe, qq = 0.f, qe = 0.f;
-    two_prod(fi, h, pp, pe);
-    if (n != 0)
-        two_prod((float)n, L, qq, qe);
-    const float t[7] = {o, pp, pe, -mu, -qq, -qe, r};
-    return exact_sign(t);
+    return side_exact(o, h, fi, mu, n, L, r);
 }
 
 // Inside indices of one atom along one axis: up to MAX_IMAGES disjoint
@@ -148,6 +155,8 @@ __device__ __forceinline__ void base_offset(float o, float mu, int n, float L, f
 }
 
 // All ranges of one atom on one axis.  Far-away coordinates give n = 0.
+// Out of line: it is set-up work, and inlining it into the output loops'
+// kernels would raise their register count (and lower their occupancy).
 __device__ __forceinline__ void axis_ranges(float o, float h, int N, float mu, bool periodic,
                                             float L, float rc, bool cut, AxisRanges &R)
 {

@@ -9,20 +9,17 @@
 
 namespace pg {
 
-// Byte layout of the window kernel's dynamic LDS: two buffers (the item
-// being stored and the item being prepared), each holding `group` slots of
-// factor rows followed by `group` slots of plane masks.
+// Byte offsets of the window kernel's dynamic LDS regions.
 struct WindowLds {
-    size_t rows, rows_bytes, masks, masks_bytes, buffer, total;
+    size_t rows, ranges, masks, types, total;
 };
 
-WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int group);
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words);
 
-// Persistent molecule window kernel (pg_window.hip).
-// unroll: runs per lane per pass (1, 2 or 4).
+// Persistent molecule window kernel (pg_window.hip); unroll: runs per lane
+// per pass (1, 2 or 4).
 hipError_t launch_window(const GridParams &p, int out_dtype, int vec, int unroll, int block,
                          int grid, size_t lds, hipStream_t s);
-int window_occupancy(int out_dtype, int vec, int unroll, int block, size_t lds);
 
 // Per-atom window table into the workspace (pg_plain.hip).
 hipError_t launch_prep(const GridParams &p, hipStream_t s);

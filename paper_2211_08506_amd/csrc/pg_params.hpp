@@ -38,8 +38,6 @@ struct GridParams {
     int32_t mask_words;      // 64-bit mask words per (channel, z) plane
     int32_t nt_store;        // non-temporal output stores
     int32_t mol_index;       // plain form: the structure of this launch
-    int32_t group;           // window form: structures per work item
-    int32_t prep_waves;      // window form: waves of the prep role
     int64_t n_atoms;
     float o[3], h[3], L[3];
     float rc[PG_MAX_CHANNELS];

@@ -1,54 +1,64 @@
-// pg_window.hip -- persistent cutoff-window kernel for ragged molecule batches
-// (gfx950).
+// pg_window.hip -- persistent cutoff-window kernel for ragged batches of
+// molecules (gfx950).
 //
 // One workgroup owns one structure at a time (persistent grid, structures
 // strided by gridDim.x).  For its structure it
 //   1. computes every atom's exact per-axis window ranges (one thread per
 //      atom and axis) -- the per-axis search of §VI-B, done exactly;
 //   2. fills dense 1-D factor rows phi_x[W] | phi_y[H] | phi_z[D] per atom in
-//      LDS (zeros outside the window; the separable tables of §VI-A) and,
-//      per (channel, z) plane, a bit mask of the atoms whose z-window
-//      contains that plane;
+//      LDS (zeros outside the window; the separable per-axis tables of
+//      §VI-A) and, per (channel, z) plane, a bit mask of the atoms of that
+//      channel whose z-window contains the plane;
 //   3. streams the structure's C x D x H x W output plane by plane: each
-//      wave takes whole (c, z) planes, each lane a run of VEC consecutive x
-//      (16 bytes), accumulates sum_a phi_z[a][z] phi_y[a][y] phi_x[a][x..]
-//      over the plane's mask in FP32 registers (only atoms of that channel
-//      whose z-window holds the plane), and writes the run once -- zeros
-//      included -- with one 16-byte (optionally non-temporal) store, so a
-//      wave's store instruction covers 1 KiB of contiguous output.
-// Every output element is written exactly once and no atomics touch the
-// output, so the result is bitwise reproducible for any launch shape; the
-// per-voxel sum runs over atoms in index order.
+//      wave takes whole (c, z) planes, each lane U runs of VEC consecutive x
+//      (16 bytes each), accumulates sum_a phi_z[a][z] phi_y[a][y] phi_x[a][x..]
+//      over the plane's mask in FP32 registers and writes each run once --
+//      zeros included -- with a 16-byte store, so one store instruction of a
+//      wave covers 1 KiB of contiguous output.
+// Steps 1-2 run once per structure out of LDS-resident data, so the store
+// stream of step 3 needs no global loads.  Every output element is written
+// exactly once, with no atomics on the output; each voxel's sum runs over
+// atoms in index order, so results are bitwise reproducible for every
+// launch shape.
 #include "pg_device.hpp"
 #include "pg_launch.hpp"
 
 namespace pg {
 
-// LDS buffer of one work item (a group of `group` structures): per slot, the
-// dense factor rows [a_cap][row_stride] and the plane masks
-// [C*D][mask_words].  The kernel holds two such buffers.
+struct RangeRec {
+    int32_t n;
+    int16_t lo[MAX_IMAGES], hi[MAX_IMAGES];
+    float bh[MAX_IMAGES], bl[MAX_IMAGES];
+};
+
 __host__ __device__ inline WindowLds window_lds_layout(int a_cap, int row_stride, int C, int D,
-                                                      int mask_words, int group)
+                                                      int mask_words)
 {
     WindowLds L;
-    L.rows = 0;
-    L.rows_bytes = ((size_t)a_cap * row_stride * sizeof(float) + 15) & ~(size_t)15;
-    L.masks = (size_t)group * L.rows_bytes;
-    L.masks_bytes = (size_t)C * D * mask_words * sizeof(unsigned long long);
-    L.buffer = (L.masks + (size_t)group * L.masks_bytes + 15) & ~(size_t)15;
-    L.total = 2 * L.buffer;
+    size_t off = 0;
+    L.rows = off;
+    off += (size_t)a_cap * row_stride * sizeof(float);
+    off = (off + 15) & ~(size_t)15;
+    L.ranges = off;
+    off += (size_t)a_cap * 3 * sizeof(RangeRec);
+    off = (off + 15) & ~(size_t)15;
+    L.masks = off;
+    off += (size_t)C * D * mask_words * sizeof(unsigned long long);
+    L.types = off;
+    off += (size_t)a_cap * sizeof(int32_t);
+    L.total = (off + 15) & ~(size_t)15;
     return L;
 }
 
-WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int group)
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words)
 {
-    return window_lds_layout(a_cap, row_stride, C, D, mask_words, group);
+    return window_lds_layout(a_cap, row_stride, C, D, mask_words);
 }
 
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v)
 {
-    unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffu));
-    unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffu));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
     return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -70,89 +80,6 @@ __device__ __forceinline__ void load_row(const float *r, float (&v)[VEC])
     }
 }
 
-// Prep role: build the factor rows and plane masks of work item `item` into
-// LDS buffer `buf` (whose masks the store role left zeroed).  One thread per
-// (slot, atom, axis): exact window ranges, then the thread fills that
-// atom's dense row for the axis and, for z, sets the atom's bit in the
-// (type, z) plane masks.  Only these waves touch global memory for inputs.
-__device__ void prep_item(const GridParams &p, const WindowLds &lay, unsigned char *buf, int item,
-                          int tp, int ntp)
-{
-    const int C = p.C, D = p.D, H = p.H, W = p.W;
-    const int RS = p.row_stride, W4 = (W + 3) & ~3, MW = p.mask_words, K = p.group;
-    const int m0 = item * K;
-    const int ns = min(K, p.n_mol - m0);
-    // total (slot, atom, axis) entries; slots with bad offsets or too many
-    // atoms get none (their grids are written as zeros) and raise an error
-    int total = 0;
-    for (int s = 0; s < ns; ++s) {
-        const int m = m0 + s;
-        const int a0 = p.offsets[m], na = p.offsets[m + 1] - a0;
-        const bool bad = na > p.a_cap || na < 0 || a0 < 0 || (long long)a0 + na > p.n_atoms;
-        if (bad && tp == 0)
-            raise_error(p.err, na > p.a_cap ? PG_E_CAPACITY : PG_E_DEVICE_DATA, m);
-        total += bad ? 0 : 3 * na;
-    }
-    for (int i = tp; i < total; i += ntp) {
-        // locate the slot of entry i: the first slot whose entries extend
-        // past i (entries of slot q are [base_q, base_q + cnt_q))
-        int s = 0, base = 0, a0 = 0;
-        for (int q = 0; q < ns; ++q) {
-            const int m = m0 + q;
-            const int qa0 = p.offsets[m], qna = p.offsets[m + 1] - qa0;
-            const bool bad = qna > p.a_cap || qna < 0 || qa0 < 0 || (long long)qa0 + qna > p.n_atoms;
-            const int cnt = bad ? 0 : 3 * qna;
-            if (i < base + cnt) {
-                s = q;
-                a0 = qa0;
-                break;
-            }
-            base += cnt;
-        }
-        const int li = i - base;
-        const int a = li / 3, ax = li - 3 * a;
-        const int m = m0 + s;
-        const size_t ga = (size_t)a0 + a;
-        const float x = p.xyz[3 * ga + 0], y = p.xyz[3 * ga + 1], z = p.xyz[3 * ga + 2];
-        const int t = p.types[ga];
-        if (!atom_valid(x, y, z, t, C)) {
-            if (ax == 0)
-                raise_error(p.err, PG_E_DEVICE_DATA, (long long)ga);
-            continue;
-        }
-        const float mu = ax == 0 ? x : (ax == 1 ? y : z);
-        const int N = ax == 0 ? W : (ax == 1 ? H : D);
-        const int off = ax == 0 ? 0 : (ax == 1 ? W4 : W4 + H);
-        const float o = p.origins ? p.origins[3 * (size_t)m + ax] : (ax == 0 ? p.o[0] : (ax == 1 ? p.o[1] : p.o[2]));
-        const float h = p.spacings ? p.spacings[3 * (size_t)m + ax] : (ax == 0 ? p.h[0] : (ax == 1 ? p.h[1] : p.h[2]));
-        const float L = ax == 0 ? p.L[0] : (ax == 1 ? p.L[1] : p.L[2]);
-        AxisRanges R;
-        axis_ranges(o, h, N, mu, p.periodic != 0, L, p.rc[t], p.cut != 0, R);
-        float *row = (float *)(buf + lay.rows + (size_t)s * lay.rows_bytes) + (size_t)a * RS + off;
-        unsigned long long *masks =
-            (unsigned long long *)(buf + lay.masks + (size_t)s * lay.masks_bytes);
-        const float inv2s2 = p.inv2s2[t];
-        int r = 0;
-        for (int idx = 0; idx < N; ++idx) {
-            // ranges are disjoint and ascending
-            while (r < R.n && idx > (r == 0 ? R.hi[0] : (r == 1 ? R.hi[1] : R.hi[2])))
-                ++r;
-            float v = 0.f;
-            if (r < R.n) {
-                const int lo = r == 0 ? R.lo[0] : (r == 1 ? R.lo[1] : R.lo[2]);
-                if (idx >= lo) {
-                    const float bh = r == 0 ? R.bh[0] : (r == 1 ? R.bh[1] : R.bh[2]);
-                    const float bl = r == 0 ? R.bl[0] : (r == 1 ? R.bl[1] : R.bl[2]);
-                    v = gauss1d(offset_at(bh, bl, h, idx), inv2s2);
-                    if (ax == 2)
-                        atomicOr(&masks[(size_t)(t * D + idx) * MW + (a >> 6)], 1ull << (a & 63));
-                }
-            }
-            row[idx] = v;
-        }
-    }
-}
-
 template <typename T, int VEC, int U>
 __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
 {
@@ -161,14 +88,14 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     const int RS = p.row_stride;
     const int W4 = (W + 3) & ~3;
     const int MW = p.mask_words;
-    const int K = p.group;
-    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW, K);
+    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW);
+    float *rows = (float *)(smem + lay.rows);
+    RangeRec *rr = (RangeRec *)(smem + lay.ranges);
+    unsigned long long *masks = (unsigned long long *)(smem + lay.masks);
+    int32_t *atype = (int32_t *)(smem + lay.types);
 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-    const int n_store = nwaves - p.prep_waves;      // store-role waves
-    const bool prep_role = wave >= n_store;
-    const int tp = tid - n_store * 64, ntp = p.prep_waves * 64;
     const int planes = C * D;
     const size_t plane_elems = (size_t)H * W;
     const size_t mol_elems = (size_t)planes * plane_elems;
@@ -178,88 +105,140 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     // exact for run indices below 2^20
     const int CW = W / VEC;
     const float inv_cw = 1.0f / (float)CW;
-    const int n_items = (p.n_mol + K - 1) / K;
 
-    // both buffers' masks start cleared; afterwards the store role clears
-    // each plane mask right after reading it
-    for (size_t i = tid; i < lay.total / sizeof(unsigned long long); i += nthr)
-        ((unsigned long long *)smem)[i] = 0ull;
-    __syncthreads();
-    if (prep_role && (int)blockIdx.x < n_items)
-        prep_item(p, lay, smem, blockIdx.x, tp, ntp);
-    __syncthreads();
+    for (int m = blockIdx.x; m < p.n_mol; m += gridDim.x) {
+        const int a0 = p.offsets[m];
+        int na = p.offsets[m + 1] - a0;
+        if (na > p.a_cap || na < 0 || a0 < 0 || (long long)a0 + na > p.n_atoms) {
+            // more atoms than the declared capacity (or bad offsets): no
+            // atoms, so the structure's grid is written as zeros; sticky error
+            if (tid == 0)
+                raise_error(p.err, na > p.a_cap ? PG_E_CAPACITY : PG_E_DEVICE_DATA, m);
+            na = 0;
+        }
+        float o[3], h[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            o[q] = p.origins ? p.origins[3 * (size_t)m + q] : p.o[q];
+            h[q] = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
+        }
 
-    int cur = 0;
-    for (int item = blockIdx.x; item < n_items; item += gridDim.x, cur ^= 1) {
-        unsigned char *bcur = smem + (size_t)cur * lay.buffer;
-        if (prep_role) {
-            // the next item of this workgroup, into the other buffer
-            const int nxt = item + gridDim.x;
-            if (nxt < n_items)
-                prep_item(p, lay, smem + (size_t)(cur ^ 1) * lay.buffer, nxt, tp, ntp);
-        } else {
-            // store role: stream the planes of every slot of this item; each
-            // lane owns U runs per pass (U back-to-back 16-byte stores)
-            const int m0 = item * K;
-            const int ns = min(K, p.n_mol - m0);
-            for (int gp = wave; gp < ns * planes; gp += n_store) {
-                const int s = gp / planes;
-                const int pl = gp - s * planes;
-                const int z = pl % D;
-                const float *rows = (const float *)(bcur + lay.rows + (size_t)s * lay.rows_bytes);
-                unsigned long long *masks =
-                    (unsigned long long *)(bcur + lay.masks + (size_t)s * lay.masks_bytes);
-                unsigned long long mk[4];
+        // ---- 1. window ranges per (atom, axis); clear plane masks
+        for (int i = tid; i < planes * MW; i += nthr)
+            masks[i] = 0ull;
+        for (int i = tid; i < na * 3; i += nthr) {
+            const int a = i / 3, ax = i - 3 * a;
+            const size_t ga = (size_t)a0 + a;
+            const float x = p.xyz[3 * ga + 0], y = p.xyz[3 * ga + 1], zc = p.xyz[3 * ga + 2];
+            const int t = p.types[ga];
+            const bool ok = atom_valid(x, y, zc, t, C);
+            RangeRec R;
+            R.n = 0;
+            if (ok) {
+                const float mu = ax == 0 ? x : (ax == 1 ? y : zc);
+                const int N = ax == 0 ? W : (ax == 1 ? H : D);
+                const float oq = ax == 0 ? o[0] : (ax == 1 ? o[1] : o[2]);
+                const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
+                const float Lq = ax == 0 ? p.L[0] : (ax == 1 ? p.L[1] : p.L[2]);
+                AxisRanges ar;
+                axis_ranges(oq, hq, N, mu, p.periodic != 0, Lq, p.rc[t], p.cut != 0, ar);
+                R.n = ar.n;
 #pragma unroll
-                for (int w = 0; w < 4; ++w)
-                    mk[w] = (w < MW) ? uniform64(masks[(size_t)pl * MW + w]) : 0ull;
-                // this wave is the only reader of the plane's mask: clear it
-                // for the item that will reuse the buffer
-                if (lane < MW)
-                    masks[(size_t)pl * MW + lane] = 0ull;
-                T *op = (T *)p.out + (size_t)(m0 + s) * mol_elems + (size_t)pl * plane_elems;
-                for (int j0 = lane; j0 < chunks; j0 += 64 * U) {
-                    int yq[U], xq[U];
-                    bool ok[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int j = j0 + 64 * u;
-                        ok[u] = j < chunks;
-                        // run j starts at element j*VEC: row j / CW, column (j % CW) * VEC
-                        const int yy = (int)(((float)j + 0.5f) * inv_cw);
-                        yq[u] = ok[u] ? yy : 0;
-                        xq[u] = ok[u] ? (j - yy * CW) * VEC : 0;
+                for (int r = 0; r < MAX_IMAGES; ++r) {
+                    R.lo[r] = (int16_t)(r < ar.n ? ar.lo[r] : 0);
+                    R.hi[r] = (int16_t)(r < ar.n ? ar.hi[r] : -1);
+                    R.bh[r] = r < ar.n ? ar.bh[r] : 0.f;
+                    R.bl[r] = r < ar.n ? ar.bl[r] : 0.f;
+                }
+            }
+            rr[i] = R;
+            if (ax == 0) {
+                atype[a] = ok ? t : -1;
+                if (!ok)
+                    raise_error(p.err, PG_E_DEVICE_DATA, (long long)ga);
+            }
+        }
+        __syncthreads();
+
+        // ---- 2. dense 1-D factor rows and (channel, z) atom masks
+        for (int e = tid; e < na * RS; e += nthr) {
+            const int a = e / RS, j = e - a * RS;
+            int ax, i, N;
+            if (j < W4) {
+                ax = 0; i = j; N = W;
+            } else if (j < W4 + H) {
+                ax = 1; i = j - W4; N = H;
+            } else {
+                ax = 2; i = j - W4 - H; N = D;
+            }
+            const int t = atype[a];
+            float v = 0.f;
+            if (t >= 0 && i < N) {
+                const RangeRec &R = rr[3 * a + ax];
+                const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
+                for (int r = 0; r < R.n; ++r) {
+                    if (i >= R.lo[r] && i <= R.hi[r]) {
+                        v = gauss1d(offset_at(R.bh[r], R.bl[r], hq, i), p.inv2s2[t]);
+                        if (ax == 2)
+                            atomicOr(&masks[(size_t)(t * D + i) * MW + (a >> 6)], 1ull << (a & 63));
                     }
-                    float acc[U][VEC];
+                }
+            }
+            rows[e] = v;
+        }
+        __syncthreads();
+
+        // ---- 3. stream the planes: each lane owns U runs per pass, so a
+        // wave issues U back-to-back 16-byte stores per pass
+        T *out = (T *)p.out + (size_t)m * mol_elems;
+        for (int pl = wave; pl < planes; pl += nwaves) {
+            const int z = pl % D;
+            unsigned long long mk[4];
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
+            for (int w = 0; w < 4; ++w)
+                mk[w] = (w < MW) ? uniform64(masks[(size_t)pl * MW + w]) : 0ull;
+            T *op = out + (size_t)pl * plane_elems;
+            for (int j0 = lane; j0 < chunks; j0 += 64 * U) {
+                int yq[U], xq[U];
+                bool ok[U];
 #pragma unroll
-                        for (int k = 0; k < VEC; ++k)
-                            acc[u][k] = 0.f;
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + 64 * u;
+                    ok[u] = j < chunks;
+                    // run j starts at element j*VEC: row j / CW, column (j % CW) * VEC
+                    const int yy = (int)(((float)j + 0.5f) * inv_cw);
+                    yq[u] = ok[u] ? yy : 0;
+                    xq[u] = ok[u] ? (j - yy * CW) * VEC : 0;
+                }
+                float acc[U][VEC];
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        unsigned long long bits = mk[w];
-                        while (bits) {
-                            const int a = w * 64 + __builtin_ctzll(bits);
-                            bits &= bits - 1;
-                            const float *row = rows + a * RS;
-                            const float gz = row[W4 + H + z];
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                            for (int u = 0; u < U; ++u) {
-                                const float gy = row[W4 + yq[u]] * gz;
-                                float fx[VEC];
-                                load_row<VEC>(row + xq[u], fx);
+                    for (int k = 0; k < VEC; ++k)
+                        acc[u][k] = 0.f;
 #pragma unroll
-                                for (int k = 0; k < VEC; ++k)
-                                    acc[u][k] = __builtin_fmaf(gy, fx[k], acc[u][k]);
-                            }
+                for (int w = 0; w < 4; ++w) {
+                    unsigned long long bits = mk[w];
+                    while (bits) {
+                        const int a = w * 64 + __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const float *row = rows + a * RS;
+                        const float gz = row[W4 + H + z];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const float gy = row[W4 + yq[u]] * gz;
+                            float fx[VEC];
+                            load_row<VEC>(row + xq[u], fx);
+#pragma unroll
+                            for (int k = 0; k < VEC; ++k)
+                                acc[u][k] = __builtin_fmaf(gy, fx[k], acc[u][k]);
                         }
                     }
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (ok[u])
-                            store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], nt);
                 }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u])
+                        store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], nt);
             }
         }
         __syncthreads();
@@ -275,8 +254,12 @@ static const void *window_fn()
 template <typename T, int VEC>
 static const void *window_fn_u(int unroll)
 {
-    return unroll >= 4 ? window_fn<T, VEC, 4>() : unroll == 2 ? window_fn<T, VEC, 2>()
-                                                              : window_fn<T, VEC, 1>();
+    switch (unroll) {
+    case 1: return window_fn<T, VEC, 1>();
+    case 2: return window_fn<T, VEC, 2>();
+    case 4: return window_fn<T, VEC, 4>();
+    }
+    return nullptr;
 }
 
 static const void *window_kernel_fn(int out_dtype, int vec, int unroll)
@@ -304,6 +287,8 @@ hipError_t launch_window(const GridParams &p, int out_dtype, int vec, int unroll
     const void *k = window_kernel_fn(out_dtype, vec, unroll);
     if (!k)
         return hipErrorInvalidValue;
+    if (p.n_mol == 0)
+        return hipSuccess;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -312,19 +297,6 @@ hipError_t launch_window(const GridParams &p, int out_dtype, int vec, int unroll
     GridParams pc = p;
     void *args[] = {&pc};
     return hipLaunchKernel(k, dim3(grid), dim3(block), args, lds, s);
-}
-
-int window_occupancy(int out_dtype, int vec, int unroll, int block, size_t lds)
-{
-    int n = 0;
-    const void *k = window_kernel_fn(out_dtype, vec, unroll);
-    if (!k)
-        return 1;
-    if (lds > 65536)
-        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
 }
 
 }  // namespace pg

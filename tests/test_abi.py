@@ -131,7 +131,7 @@ def test_workspace_and_plan_host_only():
     n = ctypes.c_size_t(123)
     d = desc_ok(form="window")
     assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(batch_ok()), ctypes.byref(n)) == 0
-    assert n.value == 0
+    assert n.value == 0                  # the window form needs no workspace
     d = desc_ok(form="plain")
     assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(batch_ok()), ctypes.byref(n)) == 0
     assert n.value >= 40 * 100 and n.value % 256 == 0

@@ -225,9 +225,9 @@ def test_capacity_overflow_reports_and_zeroes(pg, dev):
     b = synth.Batch(xyz, rng.integers(0, 5, off[-1]).astype(np.int32), off)
     wl = synth.WORKLOADS["mol256"]
     ref = ref_grid(b, wl.sigma(), wl.dims, wl.spacing, wl.origin)
-    for group in (1, 4):
+    for block in (64, 512):
         ctx = pg.Context(0)
-        ctx.set_option(pg.PG_OPT_GROUP, group)
+        ctx.set_option(pg.PG_OPT_BLOCK, block)
         g = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, form="window", ctx=ctx,
                 max_atoms=8)                   # capacity rounds to 8 atoms
         code, first = ctx.device_error()
@@ -250,15 +250,14 @@ def test_determinism_across_launch_shapes(pg, dev):
     base = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, torch.bfloat16, ctx=ctx)
     again = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, torch.bfloat16, ctx=ctx)
     assert torch.equal(base, again)
-    for blk, pc, nt, un, gr in ((64, 1, 0, 1, 1), (512, 2, 1, 2, 4), (1024, 1, 1, 4, 8),
-                                (128, 8, 0, 2, 3), (256, 1, 1, 1, 64)):
+    for blk, pc, un, nt in ((64, 1, 1, 0), (256, 2, 2, 1), (512, 4, 4, 1), (128, 8, 2, 0),
+                            (1024, 1, 1, 1), (192, 3, 4, 0)):
         ctx.set_option(pg.PG_OPT_BLOCK, blk)
         ctx.set_option(pg.PG_OPT_GRID_PER_CU, pc)
-        ctx.set_option(pg.PG_OPT_NT_STORE, nt)
         ctx.set_option(pg.PG_OPT_UNROLL, un)
-        ctx.set_option(pg.PG_OPT_GROUP, gr)
+        ctx.set_option(pg.PG_OPT_NT_STORE, nt)
         g = run(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, torch.bfloat16, ctx=ctx)
-        assert torch.equal(base, g), (blk, pc, nt, un, gr)
+        assert torch.equal(base, g), (blk, pc, un, nt)
 
 
 def test_permutation_invariance(pg, dev):
