@@ -70,9 +70,20 @@ enum { PG_OUT_F32 = 0, PG_OUT_BF16 = 1 };
 
 /* Kernel form.  AUTO lets the library choose (per-shape rule, refined by
    pg_autotune).  PLAIN: one thread per voxel, one launch per structure (the
-   baseline form).  WINDOW: persistent cutoff-window gather, atoms staged in
-   LDS, one launch per batch.  MFMA: separable BF16 matrix-core
-   contraction per z-plane for large, dense structures. */
+   baseline form).  WINDOW: cutoff-window gather in float32.  For structures
+   whose atoms fit the window kernel's LDS (max_atoms <= 256 and the staged
+   factor rows within the device's LDS) it is one persistent launch per
+   batch with each structure's atoms staged in LDS; larger structures take
+   the binned path (atoms binned per (structure, channel, z plane), one
+   workgroup per plane).  MFMA: binned path whose plane kernel evaluates
+   the separable factorisation (§III-A, §IV-C) of each plane as a BF16
+   matrix-core contraction over the plane's atoms (factors rounded to
+   bf16, float32 accumulation); meant for bf16 grids of large, dense
+   structures.  AUTO picks WINDOW when the structure fits, else MFMA for
+   bf16 and WINDOW (binned) for float32 output.  The binned path needs a
+   workspace (pg_workspace_size) and does not take per-structure spacings;
+   a plane holding more than 4096 atom windows of one channel is reported
+   as PG_E_CAPACITY through pg_get_device_error and left as zeros. */
 enum { PG_FORM_AUTO = 0, PG_FORM_PLAIN = 1, PG_FORM_WINDOW = 2, PG_FORM_MFMA = 3 };
 
 /* Grid description (all fields host values). */
@@ -193,11 +204,13 @@ int pg_last_hip_error(const pg_ctx *ctx);
 /* Describe the kernel configuration pg_grid_forward would use for this
    request: form, workgroup size, workgroups launched (per launch; the
    plain form launches one per structure), dynamic LDS bytes, output vector
-   width, non-temporal stores, atom capacity per structure, runs per lane
-   per pass and persistent workgroups per CU (window form).  Host only.
-   Errors: validation codes. */
+   width, non-temporal stores, atom capacity (per structure; per plane bin
+   on the binned path), runs per lane per pass and persistent workgroups
+   per CU (small-structure window form), and binned = 1 when the request
+   takes the binned large-structure path.  Host only.
+   Errors: validation codes, PG_E_UNSUPPORTED. */
 typedef struct pg_plan_info {
-    int32_t form, block, grid, lds_bytes, vec, nt_store, atom_capacity, unroll, per_cu, reserved;
+    int32_t form, block, grid, lds_bytes, vec, nt_store, atom_capacity, unroll, per_cu, binned;
 } pg_plan_info;
 int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
             const void *out, pg_plan_info *info);

@@ -65,7 +65,7 @@ class Batch(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("form", "block", "grid", "lds_bytes", "vec", "nt_store", "atom_capacity",
-                 "unroll", "per_cu", "reserved")]
+                 "unroll", "per_cu", "binned")]
 
 
 _LIB = None
@@ -248,7 +248,7 @@ class Context:
         info = PlanInfo()
         _check(_lib().pg_plan(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
                               _ptr(out), ctypes.byref(info)), "pg_plan")
-        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_ if n != "reserved"}
+        d = {n: getattr(info, n) for n, _ in PlanInfo._fields_}
         d["form"] = FORM_NAMES.get(d["form"], d["form"])
         return d
 

@@ -18,19 +18,6 @@
 
 namespace pg {
 
-__device__ __forceinline__ int structure_of_atom(const int32_t *offsets, int n_mol, long long a)
-{
-    int lo = 0, hi = n_mol;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((long long)offsets[mid] <= a)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ float wave_sum(float v)
 {
 #pragma unroll
@@ -69,7 +56,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                 raise_error(p.err, PG_E_DEVICE_DATA, a);
             t = -1;
         } else {
-            m = structure_of_atom(p.offsets, p.n_mol, a);
+            m = structure_of(p.offsets, p.n_mol, a);
             for (int q = 0; q < 3; ++q) {
                 o[q] = p.origins ? p.origins[3 * m + q] : p.o[q];
                 h[q] = p.spacings ? p.spacings[3 * m + q] : p.h[q];

@@ -34,6 +34,7 @@ constexpr int kGraphCacheSize = 32;
 
 struct Tuned {
     int block = 0, per_cu = 0, nt = -1, unroll = 0;
+    int form = 0;   // large structures: the measured faster form (0 = not tuned)
     double us = 0.0;
 };
 
@@ -156,11 +157,58 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
 
 struct Plan {
     int form = PG_FORM_WINDOW;
+    bool crystal = false;     // large-structure path (bins + plane kernel)
     int block = 256, grid = 1, per_cu = 0, vec = 1, nt = 1, unroll = 1;
     int a_cap = 8, row_stride = 4, mask_words = 1;
+    int bin_cap = 0;
     size_t lds = 0;           // dynamic LDS bytes of one workgroup
     size_t ws = 0;            // workspace bytes
+    size_t ws_counts = 0, ws_offsets = 0, ws_cursor = 0, ws_list = 0;  // crystal layout
 };
+
+constexpr int kCrystalBinCap = 4096;   // atoms one plane kernel sorts in LDS
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Crystal path: workspace layout (per-atom records | bin counts | bin
+// offsets | fill cursors | bin lists) and the plane kernel's LDS.
+int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, int form, Plan &P)
+{
+    if (b->spacings)
+        return PG_E_UNSUPPORTED;
+    if (form == PG_FORM_WINDOW && crystal_window_runs(d->H, d->W) == 0)
+        return PG_E_UNSUPPORTED;
+    P.crystal = true;
+    P.form = form;
+    P.bin_cap = kCrystalBinCap;
+    P.lds = crystal_plane_lds(form, d->H, d->W, P.bin_cap);
+    const int max_lds = ctx ? ctx->max_lds : 65536;
+    if (P.lds > (size_t)max_lds)
+        return PG_E_UNSUPPORTED;
+    float rc_max = 0.f;
+    for (int c = 0; c < d->C; ++c)
+        rc_max = std::max(rc_max, rc_of(d, c));
+    const long long imgs = d->periodic ? 3 : 1;
+    long long zmax = d->D;
+    if (d->cutoff_k > 0.f)
+        zmax = std::min<long long>(d->D, imgs * ((long long)std::ceil(2.0 * rc_max / d->spacing[2]) + 2));
+    const long long nb = (long long)b->n_mol * d->C * d->D;
+    const long long entries = b->n_atoms * zmax;
+    if (entries > 0xffffffffLL || nb + 1 > 0xffffffffLL)
+        return PG_E_SHAPE;
+    P.ws_counts = align256((size_t)b->n_atoms * sizeof(AtomWindow));
+    P.ws_offsets = P.ws_counts + align256((size_t)nb * 4);
+    P.ws_cursor = P.ws_offsets + align256((size_t)(nb + 1) * 4);
+    P.ws_list = P.ws_cursor + align256((size_t)nb * 4);
+    P.ws = P.ws_list + align256((size_t)std::max<long long>(entries, 1) * 4);
+    P.block = 256;
+    P.vec = 1;
+    const long long blocks = form == PG_FORM_MFMA ? nb * ((d->H + 127) / 128) * ((d->W + 127) / 128) : nb;
+    if (blocks * P.block > 0xffffffffLL)   // grid size limit of one launch
+        return PG_E_UNSUPPORTED;
+    P.grid = (int)blocks;
+    return PG_OK;
+}
 
 std::string tuning_key(const pg_grid_desc *d, const pg_batch *b, int vec)
 {
@@ -222,13 +270,24 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
     P.vec = pick_vec(d, out);
     const bool fits = window_fits(ctx, d, b, P);
     int form = d->form;
-    if (form == PG_FORM_AUTO)
-        form = fits ? PG_FORM_WINDOW : PG_FORM_MFMA;
+    if (form == PG_FORM_AUTO) {
+        if (fits) {
+            form = PG_FORM_WINDOW;
+        } else {
+            // large structures: the MFMA contraction rounds its factors to
+            // bf16, so it serves bf16 grids; fp32 grids take the fp32
+            // vector form.  A measured choice (pg_autotune) overrides.
+            form = d->out_dtype == PG_OUT_BF16 ? PG_FORM_MFMA : PG_FORM_WINDOW;
+            if (ctx) {
+                auto it = ctx->tuning.find(tuning_key(d, b, P.vec));
+                if (it != ctx->tuning.end() && it->second.form > 0)
+                    form = it->second.form;
+            }
+        }
+    }
     P.form = form;
-    if (form == PG_FORM_MFMA)
-        return PG_E_UNSUPPORTED;
-    if (form == PG_FORM_WINDOW && !fits)
-        return PG_E_UNSUPPORTED;
+    if (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits))
+        return crystal_plan(ctx, d, b, form, P);
     if (form == PG_FORM_PLAIN) {
         P.ws = (size_t)b->n_atoms * sizeof(AtomWindow);
         P.ws = (P.ws + 255) & ~(size_t)255;
@@ -316,6 +375,17 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
                 return e;
         }
         return hipSuccess;
+    }
+    if (P.crystal) {
+        unsigned char *ws = (unsigned char *)p.ws;
+        CrystalParams q;
+        q.table = (AtomWindow *)ws;
+        q.counts = (uint32_t *)(ws + P.ws_counts);
+        q.offsets = (uint32_t *)(ws + P.ws_offsets);
+        q.cursor = (uint32_t *)(ws + P.ws_cursor);
+        q.list = (int32_t *)(ws + P.ws_list);
+        q.bin_cap = P.bin_cap;
+        return launch_crystal(p, q, P.form, d->out_dtype, P.lds, s);
     }
     return launch_window(p, d->out_dtype, P.vec, P.unroll, P.block, P.grid, P.lds, s);
 }
@@ -497,9 +567,12 @@ int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, 
     info->vec = P.form == PG_FORM_PLAIN ? 1 : P.vec;
     info->nt_store = P.form == PG_FORM_PLAIN ? 0 : P.nt;
     info->atom_capacity = P.form == PG_FORM_PLAIN ? 0 : P.a_cap;
-    info->unroll = P.form == PG_FORM_WINDOW ? P.unroll : 0;
-    info->per_cu = P.form == PG_FORM_WINDOW ? P.per_cu : 0;
-    info->reserved = 0;
+    const bool mol_window = P.form == PG_FORM_WINDOW && !P.crystal;
+    info->unroll = mol_window ? P.unroll : 0;
+    info->per_cu = mol_window ? P.per_cu : 0;
+    if (P.crystal)
+        info->atom_capacity = P.bin_cap;
+    info->binned = P.crystal ? 1 : 0;
     return PG_OK;
 }
 
@@ -552,17 +625,79 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
     int s = make_plan(ctx, desc, batch, out, base);
     if (s != PG_OK)
         return s;
-    if (base.form != PG_FORM_WINDOW || batch->n_mol == 0)
+    if (batch->n_mol == 0 || base.form == PG_FORM_PLAIN)
         return PG_OK;   // nothing tunable for this request
+    if (base.crystal && (desc->form != PG_FORM_AUTO || desc->out_dtype != PG_OUT_BF16))
+        return PG_OK;   // a single admissible large-structure form
     if (reps < 1)
         reps = 1;
+    const char *venv = std::getenv("PG_AUTOTUNE_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return PG_E_HIP;
-    const char *venv = std::getenv("PG_AUTOTUNE_VERBOSE");
-    const bool verbose = venv && venv[0] == '1';
+    auto time_plan = [&](const Plan &P, double &us) -> hipError_t {
+        GridParams p;
+        fill_params(p, ctx, desc, batch, P, out, ws);
+        hipError_t e = hipSuccess;
+        for (int w = 0; w < 2 && e == hipSuccess; ++w)
+            e = launch_forward(ctx, desc, P, p, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_forward(ctx, desc, P, p, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(e1, st);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        us = 1000.0 * ms / reps;
+        return e;
+    };
+    if (base.crystal) {
+        // bf16 grids of large structures: measure both admissible forms
+        int best_form = 0;
+        double best_us = 1e30;
+        int rc = PG_OK;
+        for (int f : {PG_FORM_MFMA, PG_FORM_WINDOW}) {
+            Plan P;
+            P.vec = base.vec;
+            if (crystal_plan(ctx, desc, batch, f, P) != PG_OK || ws_bytes < P.ws || !ws)
+                continue;
+            double us = 0;
+            hipError_t e = time_plan(P, us);
+            if (e != hipSuccess) {
+                rc = hip_fail(ctx, e);
+                break;
+            }
+            if (verbose)
+                std::fprintf(stderr, "pg_autotune %s form %d: %.2f us\n",
+                             tuning_key(desc, batch, base.vec).c_str(), f, us);
+            if (us < best_us) {
+                best_us = us;
+                best_form = f;
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc == PG_OK && best_form > 0) {
+            Tuned &t = ctx->tuning[tuning_key(desc, batch, base.vec)];
+            t.form = best_form;
+            t.us = best_us;
+            if (t.block == 0) {
+                t.block = 256;
+                t.per_cu = 1;
+                t.nt = 0;
+                t.unroll = 1;
+            }
+            drop_graphs(ctx);
+        }
+        return rc;
+    }
     Tuned best;
     best.us = 1e30;
     int rc = PG_OK;
@@ -589,27 +724,12 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
                     P.unroll = un;
                     P.nt = nt;
                     P.grid = window_grid(batch, P, ctx->n_cu);
-                    GridParams p;
-                    fill_params(p, ctx, desc, batch, P, out, ws);
-                    hipError_t e = hipSuccess;
-                    for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                        e = launch_forward(ctx, desc, P, p, st);
-                    if (e == hipSuccess)
-                        e = hipEventRecord(e0, st);
-                    for (int r = 0; r < reps && e == hipSuccess; ++r)
-                        e = launch_forward(ctx, desc, P, p, st);
-                    if (e == hipSuccess)
-                        e = hipEventRecord(e1, st);
-                    if (e == hipSuccess)
-                        e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess)
-                        e = hipEventElapsedTime(&ms, e0, e1);
+                    double us = 0;
+                    hipError_t e = time_plan(P, us);
                     if (e != hipSuccess) {
                         rc = hip_fail(ctx, e);
                         break;
                     }
-                    const double us = 1000.0 * ms / reps;
                     if (verbose)
                         std::fprintf(stderr,
                                      "pg_autotune %s block %d per_cu %d grid %d unroll %d nt %d: %.2f us\n",
@@ -644,8 +764,8 @@ int pg_tuning_save(const pg_ctx *ctx, const char *path)
     for (const auto &kv : ctx->tuning) {
         f << (first ? "\n" : ",\n") << "  {\"key\": \"" << kv.first << "\", \"block\": "
           << kv.second.block << ", \"per_cu\": " << kv.second.per_cu << ", \"unroll\": "
-          << kv.second.unroll << ", \"nt\": " << kv.second.nt << ", \"us\": " << kv.second.us
-          << "}";
+          << kv.second.unroll << ", \"nt\": " << kv.second.nt << ", \"form\": " << kv.second.form
+          << ", \"us\": " << kv.second.us << "}";
         first = false;
     }
     f << "\n]}\n";
@@ -669,22 +789,39 @@ int pg_tuning_load(pg_ctx *ctx, const char *path)
         return PG_E_PARAM;
     std::map<std::string, Tuned> tab;
     size_t pos = 0;
+    auto field = [](const std::string &obj, const char *name, double &v) {
+        const std::string k = std::string("\"") + name + "\": ";
+        const size_t at = obj.find(k);
+        if (at == std::string::npos)
+            return false;
+        return std::sscanf(obj.c_str() + at + k.size(), "%lf", &v) == 1;
+    };
     while ((pos = txt.find("{\"key\": \"", pos)) != std::string::npos) {
         pos += 9;
         const size_t q = txt.find('"', pos);
-        if (q == std::string::npos)
+        const size_t end = txt.find('}', pos);
+        if (q == std::string::npos || end == std::string::npos || end < q)
             return PG_E_PARAM;
         const std::string key = txt.substr(pos, q - pos);
-        Tuned t;
-        if (std::sscanf(txt.c_str() + q,
-                        "\", \"block\": %d, \"per_cu\": %d, \"unroll\": %d, \"nt\": %d, \"us\": %lf",
-                        &t.block, &t.per_cu, &t.unroll, &t.nt, &t.us) != 5)
+        const std::string obj = txt.substr(q, end - q);
+        double blk, pc, un, nt, us, form = 0;
+        if (!field(obj, "block", blk) || !field(obj, "per_cu", pc) || !field(obj, "unroll", un) ||
+            !field(obj, "nt", nt) || !field(obj, "us", us))
             return PG_E_PARAM;
+        field(obj, "form", form);
+        Tuned t;
+        t.block = (int)blk;
+        t.per_cu = (int)pc;
+        t.unroll = (int)un;
+        t.nt = (int)nt;
+        t.us = us;
+        t.form = (int)form;
         if (t.block < 64 || t.block > 1024 || t.block % 64 || t.nt < 0 || t.nt > 1 ||
-            (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) || t.per_cu < 1 || t.per_cu > 64)
+            (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) || t.per_cu < 1 || t.per_cu > 64 ||
+            (t.form != 0 && t.form != PG_FORM_WINDOW && t.form != PG_FORM_MFMA))
             return PG_E_PARAM;
         tab[key] = t;
-        pos = q;
+        pos = end;
     }
     ctx->tuning = std::move(tab);
     return PG_OK;

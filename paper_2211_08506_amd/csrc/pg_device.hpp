@@ -65,8 +65,9 @@ __device__ __forceinline__ int exact_sign(const float (&t)[N])
     return sgn;
 }
 
-// Exact sign of o + fi h - mu - n L + r by expansion arithmetic.  Kept out
-// of line: it runs only for offsets within ~2^-20 of the cutoff edge.
+// Exact sign of o + fi h - mu - n L + r by expansion arithmetic.  Reached
+// only for offsets within ~2^-20 of the cutoff edge (inlined: measured
+// faster than a call in the window kernel's set-up phase).
 __device__ __forceinline__ int side_exact(float o, float h, float fi, float mu, int n, float L, float r)
 {
     float pp, pe, qq = 0.f, qe = 0.f;
@@ -155,8 +156,7 @@ __device__ __forceinline__ void base_offset(float o, float mu, int n, float L, f
 }
 
 // All ranges of one atom on one axis.  Far-away coordinates give n = 0.
-// Out of line: it is set-up work, and inlining it into the output loops'
-// kernels would raise their register count (and lower their occupancy).
+// Set-up work: runs once per atom and axis, before any output is written.
 __device__ __forceinline__ void axis_ranges(float o, float h, int N, float mu, bool periodic,
                                             float L, float rc, bool cut, AxisRanges &R)
 {
@@ -303,6 +303,69 @@ __device__ __forceinline__ void raise_error(DeviceError *err, int code, long lon
 __device__ __forceinline__ bool atom_valid(float x, float y, float z, int t, int C)
 {
     return t >= 0 && t < C && isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+// ---------------------------------------------------------------------------
+// Per-atom window records (plain and crystal paths)
+// ---------------------------------------------------------------------------
+// Structure holding global atom a: the last m with offsets[m] <= a (that
+// structure is non-empty and owns a).
+__device__ __forceinline__ int structure_of(const int32_t *offsets, int n_mol, long long a)
+{
+    int lo = 0, hi = n_mol;   // invariant: offsets[lo] <= a < offsets[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)offsets[mid] <= a)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Exact window ranges of atom a on the three axes (type -1: skipped atom,
+// which also raises the device error).  Returns the atom's structure.
+__device__ inline int write_atom_window(const GridParams &p, long long a, AtomWindow *w)
+{
+    const float mu[3] = {p.xyz[3 * a], p.xyz[3 * a + 1], p.xyz[3 * a + 2]};
+    const int t = p.types[a];
+    const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.C);
+    if (!ok)
+        raise_error(p.err, PG_E_DEVICE_DATA, a);
+    const int m = structure_of(p.offsets, p.n_mol, a);
+    w->type = ok ? t : -1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        AxisRanges R;
+        R.n = 0;
+        if (ok) {
+            const float o = p.origins ? p.origins[3 * (size_t)m + q] : p.o[q];
+            const float h = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
+            const int N = q == 0 ? p.W : (q == 1 ? p.H : p.D);
+            axis_ranges(o, h, N, mu[q], p.periodic != 0, p.L[q], p.rc[t], p.cut != 0, R);
+        }
+        w->n[q] = R.n;
+#pragma unroll
+        for (int r = 0; r < MAX_IMAGES; ++r) {
+            const bool u = r < R.n;
+            w->lo[q][r] = u ? R.lo[r] : 0;
+            w->hi[q][r] = u ? R.hi[r] : -1;
+            w->bh[q][r] = u ? R.bh[r] : 0.f;
+            w->bl[q][r] = u ? R.bl[r] : 0.f;
+        }
+    }
+    return m;
+}
+
+// Factor of one axis at index i from a window record: 0 outside the window.
+__device__ __forceinline__ float record_factor(const AtomWindow &w, int q, int i, float h,
+                                               float inv2s2)
+{
+    float v = 0.f;
+    for (int r = 0; r < w.n[q]; ++r)
+        if (i >= w.lo[q][r] && i <= w.hi[q][r])
+            v = gauss1d(offset_at(w.bh[q][r], w.bl[q][r], h, i), inv2s2);
+    return v;
 }
 
 }  // namespace pg

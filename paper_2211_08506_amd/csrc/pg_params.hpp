@@ -53,4 +53,14 @@ struct AtomWindow {
     float bh[3][3], bl[3][3];
 };
 
+// Crystal path: per-atom window records and (structure, channel, z) bins.
+struct CrystalParams {
+    AtomWindow *table;       // n_atoms records
+    uint32_t *counts;        // n_mol * C * D bin sizes
+    uint32_t *offsets;       // n_mol * C * D + 1 bin starts
+    uint32_t *cursor;        // n_mol * C * D fill cursors
+    int32_t *list;           // bin contents: global atom indices
+    int32_t bin_cap;         // most atoms a plane kernel sorts in LDS (a power of two)
+};
+
 }  // namespace pg

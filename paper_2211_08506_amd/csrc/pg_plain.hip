@@ -13,53 +13,12 @@
 
 namespace pg {
 
-__device__ __forceinline__ int structure_of(const int32_t *offsets, int n_mol, long long a)
-{
-    // last m with offsets[m] <= a (that structure is non-empty and holds a)
-    int lo = 0, hi = n_mol;   // invariant: offsets[lo] <= a < offsets[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((long long)offsets[mid] <= a)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __global__ void __launch_bounds__(256) prep_kernel(GridParams p)
 {
     const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= p.n_atoms)
         return;
-    AtomWindow *w = (AtomWindow *)p.ws + a;
-    const float mu[3] = {p.xyz[3 * a], p.xyz[3 * a + 1], p.xyz[3 * a + 2]};
-    const int t = p.types[a];
-    const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.C);
-    if (!ok)
-        raise_error(p.err, PG_E_DEVICE_DATA, a);
-    const int m = ok ? structure_of(p.offsets, p.n_mol, a) : 0;
-    w->type = ok ? t : -1;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        AxisRanges R;
-        R.n = 0;
-        if (ok) {
-            const float o = p.origins ? p.origins[3 * m + q] : p.o[q];
-            const float h = p.spacings ? p.spacings[3 * m + q] : p.h[q];
-            const int N = q == 0 ? p.W : (q == 1 ? p.H : p.D);
-            axis_ranges(o, h, N, mu[q], p.periodic != 0, p.L[q], p.rc[t], p.cut != 0, R);
-        }
-        w->n[q] = R.n;
-#pragma unroll
-        for (int r = 0; r < MAX_IMAGES; ++r) {
-            const bool u = r < R.n;
-            w->lo[q][r] = u ? R.lo[r] : 0;
-            w->hi[q][r] = u ? R.hi[r] : -1;
-            w->bh[q][r] = u ? R.bh[r] : 0.f;
-            w->bl[q][r] = u ? R.bl[r] : 0.f;
-        }
-    }
+    write_atom_window(p, a, (AtomWindow *)p.ws + a);
 }
 
 template <typename T>

@@ -142,10 +142,25 @@ def test_workspace_and_plan_host_only():
     # misaligned output pointer falls back to narrower stores
     assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok()), 0x10002, ctypes.byref(info)) == 0
     assert info.vec == 1
-    # structures larger than the window kernel's LDS capacity need the large-structure path
+    # structures larger than the window kernel's LDS capacity take the
+    # large-structure (binned plane) path, which needs a workspace
+    big = batch_ok(n_atoms=4000, max_atoms=1000)
+    for form, dtype in (("window", "f32"), ("mfma", "bf16"), ("auto", "bf16"), ("auto", "f32")):
+        d = desc_ok(form=form, out_dtype=dtype)
+        assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000, ctypes.byref(info)) == 0
+        want = "mfma" if (form == "mfma" or (form == "auto" and dtype == "bf16")) else "window"
+        assert info.form == pg.FORMS[want] and info.binned == 1 and info.atom_capacity == 4096
+        assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(big), ctypes.byref(n)) == 0
+        # per-atom records + 3 counters per (structure, channel, z plane) + bin lists
+        assert n.value >= 4000 * 160 + 3 * 4 * 5 * 32 * 4 and n.value % 256 == 0
+    # per-structure spacings are not supported on the large-structure path
+    big.spacings = 0x2000
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000,
+                       ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
+    # the small-structure window plan reports no large-structure flag
     d = desc_ok(form="window")
-    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok(n_atoms=4000, max_atoms=1000)),
-                       0x10000, ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok()), 0x10000, ctypes.byref(info)) == 0
+    assert info.binned == 0
 
 
 def test_null_context_calls_fail_cleanly():
