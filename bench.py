@@ -3,22 +3,31 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mol4096]
                     [--no-cpu] [--no-baseline]
 
-A step is one pass of the forward hot path over one batch: input staging is
-done once (inputs resident in HBM), then each step runs the per-atom window
-bounds + 1-D factors, the per-plane accumulation and the dense write of the
-whole B x C x D x H x W grid (one persistent window-kernel launch, replayed
-from a captured HIP graph).  Rank 0 prints one JSON line on stdout; progress
-goes to stderr.
+A step is one pass of the forward hot path over one batch: inputs are
+staged in HBM once, then each step runs the per-atom window bounds and 1-D
+factors, the accumulation and the dense write of the whole B x C x D x H x W
+grid (for molecules one persistent window-kernel launch replayed from a
+captured HIP graph; for large periodic cells the binned path's four set-up
+kernels and one plane kernel, also replayed from a graph).  Rank 0 prints
+one JSON line on stdout; progress goes to stderr.
 
-Default workload: 4096 synthetic molecules of 5-29 atoms (H/C/N/O/F mix),
-32^3 x 5 channels at 0.5 A, bf16 output.  Beside it: the plain per-molecule
-fp32 baseline (one launch per molecule), the batched fp32 form, a torch fill
-of the same byte count (practical write ceiling) and the FP64 CPU oracle on a
-bounded sample of the same batch.
+Workloads (synth.WORKLOADS):
+  mol4096      (default, headline) 4096 molecules of 5-29 atoms, 32^3 x 5
+               channels at 0.5 A, bf16 output, beside the plain per-molecule
+               fp32 baseline (one launch per molecule), the batched fp32
+               form and a torch fill of the same byte count;
+  mol4096x48   4096 molecules of 5-60 atoms, 48^3 x 5 at 0.35 A, bf16;
+  crystal8     8 periodic 20 A cells of 2000-20000 atoms, 128^3 x 8 at
+               0.16 A: bf16 (MFMA plane kernel) beside the fp32 vector form;
+  adjoint1024  the coordinate gradient of 1024 molecules, 32^3 x 5 fp32
+               upstream.
+The FP64 CPU oracle is timed on a bounded sample of the same workload, one
+thread and a thread pool (the oracle releases the GIL).
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import hashlib
 import json
 import os
@@ -30,10 +39,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = ("grids/sec + HBM GB/s (32³×5ch, batch 4096): batched BF16 vs plain FP32")
+HEADLINE_METRIC = ("grids/sec + HBM GB/s (32³×5ch, batch 4096): batched BF16 vs plain FP32")
+METRICS = {
+    "mol4096": HEADLINE_METRIC,
+    "mol4096x48": "grids/sec + HBM GB/s (48³×5ch, batch 4096, 5-60 atoms): batched BF16",
+    "crystal8": "grids/sec + HBM GB/s (128³×8ch periodic cells, batch 8): BF16 MFMA vs FP32 window",
+    "adjoint1024": "grids/sec (adjoint dL/dxyz, 32³×5ch FP32 upstream, batch 1024)",
+}
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
 WINDOW_SOURCES = ("paper_2211_08506_amd/csrc/pg_window.hip", "paper_2211_08506_amd/csrc/pg_device.hpp",
                   "paper_2211_08506_amd/csrc/pg_params.hpp")
+CPU_THREADS_MAX = 16
 
 
 def log(*a):
@@ -64,8 +81,9 @@ def measured_traffic(kernel_key: str, digest: str):
 
 
 def timed_steps(fn, steps, warmup, torch, stream):
-    """Run warmup + timed steps; return (wall ms/step, mean event ms/step,
-    per-step event ms list)."""
+    """Run warmup + timed steps bracketed by synchronisations; each step is
+    also bracketed by events on the launch stream.  Returns wall ms/step and
+    event statistics (mean, median, p10, p90 in ms)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -78,8 +96,89 @@ def timed_steps(fn, steps, warmup, torch, stream):
         e1.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    per = [e0.elapsed_time(e1) for e0, e1 in evs]
-    return wall, float(np.mean(per)), per
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    return wall, {"mean": float(per.mean()), "median": float(np.median(per)),
+                  "p10": float(np.percentile(per, 10)), "p90": float(np.percentile(per, 90))}
+
+
+def axis_windows(b, wl):
+    """Per atom and axis, the voxel index ranges of the cutoff window
+    (nearest images included when periodic), evaluated in float64: a
+    measurement aid for eval counts and dense-contraction sizes (edge voxels
+    may differ from the exact decision the kernels take)."""
+    o = np.asarray(wl.origin, np.float64)
+    h = float(wl.spacing)
+    dims_xyz = (wl.dims[2], wl.dims[1], wl.dims[0])
+    rc = (np.float32(wl.cutoff_k) * wl.sigma().astype(np.float32)).astype(np.float64)[b.types]
+    mu = b.xyz.astype(np.float64)
+    images = (-1, 0, 1) if wl.periodic else (0,)
+    ranges = []
+    for q in range(3):
+        rq = []
+        for n in images:
+            c = mu[:, q] + n * (wl.cell or 0.0) - o[q]
+            lo = np.maximum(np.ceil((c - rc) / h - 0.5), 0).astype(np.int64)
+            hi = np.minimum(np.floor((c + rc) / h - 0.5), dims_xyz[q] - 1).astype(np.int64)
+            rq.append((lo, hi))
+        ranges.append(rq)
+    return ranges
+
+
+def window_evals(b, wl) -> int:
+    """Atom-voxel evaluations of one pass: sum over atoms of window sizes."""
+    cnt = []
+    for rq in axis_windows(b, wl):
+        cnt.append(sum(np.maximum(hi - lo + 1, 0) for lo, hi in rq))
+    return int(np.sum(cnt[0] * cnt[1] * cnt[2]))
+
+
+def mfma_dense_flops(b, wl) -> int:
+    """Dense MFMA flops of the binned plane kernel: per (structure, channel,
+    z) bin, 2 x (rows x cols padded to 128-voxel super-tiles) x (bin size
+    padded to the 32-atom step)."""
+    D, H, W = wl.dims
+    mol = np.searchsorted(b.offsets, np.arange(b.n_atoms), side="right") - 1
+    bins = np.zeros((b.n_mol, wl.n_types, D), np.int64)
+    for lo, hi in axis_windows(b, wl)[2]:
+        n = np.maximum(hi - lo + 1, 0)
+        a = np.repeat(np.arange(b.n_atoms), n)
+        z = np.concatenate([np.arange(l, h + 1) for l, h in zip(lo, hi) if h >= l]) \
+            if n.sum() else np.zeros(0, np.int64)
+        np.add.at(bins, (mol[a], b.types[a], z), 1)
+    k_pad = ((bins + 31) // 32) * 32
+    tiles = ((H + 127) // 128) * ((W + 127) // 128)
+    return int(2 * 128 * 128 * tiles * k_pad.sum())
+
+
+def cpu_oracle_baseline(units, run_one, seconds, describe):
+    """Time the FP64 oracle on a bounded sample: run_one(unit) computes the
+    grids of one unit (a chunk of structures, as one oracle call) and returns
+    how many; units are taken cycling through the list, first on one thread,
+    then on a pool of threads (the oracle's C entry points release the GIL).
+    """
+    t0 = time.perf_counter()
+    n1 = i = 0
+    while time.perf_counter() - t0 < seconds * 0.6 or i < 1:
+        n1 += run_one(units[i % len(units)])
+        i += 1
+    dt1 = time.perf_counter() - t0
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    P = max(1, min(CPU_THREADS_MAX, avail))
+    nP = i = 0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(P) as ex:
+        while time.perf_counter() - t0 < seconds * 0.4 or i < P:
+            nP += sum(ex.map(run_one, [units[(i + j) % len(units)] for j in range(P)]))
+            i += P
+    dtP = time.perf_counter() - t0
+    log(f"[bench] oracle: 1 thread {n1} grids in {dt1:.1f} s; {P} threads {nP} in {dtP:.1f} s")
+    return {"value": n1 / dt1, "unit": "grids/s", "cores": 1, "kind": "oracle",
+            "sample": describe(n1, dt1, 1),
+            "threads": {"value": nP / dtP, "unit": "grids/s", "cores": P,
+                        "sample": describe(nP, dtP, P)}}
 
 
 def main():
@@ -87,10 +186,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="mol4096")
+    ap.add_argument("--workload", default="mol4096", choices=sorted(METRICS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain fp32 baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the shipped tuning table only (for profiler runs)")
     ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
@@ -102,8 +201,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "molecule batches shard across GPUs without communication, see the design notes",
-              file=sys.stderr)
+              "batches shard across GPUs by structure without communication (see the design "
+              "notes), and no multi-GPU figure is produced", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -126,101 +225,173 @@ def main():
     C = wl.n_types
     D, H, W = wl.dims
     vox = C * D * H * W
+    in_bytes = 16 * b.n_atoms + 4 * (B + 1)
+    evals = window_evals(b, wl)
+    log(f"[bench] {b.n_atoms} atoms, {evals} atom-voxel evaluations per pass")
 
     ctx = pg.Context(0, tuning=args.tuning or "shipped")
-    out_dt = torch.bfloat16 if wl.out_dtype == "bf16" else torch.float32
-    esize = 2 if out_dt == torch.bfloat16 else 4
-    desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k,
-                        wl.cell, out_dt, "window")
-    out = pg.empty_grid(desc, B, dev)
-
-    if not args.no_autotune:
-        log("[bench] autotuning the window kernel")
-        ctx.autotune(desc, bv, out, reps=3)
-    plan = ctx.plan(desc, bv, out)
-    log(f"[bench] plan {plan}")
     ctx.set_option(pg.PG_OPT_GRAPH, 0 if args.no_graph else 1)
-
-    def step():
-        ctx.forward(desc, bv, out, stream)
-
-    log(f"[bench] timing {args.steps} steps after {args.warmup} warmup")
-    wall_ms, ev_ms, per = timed_steps(step, args.steps, args.warmup, torch, stream)
-    grids_s = B / (wall_ms / 1e3)
-    out_bytes = B * vox * esize
-    in_bytes = 16 * b.n_atoms + 4 * (B + 1)
-    alg_bytes = out_bytes + in_bytes
-    achieved = alg_bytes / (ev_ms / 1e3) / 1e9
-    log(f"[bench] window {wl.out_dtype}: {wall_ms:.3f} ms/step wall, {ev_ms:.3f} ms/launch "
-        f"(events), {grids_s / 1e6:.2f} M grids/s, {achieved:.0f} GB/s")
-
-    # parity of the timed output on sampled voxels (oracle evaluates them one by one)
-    import oracle
-    rng = np.random.default_rng(123)
-    idx = synth.sample_voxel_indices(rng, b, (B, C, D, H, W), wl.origin, wl.spacing, 4000, 4000)
-    ref = oracle.voxels_fp64(b.xyz, b.types, b.offsets, sig, wl.dims, wl.spacing, idx, wl.origin,
-                             cutoff_k=wl.cutoff_k)
-    it = torch.tensor(idx, device=dev)
-    got = out[it[:, 0], it[:, 1], it[:, 2], it[:, 3], it[:, 4]].double().cpu().numpy()
-    rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    max_abs = float(np.max(np.abs(got - ref)))
-    log(f"[bench] sampled parity vs FP64 oracle: rel-L2 {rel_l2:.3e} max-abs {max_abs:.3e}")
-
-    # practical write ceiling: torch fill of the same byte count
-    fill_buf = out.view(torch.uint8).view(-1)
-    fill_wall, fill_ms, _ = timed_steps(lambda: fill_buf.fill_(0), 10, 3, torch, stream)
-    fill_gbs = out_bytes / (fill_ms / 1e3) / 1e9
-    log(f"[bench] torch fill of {out_bytes / 1e9:.2f} GB: {fill_ms:.3f} ms, {fill_gbs:.0f} GB/s")
-
+    launch = "direct launch" if args.no_graph else "HIP graph"
     extra = {}
-    # batched fp32 (same form, fp32 output)
-    desc32 = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
-                          torch.float32, "window")
-    out32 = pg.empty_grid(desc32, B, dev)
-    if not args.no_autotune:
-        ctx.autotune(desc32, bv, out32, reps=3)
-    if args.save_tuning:
-        ctx.tuning_save(args.save_tuning)
-    w32, e32, _ = timed_steps(lambda: ctx.forward(desc32, bv, out32, stream),
-                              max(5, args.steps // 5), 2, torch, stream)
-    extra["batched_fp32"] = {"grids_per_s": B / (w32 / 1e3), "ms_per_step": w32,
-                             "hbm_gbs": (B * vox * 4 + in_bytes) / (e32 / 1e3) / 1e9}
-    log(f"[bench] window fp32: {w32:.3f} ms/step, {B / (w32 / 1e3) / 1e6:.2f} M grids/s")
-    del out32
+    rec = {"metric": METRICS[wl.name], "unit": "grids/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
 
-    if not args.no_baseline:
-        descp = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
-                             torch.float32, "plain")
-        outp = pg.empty_grid(descp, B, dev)
-        ctx_p = pg.Context(0)
-        wp, ep, _ = timed_steps(lambda: ctx_p.forward(descp, bv, outp, stream), 3, 1, torch,
-                                stream)
-        extra["baseline_plain_fp32"] = {
-            "grids_per_s": B / (wp / 1e3), "ms_per_step": wp, "launches_per_step": B + 1,
-            "hbm_gbs": (B * vox * 4 + in_bytes) / (ep / 1e3) / 1e9}
-        log(f"[bench] plain fp32 per-molecule launches: {wp:.2f} ms/step, "
-            f"{B / (wp / 1e3) / 1e6:.3f} M grids/s")
-        del outp
+    def forward_case(out_dt, form, autotune, steps, warmup):
+        desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
+                            out_dt, form)
+        out = pg.empty_grid(desc, B, dev)
+        if autotune and not args.no_autotune:
+            log(f"[bench] autotuning {form} {out_dt}")
+            ctx.autotune(desc, bv, out, reps=3)
+        plan = ctx.plan(desc, bv, out)
+        wall, ev = timed_steps(lambda: ctx.forward(desc, bv, out, stream), steps, warmup,
+                               torch, stream)
+        esz = 2 if out_dt == torch.bfloat16 else 4
+        alg = B * vox * esz + in_bytes
+        res = {"plan": plan, "ms_per_step": wall, "launch_ms": ev, "grids_per_s": B / (wall / 1e3),
+               "alg_bytes": alg, "hbm_gbs": alg / (ev["mean"] / 1e3) / 1e9,
+               "evals_per_s": evals / (ev["mean"] / 1e3)}
+        log(f"[bench] {form} {out_dt} plan {plan}")
+        log(f"[bench]   {wall:.3f} ms/step wall, {ev['mean']:.3f} ms/step (events, median "
+            f"{ev['median']:.3f}), {res['grids_per_s'] / 1e6:.3f} M grids/s, "
+            f"{res['hbm_gbs']:.0f} GB/s algorithmic")
+        return desc, out, res
+
+    if wl.name == "adjoint1024":
+        desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
+                            torch.float32, "auto")
+        U = torch.tensor(synth.upstream(wl.upstream_seed, wl.grid_shape()), device=dev)
+        gxyz = torch.empty_like(xyz)
+        wall, ev = timed_steps(lambda: ctx.backward(desc, bv, U, gxyz, stream), args.steps,
+                               args.warmup, torch, stream)
+        # algorithmic bytes: the upstream values inside every window, the
+        # inputs, and the gradient written
+        alg = evals * 4 + in_bytes + 12 * b.n_atoms
+        achieved = alg / (ev["mean"] / 1e3) / 1e9
+        log(f"[bench] adjoint: {wall:.3f} ms/step wall, {ev['mean']:.3f} ms (events), "
+            f"{B / (wall / 1e3) / 1e6:.3f} M grids/s, {achieved:.0f} GB/s algorithmic")
+        rec.update({"value": B / (wall / 1e3), "ms_per_step": wall, "dtype": "f32",
+                    "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                                 "traffic": None, "kernel": "adjoint_kernel<float>",
+                                 "algorithmic_bytes_per_launch": alg, "launch_ms": ev},
+                    "evals_per_s": evals / (ev["mean"] / 1e3),
+                    "upstream_bytes_read_dense": B * vox * 4})
+        kind = "adjoint"
+    else:
+        out_dt = torch.bfloat16 if wl.out_dtype == "bf16" or wl.kind == "crystal" else torch.float32
+        desc, out, main_res = forward_case(out_dt, "auto", True, args.steps, args.warmup)
+        esize = 2 if out_dt == torch.bfloat16 else 4
+        achieved = main_res["hbm_gbs"]
+        plan = main_res["plan"]
+        # practical write ceiling: torch fill of the same byte count
+        fill_buf = out.view(torch.uint8).view(-1)
+        _, fill_ev = timed_steps(lambda: fill_buf.fill_(0), 10, 3, torch, stream)
+        fill_gbs = B * vox * esize / (fill_ev["mean"] / 1e3) / 1e9
+        log(f"[bench] torch fill of {B * vox * esize / 1e9:.2f} GB: {fill_ev['mean']:.3f} ms, "
+            f"{fill_gbs:.0f} GB/s")
+        del out
+        if wl.kind == "crystal":
+            kname = f"binned path: prep+scan+fill+cr_{plan['form']}_kernel (whole step)"
+            flops = mfma_dense_flops(b, wl)
+            extra["mfma_dense_tflops"] = (flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
+                                          if plan["form"] == "mfma" else None)
+            extra["mfma_dense_flops_per_step"] = flops
+            # the other form / dtype pairs, for the per-shape decision
+            for form, dt in (("mfma", torch.bfloat16), ("window", torch.float32),
+                             ("window", torch.bfloat16), ("mfma", torch.float32)):
+                if form == plan["form"] and dt == out_dt:
+                    continue
+                _, o2, r2 = forward_case(dt, form, False, max(5, args.steps // 2), 2)
+                extra[f"{form}_{'bf16' if dt == torch.bfloat16 else 'fp32'}"] = {
+                    k: r2[k] for k in ("ms_per_step", "launch_ms", "grids_per_s", "hbm_gbs",
+                                       "evals_per_s")}
+                del o2
+        else:
+            kname = (f"window_mol_kernel<{'bf16' if esize == 2 else 'float'},"
+                     f"{plan['vec']},{plan['unroll']}>")
+        if wl.name == "mol4096":
+            _, o32, r32 = forward_case(torch.float32, "auto", True, max(5, args.steps // 5), 2)
+            extra["batched_fp32"] = {k: r32[k] for k in ("ms_per_step", "launch_ms",
+                                                         "grids_per_s", "hbm_gbs")}
+            del o32
+            if not args.no_baseline:
+                ctx_p = pg.Context(0)
+                descp = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k,
+                                     wl.cell, torch.float32, "plain")
+                outp = pg.empty_grid(descp, B, dev)
+                wp, ep = timed_steps(lambda: ctx_p.forward(descp, bv, outp, stream), 3, 1, torch,
+                                     stream)
+                extra["baseline_plain_fp32"] = {
+                    "grids_per_s": B / (wp / 1e3), "ms_per_step": wp, "launches_per_step": B + 1,
+                    "hbm_gbs": (B * vox * 4 + in_bytes) / (ep["mean"] / 1e3) / 1e9}
+                log(f"[bench] plain fp32 per-molecule launches: {wp:.2f} ms/step, "
+                    f"{B / (wp / 1e3) / 1e6:.3f} M grids/s")
+                del outp
+        if args.save_tuning:
+            ctx.tuning_save(args.save_tuning)
+        traffic = None
+        if wl.kind != "crystal":
+            traffic = measured_traffic(f"window_{wl.name}_{'bf16' if esize == 2 else 'f32'}",
+                                       source_digest(WINDOW_SOURCES))
+        rec.update({
+            "value": main_res["grids_per_s"], "ms_per_step": main_res["ms_per_step"],
+            "dtype": "bf16" if esize == 2 else "f32",
+            "hbm_gbs": achieved,
+            "evals_per_s": main_res["evals_per_s"],
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                         "kernel": kname, "algorithmic_bytes_per_launch": main_res["alg_bytes"],
+                         "launch_ms": main_res["launch_ms"]},
+            "fill_gbs_same_bytes": fill_gbs,
+            "frac_of_fill": achieved / fill_gbs,
+        })
+        kind = "forward"
+
+    if wl.kind == "crystal":
+        desc_w = (f"{wl.name}: {B} periodic {wl.cell:g} A cubic cells of "
+                  f"{min(b.counts())}-{max(b.counts())} atoms (uniform positions, {C} types uniform)")
+    else:
+        desc_w = (f"{wl.name}: {B} molecules of {wl.atoms[0]}-{wl.atoms[1]} atoms "
+                  f"(H/C/N/O/F p=0.5/0.3/0.1/0.08/0.02, {wl.box:g} A box)")
+    rec["config"] = {"workload": f"{desc_w}, {C}x{D}x{H}x{W} grid at {wl.spacing} A, cutoff "
+                                 f"{wl.cutoff_k:g} sigma, {kind}, {launch}",
+                     "batch": B, "grid": [C, D, H, W], "n_atoms": int(b.n_atoms),
+                     "evals_per_pass": evals}
+    if kind == "forward":
+        rec["config"]["plan"] = plan
 
     cpu = None
     if not args.no_cpu:
+        # the CPU baseline leg: the FP64 oracle (test infrastructure) on the
+        # same structures, one structure per call
+        import oracle as cpu_oracle
+        chunk = 1 if wl.kind == "crystal" else 16
+        units = [(m, b.subset(range(m, min(B, m + chunk)))) for m in range(0, B, chunk)]
+        if kind == "adjoint":
+            Uh = synth.upstream(wl.upstream_seed, wl.grid_shape())
+
+            def run_one(u):
+                m, s = u
+                cpu_oracle.grad_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
+                                     Uh[m:m + s.n_mol], wl.origin, cutoff_k=wl.cutoff_k)
+                return s.n_mol
+        else:
+            def run_one(u):
+                s = u[1]
+                cpu_oracle.grid_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
+                                     wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell)
+                return s.n_mol
+        cpu_units = units
         log(f"[bench] FP64 CPU oracle on a bounded sample (~{args.cpu_seconds:.0f} s)")
-        singles = [b.subset([m]) for m in range(B)]
-        t0 = time.perf_counter()
-        n_done = 0
-        # the batch's molecules one per call, cycling through the batch until
-        # the time budget is spent (at least one pass if it finishes sooner)
-        while time.perf_counter() - t0 < args.cpu_seconds or n_done < min(B, 64):
-            s = singles[n_done % B]
-            oracle.grid_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing, wl.origin,
-                             cutoff_k=wl.cutoff_k, cell=wl.cell)
-            n_done += 1
-        dt = time.perf_counter() - t0
-        cpu = {"value": n_done / dt, "unit": "grids/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n_done} grids = the {B}-molecule batch cycled one molecule per "
-                         f"call ({n_done / B:.1f} passes), dense FP64 {C}x{D}x{H}x{W} grid, "
-                         f"single thread, {dt:.1f} s"}
-        log(f"[bench] oracle: {n_done} grids in {dt:.1f} s = {n_done / dt:.1f} grids/s")
+        per_unit = "cell" if wl.kind == "crystal" else "molecule"
+        cpu = cpu_oracle_baseline(
+            cpu_units, run_one, args.cpu_seconds,
+            lambda n, dt, P: (f"{n} {kind} grids of the {B}-structure batch, {chunk} {per_unit}"
+                              f"(s) per oracle call cycling through the batch ({n / B:.2f} "
+                              f"passes), dense FP64 {C}x{D}x{H}x{W}, {P} thread(s), {dt:.1f} s"))
+    rec["cpu_baseline"] = cpu
 
     if args.calibrate_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
@@ -232,40 +403,6 @@ def main():
         del src, dst
         log("[bench] calibration copy: 3 x 1 GiB")
 
-    digest = source_digest(WINDOW_SOURCES)
-    traffic = measured_traffic(f"window_{wl.name}_{wl.out_dtype}", digest)
-    rec = {
-        "metric": METRIC,
-        "value": grids_s,
-        "unit": "grids/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall_ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": wl.out_dtype,
-        "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {B} molecules of {wl.atoms[0]}-{wl.atoms[1]} atoms "
-                               f"(H/C/N/O/F p=0.5/0.3/0.1/0.08/0.02, {wl.box:g} A box), "
-                               f"{C}x{D}x{H}x{W} grid at {wl.spacing} A, cutoff {wl.cutoff_k:g} "
-                               f"sigma, {wl.out_dtype} out, window form, "
-                               f"{'direct launch' if args.no_graph else 'HIP graph'}",
-                   "batch": B, "grid": [C, D, H, W], "n_atoms": int(b.n_atoms),
-                   "plan": plan},
-        "hbm_gbs": achieved,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic,
-                     "kernel": "window_mol_kernel<bf16,8>" if esize == 2 else "window_mol_kernel<f32,4>",
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "launch_ms": ev_ms},
-        "fill_gbs_same_bytes": fill_gbs,
-        "frac_of_fill": achieved / fill_gbs,
-        "parity_sampled": {"rel_l2": rel_l2, "max_abs": max_abs, "samples": int(len(idx))},
-        "cpu_baseline": cpu,
-    }
     rec.update(extra)
     print(json.dumps(rec), flush=True)
 

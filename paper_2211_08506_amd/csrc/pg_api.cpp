@@ -163,15 +163,18 @@ struct Plan {
     int bin_cap = 0;
     size_t lds = 0;           // dynamic LDS bytes of one workgroup
     size_t ws = 0;            // workspace bytes
-    size_t ws_counts = 0, ws_offsets = 0, ws_cursor = 0, ws_list = 0;  // crystal layout
+    // binned-path workspace layout (byte offsets) and sizes
+    size_t ws_fac = 0, ws_bcount = 0, ws_mcount = 0, ws_mstart = 0, ws_list = 0;
+    int fstride = 0, nblk = 0;
 };
 
-constexpr int kCrystalBinCap = 4096;   // atoms one plane kernel sorts in LDS
+constexpr int kCrystalBinCap = 4096;   // atoms of one plane the plane kernel stages in LDS
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Crystal path: workspace layout (per-atom records | bin counts | bin
-// offsets | fill cursors | bin lists) and the plane kernel's LDS.
+// Binned path: workspace layout (window records | factor values | per-block
+// channel counts | per-structure channel counts | their scan | channel
+// partition list) and the plane kernel's LDS.
 int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, int form, Plan &P)
 {
     if (b->spacings)
@@ -185,22 +188,35 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
     const int max_lds = ctx ? ctx->max_lds : 65536;
     if (P.lds > (size_t)max_lds)
         return PG_E_UNSUPPORTED;
+    if (d->D > 32767)   // z ranges are packed as 16-bit values
+        return PG_E_UNSUPPORTED;
     float rc_max = 0.f;
     for (int c = 0; c < d->C; ++c)
         rc_max = std::max(rc_max, rc_of(d, c));
+    // factor values per atom and axis: all window ranges of one atom,
+    // concatenated (at most one window per image, each at most
+    // floor(2 rc / h) + 1 voxels, and never more than the axis)
     const long long imgs = d->periodic ? 3 : 1;
-    long long zmax = d->D;
-    if (d->cutoff_k > 0.f)
-        zmax = std::min<long long>(d->D, imgs * ((long long)std::ceil(2.0 * rc_max / d->spacing[2]) + 2));
-    const long long nb = (long long)b->n_mol * d->C * d->D;
-    const long long entries = b->n_atoms * zmax;
-    if (entries > 0xffffffffLL || nb + 1 > 0xffffffffLL)
+    const int dims[3] = {d->W, d->H, d->D};
+    long long S = 1;
+    for (int q = 0; q < 3; ++q) {
+        long long sq = dims[q];
+        if (d->cutoff_k > 0.f)
+            sq = std::min<long long>(sq, imgs * ((long long)std::ceil(2.0 * rc_max / d->spacing[q]) + 2));
+        S = std::max(S, sq);
+    }
+    const long long nmc = (long long)b->n_mol * d->C;
+    if (b->n_atoms * 3 * S > 0x3fffffffffLL || nmc > 0x7fffffffLL)
         return PG_E_SHAPE;
-    P.ws_counts = align256((size_t)b->n_atoms * sizeof(AtomWindow));
-    P.ws_offsets = P.ws_counts + align256((size_t)nb * 4);
-    P.ws_cursor = P.ws_offsets + align256((size_t)(nb + 1) * 4);
-    P.ws_list = P.ws_cursor + align256((size_t)nb * 4);
-    P.ws = P.ws_list + align256((size_t)std::max<long long>(entries, 1) * 4);
+    P.fstride = (int)S;
+    P.nblk = crystal_prep_blocks(b->n_atoms);
+    P.ws_fac = align256((size_t)b->n_atoms * sizeof(AtomWindow));
+    P.ws_bcount = P.ws_fac + align256((size_t)b->n_atoms * 3 * S * sizeof(float));
+    P.ws_mcount = P.ws_bcount + align256((size_t)d->C * P.nblk * 4);
+    P.ws_mstart = P.ws_mcount + align256((size_t)nmc * 4);
+    P.ws_list = P.ws_mstart + align256((size_t)nmc * 4);
+    P.ws = P.ws_list + align256((size_t)std::max<long long>(b->n_atoms, 1) * sizeof(ListEntry));
+    const long long nb = nmc * d->D;
     P.block = 256;
     P.vec = 1;
     const long long blocks = form == PG_FORM_MFMA ? nb * ((d->H + 127) / 128) * ((d->W + 127) / 128) : nb;
@@ -380,10 +396,13 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         unsigned char *ws = (unsigned char *)p.ws;
         CrystalParams q;
         q.table = (AtomWindow *)ws;
-        q.counts = (uint32_t *)(ws + P.ws_counts);
-        q.offsets = (uint32_t *)(ws + P.ws_offsets);
-        q.cursor = (uint32_t *)(ws + P.ws_cursor);
-        q.list = (int32_t *)(ws + P.ws_list);
+        q.fac = (float *)(ws + P.ws_fac);
+        q.bcount = (uint32_t *)(ws + P.ws_bcount);
+        q.mcount = (uint32_t *)(ws + P.ws_mcount);
+        q.mstart = (uint32_t *)(ws + P.ws_mstart);
+        q.list = (ListEntry *)(ws + P.ws_list);
+        q.fstride = P.fstride;
+        q.nblk = P.nblk;
         q.bin_cap = P.bin_cap;
         return launch_crystal(p, q, P.form, d->out_dtype, P.lds, s);
     }

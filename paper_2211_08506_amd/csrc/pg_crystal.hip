@@ -1,32 +1,37 @@
-// pg_crystal.hip -- large / dense structures (periodic crystal cells) on gfx950.
+// pg_crystal.hip -- large / dense structures (periodic crystal cells, big
+// clusters) on gfx950.
 //
 // Structures with more atoms than the molecule window kernel stages in LDS
-// take this path.  Set-up, all on the GPU:
-//   prep:  one thread per atom: exact per-axis window ranges (nearest
-//          periodic images included) into a per-atom record, and a count of
-//          the atom in every (structure, channel, z) plane bin its z-window
-//          covers;
-//   scan:  exclusive prefix sum of the bin counts (one workgroup);
-//   fill:  one thread per atom appends the atom index to each of its bins.
-// Then one of two plane kernels, one workgroup per (structure, channel, z
-// plane[, 128 x 128 super-tile]); each first sorts its bin by atom index so
-// that every voxel's sum runs over atoms in index order (bitwise
-// reproducible results whatever order the fill's atomics produced):
-//   mfma:   the plane is a contraction over the bin's atoms of two factor
-//           matrices (separability of the Gaussian and of the cube cutoff,
-//           §III-A / §IV-C):  G[y][x] = sum_k A[y][k] B[k][x] with
-//           A[y][k] = phi_z^k(z) phi_y^k(y) built in FP32 and rounded once
-//           to bf16, B[k][x] = phi_x^k(x) in bf16; 32 atoms per step on
-//           v_mfma_f32_32x32x16_bf16 with FP32 accumulation;
+// take this path.  Set-up, all on the GPU and free of order-dependent
+// atomics in anything that reaches the output:
+//   prep:   one thread per atom: exact per-axis window ranges (nearest
+//           periodic images included) into the atom's record, the 1-D
+//           factors of every voxel index inside them (once per atom, ranges
+//           concatenated), and counts of the atom per (channel, structure)
+//           and per (channel, prep block);
+//   scan:   exclusive scans of both count arrays in channel-major order;
+//   place:  a stable partition of all atoms by channel (ballot ranks within
+//           a block): channel c's atoms in index order, so each (structure,
+//           channel) pair is one contiguous run of the list.
+// Then one plane kernel, one workgroup per (structure, channel, z plane
+// [, 128 x 128 super-tile]).  It compacts, in list order, the atoms of its
+// run whose z window holds the plane, so every voxel sums its atoms in
+// atom-index order (bitwise reproducible), then contracts over them:
+//   mfma:   the plane is a product of two factor matrices (separability of
+//           the Gaussian and of the cube cutoff, Sec. III-A / IV-C):
+//           G[y][x] = sum_k A[y][k] B[k][x], A[y][k] = phi_z^k(z) phi_y^k(y)
+//           formed in FP32 and rounded once to bf16, B[k][x] = phi_x^k(x) in
+//           bf16; 32 atoms per step on v_mfma_f32_32x32x16_bf16, FP32
+//           accumulation;
 //   window: the same sum in FP32 on the vector ALUs -- per 32-atom step the
 //           atoms' dense factor rows go to LDS, and each lane accumulates
-//           its four 16-voxel row runs over the atoms whose y-window holds
-//           the row.
+//           its 16-voxel row runs over the atoms whose y window holds the row.
 #include "pg_device.hpp"
 #include "pg_launch.hpp"
 
 namespace pg {
 
+constexpr int PREP_BLOCK = 256; // atoms per prep / place block (4 waves)
 constexpr int KC = 32;          // atoms per contraction step
 constexpr int ST = 128;         // MFMA super-tile edge (y and x)
 constexpr int KPAD = KC + 8;    // bf16 row pitch of the LDS operand tiles
@@ -38,42 +43,58 @@ __global__ void cr_clear_kernel(uint32_t *a, long long n)
         a[i] = 0u;
 }
 
-// z planes of one record: calls f(z) once per plane of the window(s)
-template <typename F>
-__device__ __forceinline__ void for_each_z(const AtomWindow &w, F f)
+__global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, CrystalParams q)
 {
-    for (int r = 0; r < w.n[2]; ++r)
-        for (int z = w.lo[2][r]; z <= w.hi[2][r]; ++z)
-            f(z);
+    __shared__ uint32_t cnt[PG_MAX_CHANNELS];
+    const int tid = threadIdx.x;
+    for (int c = tid; c < p.C; c += PREP_BLOCK)
+        cnt[c] = 0u;
+    __syncthreads();
+    const long long a = (long long)blockIdx.x * PREP_BLOCK + tid;
+    if (a < p.n_atoms) {
+        AtomWindow *w = q.table + a;
+        const int m = write_atom_window(p, a, w);
+        const int t = w->type;
+        if (t >= 0) {
+            const float inv2s2 = p.inv2s2[t];
+            const int S = q.fstride;
+            for (int ax = 0; ax < 3; ++ax) {
+                float *f = q.fac + ((size_t)a * 3 + ax) * S;
+                const float h = p.h[ax];
+                int j = 0;
+                for (int r = 0; r < w->n[ax]; ++r) {
+                    const float bh = w->bh[ax][r], bl = w->bl[ax][r];
+                    for (int i = w->lo[ax][r]; i <= w->hi[ax][r] && j < S; ++i, ++j)
+                        f[j] = gauss1d(offset_at(bh, bl, h, i), inv2s2);
+                }
+            }
+            atomicAdd(&cnt[t], 1u);
+            atomicAdd(&q.mcount[(size_t)t * p.n_mol + m], 1u);
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < p.C; c += PREP_BLOCK)
+        q.bcount[(size_t)c * q.nblk + blockIdx.x] = cnt[c];
 }
 
-__global__ void __launch_bounds__(256) cr_prep_kernel(GridParams p, CrystalParams q)
-{
-    const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= p.n_atoms)
-        return;
-    const int m = write_atom_window(p, a, q.table + a);
-    const AtomWindow &w = q.table[a];
-    if (w.type < 0)
-        return;
-    const size_t base = ((size_t)m * p.C + w.type) * p.D;
-    for_each_z(w, [&](int z) { atomicAdd(&q.counts[base + z], 1u); });
-}
-
-// Exclusive scan of n counts into offsets[0..n]; cursor[] cleared.  One
-// workgroup of 1024 threads, each owning a contiguous segment.
-__global__ void __launch_bounds__(1024) cr_scan_kernel(CrystalParams q, long long n)
+// Exclusive scan of n counts, in place (workgroup 0: the per-block counts)
+// or into mstart (workgroup 1: the per-structure counts).  One workgroup
+// of 1024 threads per array, each thread owning a contiguous segment.
+__global__ void __launch_bounds__(1024) cr_scan_kernel(CrystalParams q, long long n_blk,
+                                                       long long n_mol)
 {
     __shared__ unsigned long long part[1024];
+    const uint32_t *in = blockIdx.x == 0 ? q.bcount : q.mcount;
+    uint32_t *out = blockIdx.x == 0 ? q.bcount : q.mstart;
+    const long long n = blockIdx.x == 0 ? n_blk : n_mol;
     const int t = threadIdx.x;
     const long long seg = (n + 1023) / 1024;
     const long long b = (long long)t * seg, e = min(n, b + seg);
     unsigned long long s = 0;
     for (long long i = b; i < e; ++i)
-        s += q.counts[i];
+        s += in[i];
     part[t] = s;
     __syncthreads();
-    // inclusive Hillis-Steele scan of the 1024 segment sums
     for (int d = 1; d < 1024; d <<= 1) {
         const unsigned long long v = t >= d ? part[t - d] : 0ull;
         __syncthreads();
@@ -82,62 +103,156 @@ __global__ void __launch_bounds__(1024) cr_scan_kernel(CrystalParams q, long lon
     }
     unsigned long long run = part[t] - s;
     for (long long i = b; i < e; ++i) {
-        q.offsets[i] = (uint32_t)run;
-        run += q.counts[i];
-        q.cursor[i] = 0u;
+        const uint32_t v = in[i];
+        out[i] = (uint32_t)run;
+        run += v;
     }
-    if (t == 1023)
-        q.offsets[n] = (uint32_t)part[1023];
 }
 
-__global__ void __launch_bounds__(256) cr_fill_kernel(GridParams p, CrystalParams q)
+__device__ __forceinline__ uint32_t pack_range(int lo, int hi)
 {
-    const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= p.n_atoms)
-        return;
-    const AtomWindow &w = q.table[a];
-    if (w.type < 0)
-        return;
-    const int m = structure_of(p.offsets, p.n_mol, a);
-    const size_t base = ((size_t)m * p.C + w.type) * p.D;
-    for_each_z(w, [&](int z) {
-        const size_t bin = base + z;
-        const uint32_t pos = atomicAdd(&q.cursor[bin], 1u);
-        q.list[q.offsets[bin] + pos] = (int32_t)a;
-    });
+    return (uint32_t)(uint16_t)(int16_t)lo | ((uint32_t)(uint16_t)(int16_t)hi << 16);
 }
 
-// Load a plane's bin into LDS and sort it ascending (bitonic, padded to a
-// power of two with INT_MAX).  Returns the count, or -1 if it exceeds cap.
-__device__ int load_sorted_bin(const CrystalParams &q, size_t bin, int32_t *ids, int cap)
+__global__ void __launch_bounds__(PREP_BLOCK) cr_place_kernel(GridParams p, CrystalParams q)
 {
-    const uint32_t start = q.offsets[bin];
-    const int cnt = (int)(q.offsets[bin + 1] - start);
-    if (cnt > cap)
-        return -1;
-    int np = 1;
-    while (np < cnt)
-        np <<= 1;
-    for (int i = threadIdx.x; i < np; i += blockDim.x)
-        ids[i] = i < cnt ? q.list[start + i] : 0x7fffffff;
+    __shared__ uint32_t wc[PREP_BLOCK / 64][PG_MAX_CHANNELS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long a = (long long)blockIdx.x * PREP_BLOCK + tid;
+    const int t = a < p.n_atoms ? q.table[a].type : -1;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    uint32_t rank = 0;
+    for (int c = 0; c < p.C; ++c) {
+        const unsigned long long mask = __ballot(t == c);
+        if (t == c)
+            rank = (uint32_t)__popcll(mask & below);
+        if (lane == 0)
+            wc[wave][c] = (uint32_t)__popcll(mask);
+    }
     __syncthreads();
-    for (int k = 2; k <= np; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < np; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const int32_t x = ids[i], y = ids[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        ids[i] = y;
-                        ids[l] = x;
+    if (t >= 0) {
+        uint32_t pos = q.bcount[(size_t)t * q.nblk + blockIdx.x] + rank;
+        for (int w = 0; w < wave; ++w)
+            pos += wc[w][t];
+        const AtomWindow &w = q.table[a];
+        ListEntry e;
+        e.atom = (int32_t)a;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            e.z[r] = r < w.n[2] ? pack_range(w.lo[2][r], w.hi[2][r]) : pack_range(0, -1);
+        q.list[pos] = e;
+    }
+}
+
+// XCD-aware workgroup order: the hardware deals consecutive workgroups to
+// the 8 XCDs in turn; remap so that each XCD runs a contiguous stretch of
+// planes (consecutive z of one structure and channel share their atoms'
+// factor rows in that XCD's L2).  A bijection on [0, gridDim.x).
+__device__ __forceinline__ long long xcd_block()
+{
+    const unsigned G = gridDim.x, full = G & ~7u, b = blockIdx.x;
+    return b < full ? (long long)(b & 7u) * (full >> 3) + (b >> 3) : (long long)b;
+}
+
+// Ordered compaction of the plane's atoms: the (m, c) run of the channel
+// partition filtered by "z window holds z", in list order, into ids[] with
+// each atom's z factor in gz[].  Returns the count, or -1 above cap (then
+// ids / gz hold a prefix only).  Uniform across the workgroup; contains
+// barriers (all threads must call it).
+__device__ int gather_plane(const GridParams &p, const CrystalParams &q, int m, int c, int z,
+                            int32_t *ids, float *gz, uint32_t *wsum)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const size_t mc = (size_t)c * p.n_mol + m;
+    const uint32_t start = q.mstart[mc], n = q.mcount[mc];
+    const int S = q.fstride, cap = q.bin_cap;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int cnt = 0;
+    for (uint32_t base = 0; base < n; base += blockDim.x) {
+        const uint32_t e = base + tid;
+        bool live = false;
+        int a = 0, jz = 0;
+        if (e < n) {
+            const ListEntry le = q.list[start + e];
+            a = le.atom;
+            int s = 0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int lo = (int16_t)(le.z[r] & 0xffffu), hi = (int16_t)(le.z[r] >> 16);
+                if (z >= lo && z <= hi) {
+                    live = true;
+                    jz = s + z - lo;
+                }
+                s += hi >= lo ? hi - lo + 1 : 0;
+            }
+        }
+        const unsigned long long mask = __ballot(live);
+        if (lane == 0)
+            wsum[wave] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        int off = cnt, total = 0;
+        for (int w = 0; w < nw; ++w) {
+            off += w < wave ? (int)wsum[w] : 0;
+            total += (int)wsum[w];
+        }
+        const int pos = off + __popcll(mask & below);
+        if (live && pos < cap) {
+            ids[pos] = a;
+            gz[pos] = jz < S ? q.fac[((size_t)a * 3 + 2) * S + jz] : 0.f;
+        }
+        cnt += total;
+        __syncthreads();
+    }
+    return cnt > cap ? -1 : cnt;
+}
+
+// x / y ranges of one step's atoms, staged in LDS: lo, hi, and the start of
+// each range in the atom's concatenated factor values.
+struct StepRec {
+    int32_t atom;
+    int32_t lo[2][3], hi[2][3], st[2][3];
+};
+
+__device__ __forceinline__ void stage_records(const CrystalParams &q, const int32_t *ids, int k0,
+                                              int kn, StepRec *recs)
+{
+    const int k = threadIdx.x;
+    if (k < KC) {
+        StepRec r;
+        r.atom = k < kn ? ids[k0 + k] : -1;
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            int s = 0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                int lo = 0, hi = -1;
+                if (r.atom >= 0) {
+                    const AtomWindow &w = q.table[r.atom];
+                    if (i < w.n[ax]) {
+                        lo = w.lo[ax][i];
+                        hi = w.hi[ax][i];
                     }
                 }
+                r.lo[ax][i] = lo;
+                r.hi[ax][i] = hi;
+                r.st[ax][i] = s - lo;
+                s += hi - lo + 1;
             }
-            __syncthreads();
         }
+        recs[k] = r;
     }
-    return cnt;
+}
+
+// Factor of the staged atom on axis ax at index v (0 outside its window).
+__device__ __forceinline__ float step_factor(const CrystalParams &q, const StepRec &r, int ax,
+                                             int v)
+{
+    int j = -1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (v >= r.lo[ax][i] && v <= r.hi[ax][i])
+            j = r.st[ax][i] + v;
+    return (j >= 0 && j < q.fstride) ? q.fac[((size_t)r.atom * 3 + ax) * q.fstride + j] : 0.f;
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -152,11 +267,13 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16 *At = (__bf16 *)smem;                          // [ST][KPAD]: A[y][k]
     __bf16 *Bt = At + ST * KPAD;                          // [ST][KPAD]: B[k][x] stored by x
-    AtomWindow *recs = (AtomWindow *)(Bt + ST * KPAD);    // [KC] records of the step
-    int32_t *ids = (int32_t *)(recs + KC);                // sorted bin
+    StepRec *recs = (StepRec *)(Bt + ST * KPAD);          // [KC]
+    uint32_t *wsum = (uint32_t *)(recs + KC);             // [4]
+    int32_t *ids = (int32_t *)(wsum + 4);                 // [bin_cap]
+    float *gzs = (float *)(ids + q.bin_cap);              // [bin_cap]
     const int C = p.C, D = p.D, H = p.H, W = p.W;
     const int nsx = (W + ST - 1) / ST, nsy = (H + ST - 1) / ST;
-    long long b = blockIdx.x;
+    long long b = xcd_block();
     const int sx = (int)(b % nsx);
     b /= nsx;
     const int sy = (int)(b % nsy);
@@ -167,15 +284,12 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
     const int m = (int)(b / C);
     const int y0 = sy * ST, x0 = sx * ST;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const size_t bin = ((size_t)m * C + c) * D + z;
 
-    const int cnt = load_sorted_bin(q, bin, ids, q.bin_cap);
+    const int cnt = gather_plane(p, q, m, c, z, ids, gzs, wsum);
     if (cnt < 0 && tid == 0 && sx == 0 && sy == 0)
         raise_error(p.err, PG_E_CAPACITY, m);
     const int nk = cnt < 0 ? 0 : cnt;
 
-    const float hx = p.h[0], hy = p.h[1], hz = p.h[2];
-    const float inv2s2 = p.inv2s2[c];
     f32x16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -187,32 +301,24 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
     const int qy = (wave >> 1) * 64, qx = (wave & 1) * 64;
 
     for (int k0 = 0; k0 < nk; k0 += KC) {
-        // ---- the step's atom records into LDS
-        {
-            const int words = (int)(sizeof(AtomWindow) / 4);
-            for (int e = tid; e < KC * words; e += blockDim.x) {
-                const int k = e / words, wd = e - k * words;
-                ((int32_t *)recs)[e] = k0 + k < nk ? ((const int32_t *)(q.table + ids[k0 + k]))[wd] : 0;
-            }
-        }
+        stage_records(q, ids, k0, min(KC, nk - k0), recs);
         __syncthreads();
-        // ---- operand columns of 32 atoms: 8 threads per atom, each 16 rows
-        // of A and 16 rows of B^T (every entry written, zeros included)
+        // operand columns of 32 atoms: 8 threads per atom, each 16 rows of A
+        // and 16 rows of B^T (every entry written, zeros included)
         {
             const int k = tid >> 3, part = tid & 7;
-            const bool live = k0 + k < nk;
-            const AtomWindow &w = recs[k];
-            const float gz = live ? record_factor(w, 2, z, hz, inv2s2) : 0.f;
+            const StepRec r = recs[k];
+            const float g = r.atom >= 0 ? gzs[k0 + k] : 0.f;
+#pragma unroll 4
             for (int i = part; i < ST; i += 8) {
-                const int y = y0 + i, x = x0 + i;
-                const float fy = (live && y < H) ? record_factor(w, 1, y, hy, inv2s2) : 0.f;
-                const float fx = (live && x < W) ? record_factor(w, 0, x, hx, inv2s2) : 0.f;
-                At[i * KPAD + k] = (__bf16)(gz * fy);
+                const float fy = r.atom >= 0 ? step_factor(q, r, 1, y0 + i) : 0.f;
+                const float fx = r.atom >= 0 ? step_factor(q, r, 0, x0 + i) : 0.f;
+                At[i * KPAD + k] = (__bf16)(g * fy);
                 Bt[i * KPAD + k] = (__bf16)fx;
             }
         }
         __syncthreads();
-        // ---- 2 k-steps of 16 on the wave's 2 x 2 tiles
+        // 2 k-steps of 16 on the wave's 2 x 2 tiles
 #pragma unroll
         for (int ks = 0; ks < KC; ks += 16) {
             const int kk = ks + 8 * (lane >> 5);
@@ -231,7 +337,7 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
         __syncthreads();
     }
 
-    // ---- store the quadrant: lane holds column (lane & 31) of rows
+    // store the quadrant: lane holds column (lane & 31) of rows
     // 8 (e / 4) + 4 (lane / 32) + e % 4 of each tile
     T *out = (T *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
 #pragma unroll
@@ -259,20 +365,20 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
     const int W16 = (W + 15) & ~15;
     float *gx = (float *)smem;                    // [KC][W16] phi_x
     float *gy = gx + KC * W16;                    // [KC][H]   phi_z(z) phi_y
-    int32_t *ids = (int32_t *)(gy + KC * H);
-    long long b = blockIdx.x;
+    StepRec *recs = (StepRec *)(gy + KC * ((H + 3) & ~3));
+    uint32_t *wsum = (uint32_t *)(recs + KC);
+    int32_t *ids = (int32_t *)(wsum + 4);
+    float *gzs = (float *)(ids + q.bin_cap);
+    long long b = xcd_block();
     const int z = (int)(b % D);
     b /= D;
     const int c = (int)(b % C);
     const int m = (int)(b / C);
     const int tid = threadIdx.x;
-    const size_t bin = ((size_t)m * C + c) * D + z;
-    const int cnt = load_sorted_bin(q, bin, ids, q.bin_cap);
+    const int cnt = gather_plane(p, q, m, c, z, ids, gzs, wsum);
     if (cnt < 0 && tid == 0)
         raise_error(p.err, PG_E_CAPACITY, m);
     const int nk = cnt < 0 ? 0 : cnt;
-    const float hx = p.h[0], hy = p.h[1], hz = p.h[2];
-    const float inv2s2 = p.inv2s2[c];
     const int runs_x = W16 / 16;
     const int n_runs = H * runs_x;
     float acc[RMAX][16];
@@ -284,15 +390,17 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
 
     for (int k0 = 0; k0 < nk; k0 += KC) {
         const int kn = min(KC, nk - k0);
+        stage_records(q, ids, k0, kn, recs);
+        __syncthreads();
         // dense factor rows of the step's atoms
         for (int e = tid; e < kn * (W16 + H); e += blockDim.x) {
             const int k = e / (W16 + H), j = e - k * (W16 + H);
-            const AtomWindow &w = q.table[ids[k0 + k]];
+            const StepRec &r = recs[k];
             if (j < W16) {
-                gx[k * W16 + j] = j < W ? record_factor(w, 0, j, hx, inv2s2) : 0.f;
+                gx[k * W16 + j] = j < W ? step_factor(q, r, 0, j) : 0.f;
             } else {
                 const int y = j - W16;
-                gy[k * H + y] = record_factor(w, 2, z, hz, inv2s2) * record_factor(w, 1, y, hy, inv2s2);
+                gy[k * H + y] = gzs[k0 + k] * step_factor(q, r, 1, y);
             }
         }
         __syncthreads();
@@ -337,11 +445,12 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
 
 size_t crystal_plane_lds(int form, int H, int W, int bin_cap)
 {
+    const size_t tail = (size_t)KC * sizeof(StepRec) + 4 * sizeof(uint32_t) +
+                        (size_t)bin_cap * (sizeof(int32_t) + sizeof(float));
     if (form == PG_FORM_MFMA)
-        return (size_t)2 * ST * KPAD * sizeof(__bf16) + (size_t)KC * sizeof(AtomWindow) +
-               (size_t)bin_cap * sizeof(int32_t);
+        return (size_t)2 * ST * KPAD * sizeof(__bf16) + tail;
     const int W16 = (W + 15) & ~15;
-    return (size_t)KC * (W16 + H) * sizeof(float) + (size_t)bin_cap * sizeof(int32_t);
+    return (size_t)KC * (W16 + ((H + 3) & ~3)) * sizeof(float) + tail;
 }
 
 // runs of 16 voxels per lane of the vector form (0: plane too large)
@@ -354,29 +463,37 @@ int crystal_window_runs(int H, int W)
     return 0;
 }
 
+int crystal_prep_blocks(long long n_atoms)
+{
+    return (int)((n_atoms + PREP_BLOCK - 1) / PREP_BLOCK);
+}
+
 hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form, int out_dtype,
                           size_t lds, hipStream_t s)
 {
     if (p.n_mol == 0)
         return hipSuccess;
-    const long long nb = (long long)p.n_mol * p.C * p.D;
-    hipLaunchKernelGGL(cr_clear_kernel, dim3((unsigned)std::min<long long>((nb + 255) / 256, 65535)),
-                       dim3(256), 0, s, q.counts, nb);
+    const long long nmc = (long long)p.n_mol * p.C;
+    hipLaunchKernelGGL(cr_clear_kernel, dim3((unsigned)std::min<long long>((nmc + 255) / 256, 65535)),
+                       dim3(256), 0, s, q.mcount, nmc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     if (p.n_atoms > 0) {
-        const unsigned ga = (unsigned)((p.n_atoms + 255) / 256);
-        hipLaunchKernelGGL(cr_prep_kernel, dim3(ga), dim3(256), 0, s, p, q);
+        hipLaunchKernelGGL(cr_prep_kernel, dim3((unsigned)q.nblk), dim3(PREP_BLOCK), 0, s, p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
-    }
-    hipLaunchKernelGGL(cr_scan_kernel, dim3(1), dim3(1024), 0, s, q, nb);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
-    if (p.n_atoms > 0) {
-        const unsigned ga = (unsigned)((p.n_atoms + 255) / 256);
-        hipLaunchKernelGGL(cr_fill_kernel, dim3(ga), dim3(256), 0, s, p, q);
+        hipLaunchKernelGGL(cr_scan_kernel, dim3(2), dim3(1024), 0, s, q, (long long)p.C * q.nblk,
+                           nmc);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(cr_place_kernel, dim3((unsigned)q.nblk), dim3(PREP_BLOCK), 0, s, p, q);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    } else {
+        // no atoms: every run is empty; mstart only has to be readable
+        hipLaunchKernelGGL(cr_clear_kernel, dim3((unsigned)std::min<long long>((nmc + 255) / 256, 65535)),
+                           dim3(256), 0, s, q.mstart, nmc);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -385,7 +502,7 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     if (form == PG_FORM_MFMA) {
         k = out_dtype == PG_OUT_F32 ? (const void *)cr_mfma_kernel<float>
                                     : (const void *)cr_mfma_kernel<__bf16>;
-        grid = nb * ((p.H + ST - 1) / ST) * ((p.W + ST - 1) / ST);
+        grid = nmc * p.D * ((p.H + ST - 1) / ST) * ((p.W + ST - 1) / ST);
     } else {
         const int r = crystal_window_runs(p.H, p.W);
         if (out_dtype == PG_OUT_F32)
@@ -400,7 +517,7 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
               : r == 8 ? (const void *)cr_window_kernel<__bf16, 8> : nullptr;
         if (!k)
             return hipErrorInvalidValue;
-        grid = nb;
+        grid = nmc * p.D;
     }
     if (lds > 65536) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

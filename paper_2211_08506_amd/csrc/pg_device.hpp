@@ -357,15 +357,4 @@ __device__ inline int write_atom_window(const GridParams &p, long long a, AtomWi
     return m;
 }
 
-// Factor of one axis at index i from a window record: 0 outside the window.
-__device__ __forceinline__ float record_factor(const AtomWindow &w, int q, int i, float h,
-                                               float inv2s2)
-{
-    float v = 0.f;
-    for (int r = 0; r < w.n[q]; ++r)
-        if (i >= w.lo[q][r] && i <= w.hi[q][r])
-            v = gauss1d(offset_at(w.bh[q][r], w.bl[q][r], h, i), inv2s2);
-    return v;
-}
-
 }  // namespace pg

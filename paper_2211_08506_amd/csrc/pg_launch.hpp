@@ -26,10 +26,11 @@ hipError_t launch_prep(const GridParams &p, hipStream_t s);
 // One structure (p.mol_index), one thread per output element (pg_plain.hip).
 hipError_t launch_plain(const GridParams &p, int out_dtype, hipStream_t s);
 
-// Crystal path (pg_crystal.hip): bins + the MFMA (form PG_FORM_MFMA) or
-// vector-ALU (PG_FORM_WINDOW) plane kernel.
+// Binned large-structure path (pg_crystal.hip): set-up kernels + the MFMA
+// (form PG_FORM_MFMA) or vector-ALU (PG_FORM_WINDOW) plane kernel.
 size_t crystal_plane_lds(int form, int H, int W, int bin_cap);
 int crystal_window_runs(int H, int W);
+int crystal_prep_blocks(long long n_atoms);
 hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form, int out_dtype,
                           size_t lds, hipStream_t s);
 

@@ -53,14 +53,28 @@ struct AtomWindow {
     float bh[3][3], bl[3][3];
 };
 
-// Crystal path: per-atom window records and (structure, channel, z) bins.
+// One entry of the channel partition: the atom and its z ranges packed as
+// (lo | hi << 16) with lo, hi as 16-bit signed values (empty: lo 0, hi -1).
+struct alignas(16) ListEntry {
+    int32_t atom;
+    uint32_t z[3];
+};
+
+// Binned (large-structure) path.  Per atom: its window record and its
+// factor values; per channel: the stable partition of all atoms by channel
+// (atom index order kept), which lays out every (structure, channel) pair
+// as one contiguous run of list entries.
 struct CrystalParams {
-    AtomWindow *table;       // n_atoms records
-    uint32_t *counts;        // n_mol * C * D bin sizes
-    uint32_t *offsets;       // n_mol * C * D + 1 bin starts
-    uint32_t *cursor;        // n_mol * C * D fill cursors
-    int32_t *list;           // bin contents: global atom indices
-    int32_t bin_cap;         // most atoms a plane kernel sorts in LDS (a power of two)
+    AtomWindow *table;       // n_atoms window records
+    float *fac;              // n_atoms x 3 x fstride factor values, ranges concatenated
+    uint32_t *bcount;        // C x nblk atoms per (channel, prep block), then their
+                             // exclusive scan in channel-major order
+    uint32_t *mcount;        // C x n_mol atoms per (channel, structure)
+    uint32_t *mstart;        // C x n_mol exclusive scan of mcount (channel-major)
+    ListEntry *list;         // n_atoms entries, channel-major, atom order within a channel
+    int32_t fstride;         // factor values per atom and axis
+    int32_t nblk;            // prep blocks (PREP_BLOCK atoms each)
+    int32_t bin_cap;         // most atoms of one plane the plane kernel stages in LDS
 };
 
 }  // namespace pg
