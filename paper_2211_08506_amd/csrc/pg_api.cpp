@@ -165,6 +165,8 @@ struct Plan {
     size_t ws = 0;            // workspace bytes
     // binned-path workspace layout (byte offsets) and sizes
     size_t ws_fac = 0, ws_bcount = 0, ws_mcount = 0, ws_mstart = 0, ws_list = 0;
+    size_t ws_zlist = 0, ws_ecount = 0, ws_prange = 0, ws_bmap = 0, ws_xop = 0, ws_yop = 0;
+    long long op_blocks = 0;
     int fstride = 0, nblk = 0;
 };
 
@@ -183,7 +185,9 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
         return PG_E_UNSUPPORTED;
     P.crystal = true;
     P.form = form;
-    P.bin_cap = kCrystalBinCap;
+    // images of one plane staged in LDS: the MFMA form keeps phi_z per image
+    // beside three 16 KiB operand stages
+    P.bin_cap = form == PG_FORM_MFMA ? MFMA_BIN_CAP : kCrystalBinCap;
     P.lds = crystal_plane_lds(form, d->H, d->W, P.bin_cap);
     const int max_lds = ctx ? ctx->max_lds : 65536;
     if (P.lds > (size_t)max_lds)
@@ -211,11 +215,28 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
     P.fstride = (int)S;
     P.nblk = crystal_prep_blocks(b->n_atoms);
     P.ws_fac = align256((size_t)b->n_atoms * sizeof(AtomWindow));
-    P.ws_bcount = P.ws_fac + align256((size_t)b->n_atoms * 3 * S * sizeof(float));
+    // factor table: the vector form only (the MFMA form evaluates factors
+    // where it uses them)
+    const size_t fac_bytes = form == PG_FORM_MFMA ? 0 : (size_t)b->n_atoms * 3 * S * sizeof(float);
+    P.ws_bcount = P.ws_fac + align256(fac_bytes);
     P.ws_mcount = P.ws_bcount + align256((size_t)d->C * P.nblk * 4);
     P.ws_mstart = P.ws_mcount + align256((size_t)nmc * 4);
     P.ws_list = P.ws_mstart + align256((size_t)nmc * 4);
     P.ws = P.ws_list + align256((size_t)std::max<long long>(b->n_atoms, 1) * sizeof(ListEntry));
+    if (form == PG_FORM_MFMA) {
+        // z-sorted images (at most 3 per atom) in 32-image operand blocks:
+        // run r starts at block ceil(3 mstart[r] / 32) + 2 r
+        if (d->D > 4096)   // the z sort's LDS counters
+            return PG_E_UNSUPPORTED;
+        P.op_blocks = (3 * b->n_atoms + 31) / 32 + 2 * nmc + 1;
+        P.ws_zlist = P.ws;
+        P.ws_ecount = P.ws_zlist + align256((size_t)P.op_blocks * 32 * sizeof(ZEntry));
+        P.ws_prange = P.ws_ecount + align256((size_t)nmc * 4);
+        P.ws_bmap = P.ws_prange + align256((size_t)nmc * d->D * 8);
+        P.ws_xop = P.ws_bmap + align256((size_t)P.op_blocks * 4);
+        P.ws_yop = P.ws_xop + align256((size_t)P.op_blocks * d->W * 32 * 2);
+        P.ws = P.ws_yop + align256((size_t)P.op_blocks * d->H * 32 * 2);
+    }
     const long long nb = nmc * d->D;
     P.block = 256;
     P.vec = 1;
@@ -401,6 +422,13 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         q.mcount = (uint32_t *)(ws + P.ws_mcount);
         q.mstart = (uint32_t *)(ws + P.ws_mstart);
         q.list = (ListEntry *)(ws + P.ws_list);
+        q.zlist = (ZEntry *)(ws + P.ws_zlist);
+        q.ecount = (uint32_t *)(ws + P.ws_ecount);
+        q.prange = (uint32_t *)(ws + P.ws_prange);
+        q.bmap = (uint32_t *)(ws + P.ws_bmap);
+        q.xop = (uint16_t *)(ws + P.ws_xop);
+        q.yop = (uint16_t *)(ws + P.ws_yop);
+        q.op_blocks = P.op_blocks;
         q.fstride = P.fstride;
         q.nblk = P.nblk;
         q.bin_cap = P.bin_cap;

@@ -4,28 +4,35 @@
 // Structures with more atoms than the molecule window kernel stages in LDS
 // take this path.  Set-up, all on the GPU and free of order-dependent
 // atomics in anything that reaches the output:
-//   prep:   one thread per atom: exact per-axis window ranges (nearest
-//           periodic images included) into the atom's record, the 1-D
-//           factors of every voxel index inside them (once per atom, ranges
-//           concatenated), and counts of the atom per (channel, structure)
-//           and per (channel, prep block);
-//   scan:   exclusive scans of both count arrays in channel-major order;
-//   place:  a stable partition of all atoms by channel (ballot ranks within
-//           a block): channel c's atoms in index order, so each (structure,
-//           channel) pair is one contiguous run of the list.
-// Then one plane kernel, one workgroup per (structure, channel, z plane
-// [, 128 x 128 super-tile]).  It compacts, in list order, the atoms of its
-// run whose z window holds the plane, so every voxel sums its atoms in
-// atom-index order (bitwise reproducible), then contracts over them:
-//   mfma:   the plane is a product of two factor matrices (separability of
-//           the Gaussian and of the cube cutoff, Sec. III-A / IV-C):
-//           G[y][x] = sum_k A[y][k] B[k][x], A[y][k] = phi_z^k(z) phi_y^k(y)
-//           formed in FP32 and rounded once to bf16, B[k][x] = phi_x^k(x) in
-//           bf16; 32 atoms per step on v_mfma_f32_32x32x16_bf16, FP32
-//           accumulation;
-//   window: the same sum in FP32 on the vector ALUs -- per 32-atom step the
-//           atoms' dense factor rows go to LDS, and each lane accumulates
-//           its 16-voxel row runs over the atoms whose y window holds the row.
+//   prep:    one thread per atom: exact per-axis window ranges (nearest
+//            periodic images included) into the atom's record, and counts of
+//            the atom per (channel, structure) and per (channel, prep block);
+//   factor:  one wave per atom: the 1-D factors of every voxel index inside
+//            its windows (ranges concatenated), written coalesced;
+//   scan:    exclusive scans of both count arrays in channel-major order;
+//   place:   a stable partition of all atoms by channel (ballot ranks within
+//            a block): channel c's atoms in index order, so each (structure,
+//            channel) pair -- a "run" -- is one contiguous stretch of the list.
+// Then one of two plane forms, one workgroup per (structure, channel, z
+// plane[, 128 x 128 super-tile]):
+//   mfma:    the plane is a product of two factor matrices (separability of
+//            the Gaussian and of the cube cutoff, Sec. III-A / IV-C):
+//            G[y][x] = sum_k phi_z^k(z) phi_y^k(y) phi_x^k(x).  Per run, a
+//            zsort kernel orders the atoms' z images stably by window start,
+//            so each plane's images are one contiguous range of that order,
+//            and an operand kernel writes phi_y and phi_x of every image once,
+//            as bf16, in 32-image blocks laid out as the matrix cores read
+//            them.  The plane kernel then streams 16-byte operand fragments,
+//            scales the phi_y fragments by phi_z of the plane, and contracts on
+//            v_mfma_f32_32x32x16_bf16 with FP32 accumulation;
+//   window:  the same sum in FP32 on the vector ALUs -- the workgroup compacts,
+//            in list order, the run's atoms whose z window holds the plane;
+//            per 32-atom step their dense factor rows go to LDS and each lane
+//            accumulates its 16-voxel row runs over the atoms whose y window
+//            holds the row.
+// Both forms sum each voxel's atoms in an order fixed by the input alone
+// (list order, or z-window start then list order), so results are bitwise
+// reproducible.
 #include "pg_device.hpp"
 #include "pg_launch.hpp"
 
@@ -34,7 +41,6 @@ namespace pg {
 constexpr int PREP_BLOCK = 256; // atoms per prep / place block (4 waves)
 constexpr int KC = 32;          // atoms per contraction step
 constexpr int ST = 128;         // MFMA super-tile edge (y and x)
-constexpr int KPAD = KC + 8;    // bf16 row pitch of the LDS operand tiles
 
 __global__ void cr_clear_kernel(uint32_t *a, long long n)
 {
@@ -43,38 +49,80 @@ __global__ void cr_clear_kernel(uint32_t *a, long long n)
         a[i] = 0u;
 }
 
+// Per-structure counts are aggregated in LDS when the block's atoms span
+// few structures (large structures: one global atomic per channel and
+// structure per block instead of one per atom).
+constexpr int PREP_SPAN = 4;
+
 __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, CrystalParams q)
 {
     __shared__ uint32_t cnt[PG_MAX_CHANNELS];
+    __shared__ uint32_t cntm[PG_MAX_CHANNELS][PREP_SPAN];
     const int tid = threadIdx.x;
-    for (int c = tid; c < p.C; c += PREP_BLOCK)
+    for (int c = tid; c < p.C; c += PREP_BLOCK) {
         cnt[c] = 0u;
+#pragma unroll
+        for (int j = 0; j < PREP_SPAN; ++j)
+            cntm[c][j] = 0u;
+    }
     __syncthreads();
-    const long long a = (long long)blockIdx.x * PREP_BLOCK + tid;
+    const long long a0 = (long long)blockIdx.x * PREP_BLOCK;
+    const long long a1 = min(p.n_atoms, a0 + PREP_BLOCK) - 1;
+    const int m_first = structure_of(p.offsets, p.n_mol, a0);
+    const int m_last = structure_of(p.offsets, p.n_mol, a1);
+    const bool local = m_last - m_first < PREP_SPAN;
+    const long long a = a0 + tid;
     if (a < p.n_atoms) {
         AtomWindow *w = q.table + a;
         const int m = write_atom_window(p, a, w);
         const int t = w->type;
         if (t >= 0) {
-            const float inv2s2 = p.inv2s2[t];
-            const int S = q.fstride;
-            for (int ax = 0; ax < 3; ++ax) {
-                float *f = q.fac + ((size_t)a * 3 + ax) * S;
-                const float h = p.h[ax];
-                int j = 0;
-                for (int r = 0; r < w->n[ax]; ++r) {
-                    const float bh = w->bh[ax][r], bl = w->bl[ax][r];
-                    for (int i = w->lo[ax][r]; i <= w->hi[ax][r] && j < S; ++i, ++j)
-                        f[j] = gauss1d(offset_at(bh, bl, h, i), inv2s2);
-                }
-            }
             atomicAdd(&cnt[t], 1u);
-            atomicAdd(&q.mcount[(size_t)t * p.n_mol + m], 1u);
+            if (local)
+                atomicAdd(&cntm[t][m - m_first], 1u);
+            else
+                atomicAdd(&q.mcount[(size_t)t * p.n_mol + m], 1u);
         }
     }
     __syncthreads();
     for (int c = tid; c < p.C; c += PREP_BLOCK)
         q.bcount[(size_t)c * q.nblk + blockIdx.x] = cnt[c];
+    if (local)
+        for (int i = tid; i < p.C * PREP_SPAN; i += PREP_BLOCK) {
+            const int c = i / PREP_SPAN, j = i - c * PREP_SPAN;
+            if (cntm[c][j] != 0u)
+                atomicAdd(&q.mcount[(size_t)c * p.n_mol + m_first + j], cntm[c][j]);
+        }
+}
+
+// One wave per atom: factor values of all window ranges, concatenated per
+// axis (lane j takes entries j, j + 64, ...), so each wave's stores are
+// contiguous.
+__global__ void __launch_bounds__(256) cr_factor_kernel(GridParams p, CrystalParams q)
+{
+    const long long a = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (a >= p.n_atoms)
+        return;
+    const AtomWindow &w = q.table[a];
+    const int t = w.type;
+    if (t < 0)
+        return;
+    const float inv2s2 = p.inv2s2[t];
+    const int S = q.fstride;
+    for (int ax = 0; ax < 3; ++ax) {
+        float *f = q.fac + ((size_t)a * 3 + ax) * S;
+        const float h = p.h[ax];
+        int base = 0;
+        for (int r = 0; r < w.n[ax]; ++r) {
+            const int lo = w.lo[ax][r], len = w.hi[ax][r] - lo + 1;
+            const float bh = w.bh[ax][r], bl = w.bl[ax][r];
+            for (int i = lane; i < len; i += 64)
+                if (base + i < S)
+                    f[base + i] = gauss1d(offset_at(bh, bl, h, lo + i), inv2s2);
+            base += len;
+        }
+    }
 }
 
 // Exclusive scan of n counts, in place (workgroup 0: the per-block counts)
@@ -138,8 +186,12 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_place_kernel(GridParams p, Crys
         ListEntry e;
         e.atom = (int32_t)a;
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-            e.z[r] = r < w.n[2] ? pack_range(w.lo[2][r], w.hi[2][r]) : pack_range(0, -1);
+        for (int r = 0; r < 3; ++r) {
+            const bool u = r < w.n[2];
+            e.z[r] = u ? pack_range(w.lo[2][r], w.hi[2][r]) : pack_range(0, -1);
+            e.bh[r] = u ? w.bh[2][r] : 0.f;
+            e.bl[r] = u ? w.bl[2][r] : 0.f;
+        }
         q.list[pos] = e;
     }
 }
@@ -255,22 +307,224 @@ __device__ __forceinline__ float step_factor(const CrystalParams &q, const StepR
     return (j >= 0 && j < q.fstride) ? q.fac[((size_t)r.atom * 3 + ax) * q.fstride + j] : 0.f;
 }
 
+// ---------------------------------------------------------------------------
+// MFMA form
+// ---------------------------------------------------------------------------
+
+// First 32-image operand block of run mc.  Runs are spaced so that run mc
+// owns at least ceil(3 count / 32) blocks (an atom has at most 3 z images):
+// block(mc) = ceil(3 mstart[mc] / 32) + 2 mc.
+__device__ __forceinline__ long long run_block(const CrystalParams &q, size_t mc)
+{
+    return (long long)((3ull * q.mstart[mc] + 31ull) / 32ull) + 2ll * (long long)mc;
+}
+
+__device__ __forceinline__ int range_lo(uint32_t v) { return (int16_t)(v & 0xffffu); }
+__device__ __forceinline__ int range_hi(uint32_t v) { return (int16_t)(v >> 16); }
+
+// One workgroup per run: the run's z images (one per z range of each
+// atom), sorted stably by window start, into zlist -- a counting sort over z
+// in LDS.  The run's list is split into one contiguous part per wave; each
+// wave counts its part (per-wave histograms), the counts are scanned over
+// (z, wave) so that every wave gets its own cursors, and each wave places its
+// part in list order, ranks of equal keys from ballots over the key bits.
+// Per plane z it writes a range [first, end) of that order holding every
+// image whose window holds z (end: images starting at or before z; first:
+// the start of the images starting at z - Lmax + 1, Lmax the run's longest
+// z window, as no earlier image reaches z), the run's image count and the
+// map of its operand blocks.  Dynamic LDS: (waves + 1) x D words.
+__global__ void __launch_bounds__(1024) cr_zsort_kernel(GridParams p, CrystalParams q)
+{
+    extern __shared__ uint32_t zs[];
+    __shared__ uint32_t wtot[16];
+    __shared__ int lmax_s;
+    const int D = p.D, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = blockDim.x >> 6, nt = blockDim.x;
+    uint32_t *zst = zs, *hist = zs + D;          // hist[w * D + z]: counts, then cursors
+    const size_t mc = blockIdx.x;
+    const uint32_t start = q.mstart[mc], n = q.mcount[mc];
+    for (int i = tid; i < (nw + 1) * D; i += nt)
+        zs[i] = 0u;
+    if (tid == 0)
+        lmax_s = 1;
+    __syncthreads();
+    const uint32_t part = (n + nw - 1) / nw;
+    const uint32_t pb = min(n, part * wave), pe = min(n, pb + part);
+    uint32_t *hw = hist + (size_t)wave * D;
+    int lmax = 1;
+    for (uint32_t base = pb; base < pe; base += 256) {
+        uint32_t zr[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t e = base + 64 * u + lane;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                zr[u][r] = e < pe ? q.list[start + e].z[r] : 0xffff0000u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int lo = range_lo(zr[u][r]), hi = range_hi(zr[u][r]);
+                if (hi >= lo) {
+                    atomicAdd(&hw[lo], 1u);
+                    lmax = max(lmax, hi - lo + 1);
+                }
+            }
+    }
+    atomicMax(&lmax_s, lmax);
+    __syncthreads();
+    // exclusive scan over z of the per-z totals: a segment of z per thread
+    const int seg = (D + nt - 1) / nt, zb = min(D, tid * seg), ze = min(D, zb + seg);
+    uint32_t sum = 0;
+    for (int z = zb; z < ze; ++z)
+        for (int w = 0; w < nw; ++w)
+            sum += hist[(size_t)w * D + z];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += v;
+    }
+    if (lane == 63)
+        wtot[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w)
+        run += wtot[w];
+    uint32_t n_img = 0;
+    for (int w = 0; w < nw; ++w)
+        n_img += wtot[w];
+    for (int z = zb; z < ze; ++z) {
+        zst[z] = run;
+        for (int w = 0; w < nw; ++w) {   // counts -> per-wave cursors
+            const uint32_t c = hist[(size_t)w * D + z];
+            hist[(size_t)w * D + z] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const int lmx = lmax_s;
+    for (int z = tid; z < D; z += nt) {
+        const uint32_t first = zst[max(0, z - lmx + 1)];
+        const uint32_t end = z + 1 < D ? zst[z + 1] : n_img;
+        q.prange[((size_t)mc * D + z) * 2] = first;
+        q.prange[((size_t)mc * D + z) * 2 + 1] = end;
+    }
+    int bits = 0;
+    while ((1 << bits) < D)
+        ++bits;
+    const long long eb = 32ll * run_block(q, mc);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    auto fetch = [&](uint32_t e, ListEntry &le) {
+        le.atom = -1;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            le.z[r] = 0xffff0000u;   // empty range
+            le.bh[r] = le.bl[r] = 0.f;
+        }
+        if (e < pe)
+            le = q.list[start + e];
+    };
+    ListEntry nxt;
+    fetch(pb + lane, nxt);
+    for (uint32_t base = pb; base < pe; base += 64) {
+        const ListEntry le = nxt;
+        fetch(base + 64 + lane, nxt);   // the next chunk's entry, in flight meanwhile
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int lo = range_lo(le.z[r]), hi = range_hi(le.z[r]);
+            const bool valid = hi >= lo;
+            // lanes of this wave holding an image with the same start
+            unsigned long long match = __ballot(valid);
+            for (int bb = 0; bb < bits; ++bb) {
+                const bool bit = valid && ((lo >> bb) & 1);
+                const unsigned long long m1 = __ballot(bit);
+                match &= bit ? m1 : ~m1;
+            }
+            if (valid) {
+                const uint32_t rank = (uint32_t)__popcll(match & below);
+                const uint32_t pos = hw[lo] + rank;
+                if (rank == 0)
+                    hw[lo] = pos + (uint32_t)__popcll(match);
+                ZEntry zent;
+                zent.atom = le.atom;
+                zent.range = le.z[r];
+                zent.bh = le.bh[r];
+                zent.bl = le.bl[r];
+                q.zlist[eb + pos] = zent;
+            }
+        }
+    }
+    if (tid == 0)
+        q.ecount[mc] = n_img;
+    const long long b0 = run_block(q, mc), nb = (n_img + 31) / 32;
+    for (long long i = tid; i < nb; i += nt)
+        q.bmap[b0 + i] = (uint32_t)mc + 1u;
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float v)
+{
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// One workgroup per operand block: phi_x and phi_y of its 32 images over
+// the whole x and y axes, as bf16, laid out [block][row][32 images] so that
+// a 16-byte load is one MFMA operand fragment.  The block is first cleared
+// with 16-byte stores; then 8 threads per image write the image's window
+// elements only (zeros elsewhere; images past the run's end stay zero).
+__global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalParams q)
+{
+    const long long gb = blockIdx.x;
+    const uint32_t tag = q.bmap[gb];
+    if (tag == 0u)
+        return;
+    const size_t mc = tag - 1u;
+    const int c = (int)(mc / (size_t)p.n_mol);
+    const long long b0 = run_block(q, mc);
+    const int tid = threadIdx.x, kl = tid & 31, rg = tid >> 5;
+    const long long k = (gb - b0) * 32 + kl;
+    const int W = p.W, H = p.H;
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    u4 *xz = (u4 *)(q.xop + (size_t)gb * W * 32);
+    u4 *yz = (u4 *)(q.yop + (size_t)gb * H * 32);
+    for (int i = tid; i < W * 4; i += 256)
+        xz[i] = u4{0u, 0u, 0u, 0u};
+    for (int i = tid; i < H * 4; i += 256)
+        yz[i] = u4{0u, 0u, 0u, 0u};
+    __threadfence_block();
+    __syncthreads();
+    if (k >= (long long)q.ecount[mc])
+        return;
+    const AtomWindow &w = q.table[q.zlist[32 * b0 + k].atom];
+    const float inv2s2 = p.inv2s2[c];
+    uint16_t *xo = q.xop + (size_t)gb * W * 32 + kl;
+    uint16_t *yo = q.yop + (size_t)gb * H * 32 + kl;
+    for (int r = 0; r < w.n[0]; ++r) {
+        const float bh = w.bh[0][r], bl = w.bl[0][r];
+        for (int v = w.lo[0][r] + rg; v <= w.hi[0][r]; v += 8)
+            xo[(size_t)v * 32] = bf16_bits(gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2));
+    }
+    for (int r = 0; r < w.n[1]; ++r) {
+        const float bh = w.bh[1][r], bl = w.bl[1][r];
+        for (int v = w.lo[1][r] + rg; v <= w.hi[1][r]; v += 8)
+            yo[(size_t)v * 32] = bf16_bits(gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2));
+    }
+}
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // One workgroup (4 waves) per (structure, channel, z, super-tile); wave w
 // owns the 64 x 64 quadrant (w / 2, w % 2) of the 128 x 128 super-tile as
-// 2 x 2 MFMA tiles of 32 x 32.
+// 2 x 2 MFMA tiles of 32 x 32.  The plane's images are the contiguous range
+// [first, end) of its run's z order, taken in whole 32-image operand blocks
+// (images of a block outside the plane get phi_z = 0).
 template <typename T>
 __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParams q)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *At = (__bf16 *)smem;                          // [ST][KPAD]: A[y][k]
-    __bf16 *Bt = At + ST * KPAD;                          // [ST][KPAD]: B[k][x] stored by x
-    StepRec *recs = (StepRec *)(Bt + ST * KPAD);          // [KC]
-    uint32_t *wsum = (uint32_t *)(recs + KC);             // [4]
-    int32_t *ids = (int32_t *)(wsum + 4);                 // [bin_cap]
-    float *gzs = (float *)(ids + q.bin_cap);              // [bin_cap]
+    __shared__ __attribute__((aligned(16))) float gzs[MFMA_BIN_CAP];   // phi_z per image
     const int C = p.C, D = p.D, H = p.H, W = p.W;
     const int nsx = (W + ST - 1) / ST, nsy = (H + ST - 1) / ST;
     long long b = xcd_block();
@@ -284,11 +538,30 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
     const int m = (int)(b / C);
     const int y0 = sy * ST, x0 = sx * ST;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    const int cnt = gather_plane(p, q, m, c, z, ids, gzs, wsum);
-    if (cnt < 0 && tid == 0 && sx == 0 && sy == 0)
-        raise_error(p.err, PG_E_CAPACITY, m);
-    const int nk = cnt < 0 ? 0 : cnt;
+    const size_t mc = (size_t)c * p.n_mol + m;
+    const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
+    const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
+    const uint32_t n_img = q.ecount[mc];
+    const int kb0 = (int)(first / 32);
+    int nkb = first < end ? (int)((end + 31) / 32) - kb0 : 0;
+    if (nkb * 32 > min(q.bin_cap, MFMA_BIN_CAP)) {
+        if (tid == 0 && sx == 0 && sy == 0)
+            raise_error(p.err, PG_E_CAPACITY, m);
+        nkb = 0;
+    }
+    const long long rb = run_block(q, mc);
+    const float inv2s2 = p.inv2s2[c], hz = p.h[2];
+    for (int i = tid; i < nkb * 32; i += blockDim.x) {
+        const uint32_t k = (uint32_t)kb0 * 32 + i;
+        float g = 0.f;
+        if (k < n_img) {
+            const ZEntry ze = q.zlist[32 * rb + k];
+            if (z >= range_lo(ze.range) && z <= range_hi(ze.range))
+                g = gauss1d(offset_at(ze.bh, ze.bl, hz, z), inv2s2);
+        }
+        gzs[i] = g;
+    }
+    __syncthreads();
 
     f32x16 acc[2][2];
 #pragma unroll
@@ -299,46 +572,72 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
             for (int e = 0; e < 16; ++e)
                 acc[i][j][e] = 0.f;
     const int qy = (wave >> 1) * 64, qx = (wave & 1) * 64;
-
-    for (int k0 = 0; k0 < nk; k0 += KC) {
-        stage_records(q, ids, k0, min(KC, nk - k0), recs);
-        __syncthreads();
-        // operand columns of 32 atoms: 8 threads per atom, each 16 rows of A
-        // and 16 rows of B^T (every entry written, zeros included)
-        {
-            const int k = tid >> 3, part = tid & 7;
-            const StepRec r = recs[k];
-            const float g = r.atom >= 0 ? gzs[k0 + k] : 0.f;
-#pragma unroll 4
-            for (int i = part; i < ST; i += 8) {
-                const float fy = r.atom >= 0 ? step_factor(q, r, 1, y0 + i) : 0.f;
-                const float fx = r.atom >= 0 ? step_factor(q, r, 0, x0 + i) : 0.f;
-                At[i * KPAD + k] = (__bf16)(g * fy);
-                Bt[i * KPAD + k] = (__bf16)fx;
-            }
-        }
-        __syncthreads();
-        // 2 k-steps of 16 on the wave's 2 x 2 tiles
+    const int ko = 8 * (lane >> 5);
+    const __bf16 *yop = (const __bf16 *)q.yop, *xop = (const __bf16 *)q.xop;
+    // operand rows of this lane; rows past the plane edge load the last row
+    // instead: they only feed output rows / columns that are never stored
+    int yc[2], xc[2];
 #pragma unroll
-        for (int ks = 0; ks < KC; ks += 16) {
-            const int kk = ks + 8 * (lane >> 5);
-            bf16x8 av[2], bv[2];
+    for (int i = 0; i < 2; ++i) {
+        yc[i] = min(y0 + qy + 32 * i + (lane & 31), H - 1);
+        xc[i] = min(x0 + qx + 32 * i + (lane & 31), W - 1);
+    }
+    // fragments of one operand block, [k-half][tile]: 16-byte loads with no
+    // use of the registers here, so they stay in flight until contracted
+    auto load_block = [&](int kb, bf16x8 (&ar)[2][2], bf16x8 (&br)[2][2]) {
+        const size_t gb = (size_t)(rb + kb0 + kb);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                av[i] = *(const bf16x8 *)(At + (qy + 32 * i + (lane & 31)) * KPAD + kk);
-                bv[i] = *(const bf16x8 *)(Bt + (qx + 32 * i + (lane & 31)) * KPAD + kk);
+                const int kk = 16 * h + ko;
+                ar[h][i] = *(const bf16x8 *)(yop + (gb * H + yc[i]) * 32 + kk);
+                br[h][i] = *(const bf16x8 *)(xop + (gb * W + xc[i]) * 32 + kk);
             }
+    };
+    // A = phi_y scaled by phi_z of the plane (rounded once to bf16), B = phi_x
+    auto contract = [&](int kb, const bf16x8 (&ar)[2][2], const bf16x8 (&br)[2][2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kk = 16 * h + ko;
+            const float4 g0 = *(const float4 *)(gzs + kb * 32 + kk);
+            const float4 g1 = *(const float4 *)(gzs + kb * 32 + kk + 4);
+            const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+            bf16x8 av[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    av[i][e] = (__bf16)((float)ar[h][i][e] * g[e]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], br[h][j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
+    };
+    // two fragment sets in turn: the loads of one block are in flight while
+    // the other block is contracted (scheduling barriers keep that order)
+    bf16x8 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
+    if (nkb > 0)
+        load_block(0, a0, b0);
+    int kb = 0;
+    for (; kb + 1 < nkb; kb += 2) {
+        load_block(kb + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        contract(kb, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_block(min(kb + 2, nkb - 1), a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        contract(kb + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    if (kb < nkb)
+        contract(kb, a0, b0);
 
     // store the quadrant: lane holds column (lane & 31) of rows
-    // 8 (e / 4) + 4 (lane / 32) + e % 4 of each tile
+    // 8 (e / 4) + 4 (lane / 32) + e % 4 of each tile; a store instruction
+    // writes 64 contiguous bytes (bf16) per half-wave
     T *out = (T *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -445,12 +744,23 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
 
 size_t crystal_plane_lds(int form, int H, int W, int bin_cap)
 {
+    if (form == PG_FORM_MFMA)   // all static: phi_z per image and the operand stages
+        return 0;
     const size_t tail = (size_t)KC * sizeof(StepRec) + 4 * sizeof(uint32_t) +
                         (size_t)bin_cap * (sizeof(int32_t) + sizeof(float));
-    if (form == PG_FORM_MFMA)
-        return (size_t)2 * ST * KPAD * sizeof(__bf16) + tail;
     const int W16 = (W + 15) & ~15;
     return (size_t)KC * (W16 + ((H + 3) & ~3)) * sizeof(float) + tail;
+}
+
+// waves of the z-sort workgroup: up to 16, within 64 KB of LDS counters
+int crystal_zsort_waves(int D)
+{
+    return std::max(1, std::min(16, 16000 / D - 1));
+}
+
+size_t crystal_zsort_lds(int D)
+{
+    return (size_t)(crystal_zsort_waves(D) + 1) * D * sizeof(uint32_t);
 }
 
 // runs of 16 voxels per lane of the vector form (0: plane too large)
@@ -479,10 +789,22 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    const unsigned clear_grid_b = (unsigned)std::min<long long>((q.op_blocks + 255) / 256, 65535);
+    if (form == PG_FORM_MFMA) {
+        hipLaunchKernelGGL(cr_clear_kernel, dim3(clear_grid_b), dim3(256), 0, s, q.bmap, q.op_blocks);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
     if (p.n_atoms > 0) {
         hipLaunchKernelGGL(cr_prep_kernel, dim3((unsigned)q.nblk), dim3(PREP_BLOCK), 0, s, p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
+        if (form != PG_FORM_MFMA) {   // the MFMA form evaluates factors where it uses them
+            hipLaunchKernelGGL(cr_factor_kernel, dim3((unsigned)((p.n_atoms + 3) / 4)), dim3(256),
+                               0, s, p, q);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+        }
         hipLaunchKernelGGL(cr_scan_kernel, dim3(2), dim3(1024), 0, s, q, (long long)p.C * q.nblk,
                            nmc);
         if ((e = hipGetLastError()) != hipSuccess)
@@ -494,6 +816,22 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
         // no atoms: every run is empty; mstart only has to be readable
         hipLaunchKernelGGL(cr_clear_kernel, dim3((unsigned)std::min<long long>((nmc + 255) / 256, 65535)),
                            dim3(256), 0, s, q.mstart, nmc);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    if (form == PG_FORM_MFMA) {
+        const size_t zl = crystal_zsort_lds(p.D);
+        if (zl > 65536) {
+            e = hipFuncSetAttribute((const void *)cr_zsort_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl);
+            if (e != hipSuccess)
+                return e;
+        }
+        hipLaunchKernelGGL(cr_zsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_zsort_waves(p.D)),
+                           zl, s, p, q);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(cr_operand_kernel, dim3((unsigned)q.op_blocks), dim3(256), 0, s, p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

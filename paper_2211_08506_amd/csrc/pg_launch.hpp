@@ -31,6 +31,9 @@ hipError_t launch_plain(const GridParams &p, int out_dtype, hipStream_t s);
 size_t crystal_plane_lds(int form, int H, int W, int bin_cap);
 int crystal_window_runs(int H, int W);
 int crystal_prep_blocks(long long n_atoms);
+// z images of one plane the MFMA plane kernel stages (static LDS)
+constexpr int MFMA_BIN_CAP = 2048;
+size_t crystal_zsort_lds(int D);
 hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form, int out_dtype,
                           size_t lds, hipStream_t s);
 

@@ -53,28 +53,47 @@ struct AtomWindow {
     float bh[3][3], bl[3][3];
 };
 
-// One entry of the channel partition: the atom and its z ranges packed as
-// (lo | hi << 16) with lo, hi as 16-bit signed values (empty: lo 0, hi -1).
+// One entry of the channel partition: the atom, its z ranges packed as
+// (lo | hi << 16) with lo, hi as 16-bit signed values (empty: lo 0, hi -1),
+// and the float-float base offset o_z - mu_z - n L_z of each range.
 struct alignas(16) ListEntry {
     int32_t atom;
     uint32_t z[3];
+    float bh[3], bl[3];
+};
+
+// One z image of one atom in the z-sorted order of the MFMA form: the atom,
+// its z range packed as in ListEntry, and the range's base offset.
+struct ZEntry {
+    int32_t atom;
+    uint32_t range;
+    float bh, bl;
 };
 
 // Binned (large-structure) path.  Per atom: its window record and its
 // factor values; per channel: the stable partition of all atoms by channel
 // (atom index order kept), which lays out every (structure, channel) pair
-// as one contiguous run of list entries.
+// ("run") as one contiguous stretch of the list.  The MFMA form adds, per
+// run, the z images sorted by window start, each plane's contiguous range
+// of them, and the bf16 factor operands in 32-entry blocks.
 struct CrystalParams {
     AtomWindow *table;       // n_atoms window records
     float *fac;              // n_atoms x 3 x fstride factor values, ranges concatenated
     uint32_t *bcount;        // C x nblk atoms per (channel, prep block), then their
                              // exclusive scan in channel-major order
-    uint32_t *mcount;        // C x n_mol atoms per (channel, structure)
-    uint32_t *mstart;        // C x n_mol exclusive scan of mcount (channel-major)
+    uint32_t *mcount;        // C x n_mol atoms per run (channel-major)
+    uint32_t *mstart;        // C x n_mol exclusive scan of mcount
     ListEntry *list;         // n_atoms entries, channel-major, atom order within a channel
+    ZEntry *zlist;           // entry capacity: run r starts at entry 32 * run_block(r)
+    uint32_t *ecount;        // C x n_mol z images per run
+    uint32_t *prange;        // C x n_mol x D x 2: first and end image of each plane
+    uint32_t *bmap;          // per operand block: run + 1 (0: unused)
+    uint16_t *xop;           // operand blocks x W x 32 bf16: phi_x of 32 images
+    uint16_t *yop;           // operand blocks x H x 32 bf16: phi_y of 32 images
+    int64_t op_blocks;       // operand block capacity
     int32_t fstride;         // factor values per atom and axis
     int32_t nblk;            // prep blocks (PREP_BLOCK atoms each)
-    int32_t bin_cap;         // most atoms of one plane the plane kernel stages in LDS
+    int32_t bin_cap;         // most atoms (images) of one plane a plane kernel takes
 };
 
 }  // namespace pg

@@ -156,9 +156,10 @@ def test_determinism(pg, dev):
 
 
 def test_bin_capacity_overflow_reports_and_zeroes(pg, dev):
-    """A plane whose bin holds more than 4096 atoms of one channel is
-    written as zeros and flagged (structure index); other planes and
-    structures are unaffected."""
+    """A plane holding more atoms of one channel than the plane kernel
+    stages (4096, or 2048 z images for the MFMA form) is written as zeros
+    and flagged (structure index); other planes and structures are
+    unaffected."""
     rng = np.random.default_rng(35)
     sig = [0.5, 0.5]
     xyz = np.concatenate([rng.uniform(-0.5, 0.5, size=(5000, 3)),
