@@ -82,9 +82,10 @@ enum { PG_OUT_F32 = 0, PG_OUT_BF16 = 1 };
    structures.  AUTO picks WINDOW when the structure fits, else MFMA for
    bf16 and WINDOW (binned) for float32 output.  The binned path needs a
    workspace (pg_workspace_size) and does not take per-structure spacings;
-   a plane holding more atoms of one channel than the form stages in LDS
-   (4096 for WINDOW, 2048 z images for MFMA; pg_plan_info.atom_capacity) is
-   reported as PG_E_CAPACITY through pg_get_device_error and left as zeros. */
+   under MFMA, a plane holding more than 2048 z images of one channel
+   (pg_plan_info.atom_capacity) is reported as PG_E_CAPACITY through
+   pg_get_device_error and left as zeros; the binned WINDOW form has no such
+   limit (atom_capacity 0).  The binned path needs D <= 4096. */
 enum { PG_FORM_AUTO = 0, PG_FORM_PLAIN = 1, PG_FORM_WINDOW = 2, PG_FORM_MFMA = 3 };
 
 /* Grid description (all fields host values). */

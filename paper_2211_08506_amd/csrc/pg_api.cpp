@@ -164,79 +164,67 @@ struct Plan {
     size_t lds = 0;           // dynamic LDS bytes of one workgroup
     size_t ws = 0;            // workspace bytes
     // binned-path workspace layout (byte offsets) and sizes
-    size_t ws_fac = 0, ws_bcount = 0, ws_mcount = 0, ws_mstart = 0, ws_list = 0;
+    size_t ws_bcount = 0, ws_mcount = 0, ws_mstart = 0, ws_list = 0;
     size_t ws_zlist = 0, ws_ecount = 0, ws_prange = 0, ws_bmap = 0, ws_xop = 0, ws_yop = 0;
     long long op_blocks = 0;
-    int fstride = 0, nblk = 0;
+    int nblk = 0;
 };
 
-constexpr int kCrystalBinCap = 4096;   // atoms of one plane the plane kernel stages in LDS
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Binned path: workspace layout (window records | factor values | per-block
-// channel counts | per-structure channel counts | their scan | channel
-// partition list) and the plane kernel's LDS.
+// Binned path: workspace layout (window records | per-block channel counts
+// | per-structure channel counts | their scan | channel partition | z-sorted
+// images | per-run image counts | per-plane image ranges | operand block map
+// | bf16 operands (MFMA form)) and the plane kernel's LDS.
 int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, int form, Plan &P)
 {
     if (b->spacings)
         return PG_E_UNSUPPORTED;
     if (form == PG_FORM_WINDOW && crystal_window_runs(d->H, d->W) == 0)
         return PG_E_UNSUPPORTED;
+    if (d->D > 4096)   // the z sort's LDS counters; z ranges packed as 16-bit values
+        return PG_E_UNSUPPORTED;
     P.crystal = true;
     P.form = form;
-    // images of one plane staged in LDS: the MFMA form keeps phi_z per image
-    // beside three 16 KiB operand stages
-    P.bin_cap = form == PG_FORM_MFMA ? MFMA_BIN_CAP : kCrystalBinCap;
-    P.lds = crystal_plane_lds(form, d->H, d->W, P.bin_cap);
+    // the MFMA form stages phi_z of a plane's z images in LDS; the vector
+    // form streams them (no limit)
+    P.bin_cap = form == PG_FORM_MFMA ? MFMA_BIN_CAP : 0;
+    P.lds = crystal_plane_lds(form, d->H, d->W);
     const int max_lds = ctx ? ctx->max_lds : 65536;
     if (P.lds > (size_t)max_lds)
         return PG_E_UNSUPPORTED;
-    if (d->D > 32767)   // z ranges are packed as 16-bit values
-        return PG_E_UNSUPPORTED;
-    float rc_max = 0.f;
-    for (int c = 0; c < d->C; ++c)
-        rc_max = std::max(rc_max, rc_of(d, c));
-    // factor values per atom and axis: all window ranges of one atom,
-    // concatenated (at most one window per image, each at most
-    // floor(2 rc / h) + 1 voxels, and never more than the axis)
-    const long long imgs = d->periodic ? 3 : 1;
-    const int dims[3] = {d->W, d->H, d->D};
-    long long S = 1;
-    for (int q = 0; q < 3; ++q) {
-        long long sq = dims[q];
-        if (d->cutoff_k > 0.f)
-            sq = std::min<long long>(sq, imgs * ((long long)std::ceil(2.0 * rc_max / d->spacing[q]) + 2));
-        S = std::max(S, sq);
-    }
     const long long nmc = (long long)b->n_mol * d->C;
-    if (b->n_atoms * 3 * S > 0x3fffffffffLL || nmc > 0x7fffffffLL)
+    if (nmc > 0x7fffffffLL || 3 * b->n_atoms > 0xffffffffLL)
         return PG_E_SHAPE;
-    P.fstride = (int)S;
     P.nblk = crystal_prep_blocks(b->n_atoms);
-    P.ws_fac = align256((size_t)b->n_atoms * sizeof(AtomWindow));
-    // factor table: the vector form only (the MFMA form evaluates factors
-    // where it uses them)
-    const size_t fac_bytes = form == PG_FORM_MFMA ? 0 : (size_t)b->n_atoms * 3 * S * sizeof(float);
-    P.ws_bcount = P.ws_fac + align256(fac_bytes);
-    P.ws_mcount = P.ws_bcount + align256((size_t)d->C * P.nblk * 4);
-    P.ws_mstart = P.ws_mcount + align256((size_t)nmc * 4);
-    P.ws_list = P.ws_mstart + align256((size_t)nmc * 4);
-    P.ws = P.ws_list + align256((size_t)std::max<long long>(b->n_atoms, 1) * sizeof(ListEntry));
+    // z images (at most 3 per atom) in 32-image blocks: run r starts at
+    // block ceil(3 mstart[r] / 32) + 2 r
+    P.op_blocks = (3 * b->n_atoms + 31) / 32 + 2 * nmc + 1;
+    size_t off = align256((size_t)b->n_atoms * sizeof(AtomWindow));
+    P.ws_bcount = off;
+    off += align256((size_t)d->C * P.nblk * 4);
+    P.ws_mcount = off;
+    off += align256((size_t)nmc * 4);
+    P.ws_mstart = off;
+    off += align256((size_t)nmc * 4);
+    P.ws_list = off;
+    off += align256((size_t)std::max<long long>(b->n_atoms, 1) * sizeof(ListEntry));
+    P.ws_zlist = off;
+    off += align256((size_t)P.op_blocks * 32 * sizeof(ZEntry));
+    P.ws_ecount = off;
+    off += align256((size_t)nmc * 4);
+    P.ws_prange = off;
+    off += align256((size_t)nmc * d->D * 8);
+    P.ws_bmap = off;
+    off += align256((size_t)P.op_blocks * 4);
+    P.ws_xop = P.ws_yop = off;
     if (form == PG_FORM_MFMA) {
-        // z-sorted images (at most 3 per atom) in 32-image operand blocks:
-        // run r starts at block ceil(3 mstart[r] / 32) + 2 r
-        if (d->D > 4096)   // the z sort's LDS counters
-            return PG_E_UNSUPPORTED;
-        P.op_blocks = (3 * b->n_atoms + 31) / 32 + 2 * nmc + 1;
-        P.ws_zlist = P.ws;
-        P.ws_ecount = P.ws_zlist + align256((size_t)P.op_blocks * 32 * sizeof(ZEntry));
-        P.ws_prange = P.ws_ecount + align256((size_t)nmc * 4);
-        P.ws_bmap = P.ws_prange + align256((size_t)nmc * d->D * 8);
-        P.ws_xop = P.ws_bmap + align256((size_t)P.op_blocks * 4);
-        P.ws_yop = P.ws_xop + align256((size_t)P.op_blocks * d->W * 32 * 2);
-        P.ws = P.ws_yop + align256((size_t)P.op_blocks * d->H * 32 * 2);
+        off += align256((size_t)P.op_blocks * d->W * 32 * 2);
+        P.ws_yop = off;
+        off += align256((size_t)P.op_blocks * d->H * 32 * 2);
     }
+    P.ws = off;
     const long long nb = nmc * d->D;
     P.block = 256;
     P.vec = 1;
@@ -417,7 +405,6 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         unsigned char *ws = (unsigned char *)p.ws;
         CrystalParams q;
         q.table = (AtomWindow *)ws;
-        q.fac = (float *)(ws + P.ws_fac);
         q.bcount = (uint32_t *)(ws + P.ws_bcount);
         q.mcount = (uint32_t *)(ws + P.ws_mcount);
         q.mstart = (uint32_t *)(ws + P.ws_mstart);
@@ -429,7 +416,6 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         q.xop = (uint16_t *)(ws + P.ws_xop);
         q.yop = (uint16_t *)(ws + P.ws_yop);
         q.op_blocks = P.op_blocks;
-        q.fstride = P.fstride;
         q.nblk = P.nblk;
         q.bin_cap = P.bin_cap;
         return launch_crystal(p, q, P.form, d->out_dtype, P.lds, s);

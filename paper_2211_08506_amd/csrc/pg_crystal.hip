@@ -95,36 +95,6 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, Cryst
         }
 }
 
-// One wave per atom: factor values of all window ranges, concatenated per
-// axis (lane j takes entries j, j + 64, ...), so each wave's stores are
-// contiguous.
-__global__ void __launch_bounds__(256) cr_factor_kernel(GridParams p, CrystalParams q)
-{
-    const long long a = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (a >= p.n_atoms)
-        return;
-    const AtomWindow &w = q.table[a];
-    const int t = w.type;
-    if (t < 0)
-        return;
-    const float inv2s2 = p.inv2s2[t];
-    const int S = q.fstride;
-    for (int ax = 0; ax < 3; ++ax) {
-        float *f = q.fac + ((size_t)a * 3 + ax) * S;
-        const float h = p.h[ax];
-        int base = 0;
-        for (int r = 0; r < w.n[ax]; ++r) {
-            const int lo = w.lo[ax][r], len = w.hi[ax][r] - lo + 1;
-            const float bh = w.bh[ax][r], bl = w.bl[ax][r];
-            for (int i = lane; i < len; i += 64)
-                if (base + i < S)
-                    f[base + i] = gauss1d(offset_at(bh, bl, h, lo + i), inv2s2);
-            base += len;
-        }
-    }
-}
-
 // Exclusive scan of n counts, in place (workgroup 0: the per-block counts)
 // or into mstart (workgroup 1: the per-structure counts).  One workgroup
 // of 1024 threads per array, each thread owning a contiguous segment.
@@ -204,107 +174,6 @@ __device__ __forceinline__ long long xcd_block()
 {
     const unsigned G = gridDim.x, full = G & ~7u, b = blockIdx.x;
     return b < full ? (long long)(b & 7u) * (full >> 3) + (b >> 3) : (long long)b;
-}
-
-// Ordered compaction of the plane's atoms: the (m, c) run of the channel
-// partition filtered by "z window holds z", in list order, into ids[] with
-// each atom's z factor in gz[].  Returns the count, or -1 above cap (then
-// ids / gz hold a prefix only).  Uniform across the workgroup; contains
-// barriers (all threads must call it).
-__device__ int gather_plane(const GridParams &p, const CrystalParams &q, int m, int c, int z,
-                            int32_t *ids, float *gz, uint32_t *wsum)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const size_t mc = (size_t)c * p.n_mol + m;
-    const uint32_t start = q.mstart[mc], n = q.mcount[mc];
-    const int S = q.fstride, cap = q.bin_cap;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int cnt = 0;
-    for (uint32_t base = 0; base < n; base += blockDim.x) {
-        const uint32_t e = base + tid;
-        bool live = false;
-        int a = 0, jz = 0;
-        if (e < n) {
-            const ListEntry le = q.list[start + e];
-            a = le.atom;
-            int s = 0;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const int lo = (int16_t)(le.z[r] & 0xffffu), hi = (int16_t)(le.z[r] >> 16);
-                if (z >= lo && z <= hi) {
-                    live = true;
-                    jz = s + z - lo;
-                }
-                s += hi >= lo ? hi - lo + 1 : 0;
-            }
-        }
-        const unsigned long long mask = __ballot(live);
-        if (lane == 0)
-            wsum[wave] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        int off = cnt, total = 0;
-        for (int w = 0; w < nw; ++w) {
-            off += w < wave ? (int)wsum[w] : 0;
-            total += (int)wsum[w];
-        }
-        const int pos = off + __popcll(mask & below);
-        if (live && pos < cap) {
-            ids[pos] = a;
-            gz[pos] = jz < S ? q.fac[((size_t)a * 3 + 2) * S + jz] : 0.f;
-        }
-        cnt += total;
-        __syncthreads();
-    }
-    return cnt > cap ? -1 : cnt;
-}
-
-// x / y ranges of one step's atoms, staged in LDS: lo, hi, and the start of
-// each range in the atom's concatenated factor values.
-struct StepRec {
-    int32_t atom;
-    int32_t lo[2][3], hi[2][3], st[2][3];
-};
-
-__device__ __forceinline__ void stage_records(const CrystalParams &q, const int32_t *ids, int k0,
-                                              int kn, StepRec *recs)
-{
-    const int k = threadIdx.x;
-    if (k < KC) {
-        StepRec r;
-        r.atom = k < kn ? ids[k0 + k] : -1;
-#pragma unroll
-        for (int ax = 0; ax < 2; ++ax) {
-            int s = 0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                int lo = 0, hi = -1;
-                if (r.atom >= 0) {
-                    const AtomWindow &w = q.table[r.atom];
-                    if (i < w.n[ax]) {
-                        lo = w.lo[ax][i];
-                        hi = w.hi[ax][i];
-                    }
-                }
-                r.lo[ax][i] = lo;
-                r.hi[ax][i] = hi;
-                r.st[ax][i] = s - lo;
-                s += hi - lo + 1;
-            }
-        }
-        recs[k] = r;
-    }
-}
-
-// Factor of the staged atom on axis ax at index v (0 outside its window).
-__device__ __forceinline__ float step_factor(const CrystalParams &q, const StepRec &r, int ax,
-                                             int v)
-{
-    int j = -1;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (v >= r.lo[ax][i] && v <= r.hi[ax][i])
-            j = r.st[ax][i] + v;
-    return (j >= 0 && j < q.fstride) ? q.fac[((size_t)r.atom * 3 + ax) * q.fstride + j] : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -654,102 +523,142 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
             }
 }
 
-// FP32 vector-ALU form: one workgroup (256 threads) per (structure,
-// channel, z); lane t owns 16-voxel row runs p = t + 256 r of the plane.
-template <typename T, int RMAX>
+// FP32 vector-ALU form: one workgroup (256 threads) per (structure, channel,
+// z); the plane's images are the range [first, end) of the run's z order.
+// Per 32-image step the images' dense factor rows go to LDS -- phi_x, and
+// phi_z(z) phi_y -- evaluated where the windows are (8 threads per image),
+// and, per 32 x 32 output tile, a bit mask of the step's images whose
+// window meets the tile.  Wave w owns tiles w, w + 4, ...; lane l owns the
+// 4 x 4 voxels at rows 4 (l / 8), columns 4 (l % 8) of each: for every
+// image in the tile's mask (lowest bit first) it reads 4 phi_y and 4 phi_x
+// values and does 16 FMAs.  Each voxel sums its images in z order, in FP32.
+template <typename T, int TMAX>
 __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalParams q)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int C = p.C, D = p.D, H = p.H, W = p.W;
-    const int W16 = (W + 15) & ~15;
-    float *gx = (float *)smem;                    // [KC][W16] phi_x
-    float *gy = gx + KC * W16;                    // [KC][H]   phi_z(z) phi_y
-    StepRec *recs = (StepRec *)(gy + KC * ((H + 3) & ~3));
-    uint32_t *wsum = (uint32_t *)(recs + KC);
-    int32_t *ids = (int32_t *)(wsum + 4);
-    float *gzs = (float *)(ids + q.bin_cap);
+    const int W32 = (W + 31) & ~31, H32 = (H + 31) & ~31;
+    const int ntx = W32 / 32, nty = H32 / 32, ntiles = ntx * nty;
+    float *gx = (float *)smem;                    // [KC][W32] phi_x
+    float *gy = gx + KC * W32;                    // [KC][H32] phi_z(z) phi_y
+    uint32_t *tmask = (uint32_t *)(gy + KC * H32);   // [ntiles] images meeting each tile
     long long b = xcd_block();
     const int z = (int)(b % D);
     b /= D;
     const int c = (int)(b % C);
     const int m = (int)(b / C);
-    const int tid = threadIdx.x;
-    const int cnt = gather_plane(p, q, m, c, z, ids, gzs, wsum);
-    if (cnt < 0 && tid == 0)
-        raise_error(p.err, PG_E_CAPACITY, m);
-    const int nk = cnt < 0 ? 0 : cnt;
-    const int runs_x = W16 / 16;
-    const int n_runs = H * runs_x;
-    float acc[RMAX][16];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const size_t mc = (size_t)c * p.n_mol + m;
+    const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
+    const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
+    const long long eb = 32ll * run_block(q, mc);
+    const float inv2s2 = p.inv2s2[c];
+    const int ly = 4 * (lane >> 3), lx = 4 * (lane & 7);
+    float acc[TMAX][4][4];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r)
+    for (int i = 0; i < TMAX; ++i)
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
-            acc[r][e] = 0.f;
+        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc[i][rr][e] = 0.f;
 
-    for (int k0 = 0; k0 < nk; k0 += KC) {
-        const int kn = min(KC, nk - k0);
-        stage_records(q, ids, k0, kn, recs);
+    for (uint32_t k0 = first; k0 < end; k0 += KC) {
+        const int kn = (int)min((uint32_t)KC, end - k0);
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        for (int i = tid; i < 8 * (W32 + H32); i += blockDim.x)
+            ((u4 *)gx)[i] = u4{0u, 0u, 0u, 0u};
+        for (int i = tid; i < ntiles; i += blockDim.x)
+            tmask[i] = 0u;
         __syncthreads();
-        // dense factor rows of the step's atoms
-        for (int e = tid; e < kn * (W16 + H); e += blockDim.x) {
-            const int k = e / (W16 + H), j = e - k * (W16 + H);
-            const StepRec &r = recs[k];
-            if (j < W16) {
-                gx[k * W16 + j] = j < W ? step_factor(q, r, 0, j) : 0.f;
-            } else {
-                const int y = j - W16;
-                gy[k * H + y] = gzs[k0 + k] * step_factor(q, r, 1, y);
+        {
+            const int k = tid >> 3, part = tid & 7;
+            if (k < kn) {
+                const ZEntry ze = q.zlist[eb + k0 + k];
+                if (z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
+                    const float g = gauss1d(offset_at(ze.bh, ze.bl, p.h[2], z), inv2s2);
+                    const AtomWindow &w = q.table[ze.atom];
+                    uint32_t tx = 0u, ty = 0u;   // tile columns / rows the windows meet
+                    for (int r = 0; r < w.n[0]; ++r) {
+                        const float bh = w.bh[0][r], bl = w.bl[0][r];
+                        for (int t = w.lo[0][r] >> 5; t <= (w.hi[0][r] >> 5); ++t)
+                            tx |= 1u << t;
+                        for (int v = w.lo[0][r] + part; v <= w.hi[0][r]; v += 8)
+                            gx[k * W32 + v] = gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2);
+                    }
+                    for (int r = 0; r < w.n[1]; ++r) {
+                        const float bh = w.bh[1][r], bl = w.bl[1][r];
+                        for (int t = w.lo[1][r] >> 5; t <= (w.hi[1][r] >> 5); ++t)
+                            ty |= 1u << t;
+                        for (int v = w.lo[1][r] + part; v <= w.hi[1][r]; v += 8)
+                            gy[k * H32 + v] = g * gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2);
+                    }
+                    if (part == 0)
+                        for (int tr = 0; tr < nty; ++tr)
+                            if ((ty >> tr) & 1u)
+                                for (int tc = 0; tc < ntx; ++tc)
+                                    if ((tx >> tc) & 1u)
+                                        atomicOr(&tmask[tr * ntx + tc], 1u << k);
+                }
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            const int run = tid + 256 * r;
-            if (run < n_runs) {
-                const int y = run / runs_x, xr = (run - y * runs_x) * 16;
-                for (int k = 0; k < kn; ++k) {
-                    const float g = gy[k * H + y];
-                    if (g == 0.f)
-                        continue;
-                    const float4 *f = (const float4 *)(gx + k * W16 + xr);
+        for (int i = 0; i < TMAX; ++i) {
+            const int t = wave + 4 * i;
+            if (t >= ntiles)
+                break;
+            const int y = 32 * (t / ntx) + ly, x = 32 * (t % ntx) + lx;
+            uint32_t mk = tmask[t];
+            while (mk) {
+                const int k = __builtin_ctz(mk);
+                mk &= mk - 1u;
+                const float4 g4 = *(const float4 *)(gy + k * H32 + y);
+                const float4 f4 = *(const float4 *)(gx + k * W32 + x);
+                const float gr[4] = {g4.x, g4.y, g4.z, g4.w}, fr[4] = {f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const float4 fv = f[v];
-                        acc[r][4 * v + 0] = __builtin_fmaf(g, fv.x, acc[r][4 * v + 0]);
-                        acc[r][4 * v + 1] = __builtin_fmaf(g, fv.y, acc[r][4 * v + 1]);
-                        acc[r][4 * v + 2] = __builtin_fmaf(g, fv.z, acc[r][4 * v + 2]);
-                        acc[r][4 * v + 3] = __builtin_fmaf(g, fv.w, acc[r][4 * v + 3]);
-                    }
-                }
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[i][rr][e] = __builtin_fmaf(gr[rr], fr[e], acc[i][rr][e]);
             }
         }
         __syncthreads();
     }
     T *out = (T *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
+    const bool vec_ok = (W & 3) == 0 && ((uintptr_t)p.out & 15) == 0;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        const int run = tid + 256 * r;
-        if (run < n_runs) {
-            const int y = run / runs_x, xr = (run - y * runs_x) * 16;
-            for (int e = 0; e < 16; ++e) {
-                if (xr + e < W) {
-                    const float v[1] = {acc[r][e]};
-                    store_vec<T, 1>(out + (size_t)y * W + xr + e, v, p.nt_store != 0);
-                }
+    for (int i = 0; i < TMAX; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= ntiles)
+            break;
+        const int y0 = 32 * (t / ntx) + ly, x0 = 32 * (t % ntx) + lx;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int y = y0 + rr;
+            if (y >= H)
+                continue;
+            T *o = out + (size_t)y * W + x0;
+            if (vec_ok && x0 + 3 < W) {
+                store_vec<T, 4>(o, acc[i][rr], p.nt_store != 0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (x0 + e < W) {
+                        const float v[1] = {acc[i][rr][e]};
+                        store_vec<T, 1>(o + e, v, p.nt_store != 0);
+                    }
             }
         }
     }
 }
 
-size_t crystal_plane_lds(int form, int H, int W, int bin_cap)
+size_t crystal_plane_lds(int form, int H, int W)
 {
-    if (form == PG_FORM_MFMA)   // all static: phi_z per image and the operand stages
+    if (form == PG_FORM_MFMA)   // all static: phi_z per image
         return 0;
-    const size_t tail = (size_t)KC * sizeof(StepRec) + 4 * sizeof(uint32_t) +
-                        (size_t)bin_cap * (sizeof(int32_t) + sizeof(float));
-    const int W16 = (W + 15) & ~15;
-    return (size_t)KC * (W16 + ((H + 3) & ~3)) * sizeof(float) + tail;
+    const int W32 = (W + 31) & ~31, H32 = (H + 31) & ~31;
+    return (size_t)KC * (W32 + H32) * sizeof(float) + (size_t)(W32 / 32) * (H32 / 32) * 4;
 }
 
 // waves of the z-sort workgroup: up to 16, within 64 KB of LDS counters
@@ -763,12 +672,16 @@ size_t crystal_zsort_lds(int D)
     return (size_t)(crystal_zsort_waves(D) + 1) * D * sizeof(uint32_t);
 }
 
-// runs of 16 voxels per lane of the vector form (0: plane too large)
+// 32 x 32 tiles per wave of the vector form (0: plane too large; tile masks
+// are 32-bit per axis)
 int crystal_window_runs(int H, int W)
 {
-    const long long runs = (long long)H * (((W + 15) & ~15) / 16);
+    const int ty = (H + 31) / 32, tx = (W + 31) / 32;
+    if (ty > 32 || tx > 32)
+        return 0;
+    const int tiles = tx * ty;
     for (int r = 1; r <= 8; r <<= 1)
-        if (runs <= 256LL * r)
+        if (tiles <= 4 * r)
             return r;
     return 0;
 }
@@ -790,21 +703,13 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     if (e != hipSuccess)
         return e;
     const unsigned clear_grid_b = (unsigned)std::min<long long>((q.op_blocks + 255) / 256, 65535);
-    if (form == PG_FORM_MFMA) {
-        hipLaunchKernelGGL(cr_clear_kernel, dim3(clear_grid_b), dim3(256), 0, s, q.bmap, q.op_blocks);
-        if ((e = hipGetLastError()) != hipSuccess)
-            return e;
-    }
+    hipLaunchKernelGGL(cr_clear_kernel, dim3(clear_grid_b), dim3(256), 0, s, q.bmap, q.op_blocks);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
     if (p.n_atoms > 0) {
         hipLaunchKernelGGL(cr_prep_kernel, dim3((unsigned)q.nblk), dim3(PREP_BLOCK), 0, s, p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
-        if (form != PG_FORM_MFMA) {   // the MFMA form evaluates factors where it uses them
-            hipLaunchKernelGGL(cr_factor_kernel, dim3((unsigned)((p.n_atoms + 3) / 4)), dim3(256),
-                               0, s, p, q);
-            if ((e = hipGetLastError()) != hipSuccess)
-                return e;
-        }
         hipLaunchKernelGGL(cr_scan_kernel, dim3(2), dim3(1024), 0, s, q, (long long)p.C * q.nblk,
                            nmc);
         if ((e = hipGetLastError()) != hipSuccess)
@@ -819,18 +724,18 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    if (form == PG_FORM_MFMA) {
-        const size_t zl = crystal_zsort_lds(p.D);
-        if (zl > 65536) {
-            e = hipFuncSetAttribute((const void *)cr_zsort_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl);
-            if (e != hipSuccess)
-                return e;
-        }
-        hipLaunchKernelGGL(cr_zsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_zsort_waves(p.D)),
-                           zl, s, p, q);
-        if ((e = hipGetLastError()) != hipSuccess)
+    const size_t zl = crystal_zsort_lds(p.D);
+    if (zl > 65536) {
+        e = hipFuncSetAttribute((const void *)cr_zsort_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl);
+        if (e != hipSuccess)
             return e;
+    }
+    hipLaunchKernelGGL(cr_zsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_zsort_waves(p.D)), zl,
+                       s, p, q);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (form == PG_FORM_MFMA) {
         hipLaunchKernelGGL(cr_operand_kernel, dim3((unsigned)q.op_blocks), dim3(256), 0, s, p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;

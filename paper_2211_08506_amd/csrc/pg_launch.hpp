@@ -28,7 +28,7 @@ hipError_t launch_plain(const GridParams &p, int out_dtype, hipStream_t s);
 
 // Binned large-structure path (pg_crystal.hip): set-up kernels + the MFMA
 // (form PG_FORM_MFMA) or vector-ALU (PG_FORM_WINDOW) plane kernel.
-size_t crystal_plane_lds(int form, int H, int W, int bin_cap);
+size_t crystal_plane_lds(int form, int H, int W);
 int crystal_window_runs(int H, int W);
 int crystal_prep_blocks(long long n_atoms);
 // z images of one plane the MFMA plane kernel stages (static LDS)

@@ -70,15 +70,14 @@ struct ZEntry {
     float bh, bl;
 };
 
-// Binned (large-structure) path.  Per atom: its window record and its
-// factor values; per channel: the stable partition of all atoms by channel
-// (atom index order kept), which lays out every (structure, channel) pair
-// ("run") as one contiguous stretch of the list.  The MFMA form adds, per
-// run, the z images sorted by window start, each plane's contiguous range
-// of them, and the bf16 factor operands in 32-entry blocks.
+// Binned (large-structure) path.  Per atom: its window record; per channel:
+// the stable partition of all atoms by channel (atom index order kept),
+// which lays out every (structure, channel) pair ("run") as one contiguous
+// stretch of the list; per run, the z images sorted by window start and
+// each plane's contiguous range of them; for the MFMA form, the bf16 factor
+// operands in 32-image blocks.
 struct CrystalParams {
     AtomWindow *table;       // n_atoms window records
-    float *fac;              // n_atoms x 3 x fstride factor values, ranges concatenated
     uint32_t *bcount;        // C x nblk atoms per (channel, prep block), then their
                              // exclusive scan in channel-major order
     uint32_t *mcount;        // C x n_mol atoms per run (channel-major)
@@ -91,9 +90,8 @@ struct CrystalParams {
     uint16_t *xop;           // operand blocks x W x 32 bf16: phi_x of 32 images
     uint16_t *yop;           // operand blocks x H x 32 bf16: phi_y of 32 images
     int64_t op_blocks;       // operand block capacity
-    int32_t fstride;         // factor values per atom and axis
     int32_t nblk;            // prep blocks (PREP_BLOCK atoms each)
-    int32_t bin_cap;         // most atoms (images) of one plane a plane kernel takes
+    int32_t bin_cap;         // most z images of one plane the MFMA plane kernel takes
 };
 
 }  // namespace pg

@@ -142,9 +142,9 @@ def test_binned_path_agrees_with_small_structure_path(pg, dev):
 
 
 def test_determinism(pg, dev):
-    """The fill pass appends atoms to the plane bins with atomics in any
-    order; the plane kernels sort each bin, so every voxel sums its atoms
-    in index order and repeated calls are bitwise identical."""
+    """The set-up fixes each plane's image order from the input alone (a
+    stable partition by channel, then a stable sort by z-window start), so
+    repeated calls are bitwise identical."""
     sig = synth.sigma_table(3, 0.3, 0.45)
     b = cell_batch(34, [900, 500], 8.0, 3)
     for form, dt, _ in CASES:
@@ -155,11 +155,11 @@ def test_determinism(pg, dev):
             assert torch.equal(g0, g1), form
 
 
-def test_bin_capacity_overflow_reports_and_zeroes(pg, dev):
-    """A plane holding more atoms of one channel than the plane kernel
-    stages (4096, or 2048 z images for the MFMA form) is written as zeros
-    and flagged (structure index); other planes and structures are
-    unaffected."""
+def test_dense_plane_capacity(pg, dev):
+    """5000 atoms of one channel within 1 A: the FP32 vector form streams a
+    plane's images and has no capacity limit; the MFMA form stages phi_z of
+    at most 2048 z images per plane -- a fuller plane is written as zeros
+    and flagged (structure index), other planes and structures unaffected."""
     rng = np.random.default_rng(35)
     sig = [0.5, 0.5]
     xyz = np.concatenate([rng.uniform(-0.5, 0.5, size=(5000, 3)),
@@ -168,23 +168,26 @@ def test_bin_capacity_overflow_reports_and_zeroes(pg, dev):
     b = synth.Batch(xyz, types, np.array([0, 5000, 5300], np.int32))
     dims, h, origin = (24, 24, 24), 0.25, (-3, -3, -3)
     ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, dims, h, origin)
-    for form in ("window", "mfma"):
-        say(f"case bin capacity form={form}")
-        ctx = pg.Context(0)
-        g = run(pg, dev, b, sig, dims, h, origin, torch.float32, form, ctx=ctx)
-        code, first = ctx.device_error()
-        assert code == pg.PG_E_CAPACITY and first == 0
-        got = g.double().cpu().numpy()
-        tol = F32_TOL if form == "window" else BF16_TOL
-        dropped = 0
-        for z in range(dims[0]):
-            if not got[0, 0, z].any() and ref[0, 0, z].any():
-                dropped += 1                    # an overflowing bin
-            else:
-                assert errors(got[0, 0, z], ref[0, 0, z])[0] <= tol
-        assert dropped >= 1
-        assert not got[0, 1].any()
-        assert errors(got[1], ref[1])[0] <= tol
+    say("case dense plane form=window")
+    ctx = pg.Context(0)
+    g = run(pg, dev, b, sig, dims, h, origin, torch.float32, "window", ctx=ctx)
+    assert ctx.device_error()[0] == 0
+    check("dense/window", g, ref, F32_TOL)
+    say("case dense plane form=mfma")
+    ctx = pg.Context(0)
+    g = run(pg, dev, b, sig, dims, h, origin, torch.float32, "mfma", ctx=ctx)
+    code, first = ctx.device_error()
+    assert code == pg.PG_E_CAPACITY and first == 0
+    got = g.double().cpu().numpy()
+    dropped = 0
+    for z in range(dims[0]):
+        if not got[0, 0, z].any() and ref[0, 0, z].any():
+            dropped += 1                    # a plane above capacity
+        else:
+            assert errors(got[0, 0, z], ref[0, 0, z])[0] <= BF16_TOL
+    assert dropped >= 1
+    assert not got[0, 1].any()
+    assert errors(got[1], ref[1])[0] <= BF16_TOL
 
 
 def test_adjoint_large_structures(pg, dev):
