@@ -293,7 +293,9 @@ def main():
             f"{fill_gbs:.0f} GB/s")
         del out
         if wl.kind == "crystal":
-            kname = f"binned path: prep+scan+fill+cr_{plan['form']}_kernel (whole step)"
+            kname = ("binned path, whole step: cr_clear, cr_prep, cr_scan, cr_place, cr_zsort, "
+                     + ("cr_operand, " if plan["form"] == "mfma" else "")
+                     + f"cr_{plan['form']}_kernel")
             flops = mfma_dense_flops(b, wl)
             extra["mfma_dense_tflops"] = (flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
                                           if plan["form"] == "mfma" else None)
