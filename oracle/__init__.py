@@ -13,9 +13,12 @@ Functions:
               decisions, for tiny grids (brute.py)
 
 What is computed is the point-sampled, un-normalised Gaussian of §III-A
-Eq. 1 at voxel centres, one channel per element type, truncated to a cube of
-half-width rc_t = fl32(k * sigma_t) (§VI-B threshold truncation), with the
-nearest-image offset for periodic orthorhombic cells (§III-A).
+Eq. 1 at voxel centres (value="point"), or the integral of the normalised
+Gaussian over each voxel box, a product of per-axis erf differences (§III-A
+Eq. 2-5; value="box"), one channel per element type, truncated to a cube of
+half-width rc_t = fl32(k * sigma_t) around the atom, decided on the voxel
+centres (§VI-B threshold truncation), with the nearest-image offset for
+periodic orthorhombic cells (§III-A).
 """
 from __future__ import annotations
 
@@ -49,14 +52,17 @@ def _load():
         from .build import build
         build()
     lib = ctypes.CDLL(_LIB_PATH)
-    lib.pgo_grid.argtypes = _COMMON + [_dp, _i64p, _i64p]
+    lib.pgo_grid.argtypes = _COMMON + [ctypes.c_int, _dp, _i64p, _i64p]
     lib.pgo_grid.restype = ctypes.c_int
-    lib.pgo_grad.argtypes = _COMMON + [_dp, _dp]
+    lib.pgo_grad.argtypes = _COMMON + [ctypes.c_int, _dp, _dp]
     lib.pgo_grad.restype = ctypes.c_int
-    lib.pgo_voxels.argtypes = _COMMON + [ctypes.c_int64, _i64p, _dp]
+    lib.pgo_voxels.argtypes = _COMMON + [ctypes.c_int, ctypes.c_int64, _i64p, _dp]
     lib.pgo_voxels.restype = ctypes.c_int
     lib.pgo_count_evals.argtypes = _COMMON
     lib.pgo_count_evals.restype = ctypes.c_int64
+    lib.pgo_version.restype = ctypes.c_int
+    if lib.pgo_version() != 2:
+        raise ImportError(f"{_LIB_PATH} is stale: rebuild it with oracle/build.py")
     _lib = lib
     return lib
 
@@ -64,6 +70,9 @@ def _load():
 def _f32(v) -> np.ndarray:
     """float32-rounded values as float64."""
     return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+VALUES = {"point": 0, "box": 1}
 
 
 def _ptr(a: Optional[np.ndarray], t):
@@ -119,14 +128,16 @@ class _Args:
 
 
 def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3.0,
-              cell=None, origins=None, spacings=None, n_types=None, return_stats=False):
+              cell=None, origins=None, spacings=None, n_types=None, return_stats=False,
+              value="point"):
     """Dense FP64 grids, shape (B, C, D, H, W), x fastest."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
               origins, spacings, n_types)
     out = np.empty(a.shape, dtype=np.float64)
     ev = ctypes.c_int64(0)
     sk = ctypes.c_int64(0)
-    rc = _load().pgo_grid(*a.common(), _ptr(out, _dp), ctypes.byref(ev), ctypes.byref(sk))
+    rc = _load().pgo_grid(*a.common(), VALUES[value], _ptr(out, _dp), ctypes.byref(ev),
+                          ctypes.byref(sk))
     if rc != 0:
         raise MemoryError("pgo_grid failed")
     if return_stats:
@@ -135,26 +146,27 @@ def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3
 
 
 def grad_fp64(xyz, types, offsets, sigma, dims, spacing, U, origin=None, cutoff_k=3.0,
-              cell=None, origins=None, spacings=None, n_types=None):
+              cell=None, origins=None, spacings=None, n_types=None, value="point"):
     """dL/dxyz for L = sum(U * G), shape (n_atoms, 3) float64."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
               origins, spacings, n_types)
     u = np.ascontiguousarray(np.asarray(U, dtype=np.float64).reshape(a.shape))
     g = np.empty((a.xyz.shape[0], 3), dtype=np.float64)
-    rc = _load().pgo_grad(*a.common(), _ptr(u, _dp), _ptr(g, _dp))
+    rc = _load().pgo_grad(*a.common(), VALUES[value], _ptr(u, _dp), _ptr(g, _dp))
     if rc != 0:
         raise MemoryError("pgo_grad failed")
     return g
 
 
 def voxels_fp64(xyz, types, offsets, sigma, dims, spacing, idx, origin=None, cutoff_k=3.0,
-                cell=None, origins=None, spacings=None, n_types=None):
+                cell=None, origins=None, spacings=None, n_types=None, value="point"):
     """Grid values at sampled voxels; idx is (S, 5) rows of (b, c, z, y, x)."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
               origins, spacings, n_types)
     q = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 5))
     v = np.empty(q.shape[0], dtype=np.float64)
-    rc = _load().pgo_voxels(*a.common(), ctypes.c_int64(q.shape[0]), _ptr(q, _i64p), _ptr(v, _dp))
+    rc = _load().pgo_voxels(*a.common(), VALUES[value], ctypes.c_int64(q.shape[0]),
+                            _ptr(q, _i64p), _ptr(v, _dp))
     if rc != 0:
         raise ValueError("sample index out of range")
     return v

@@ -33,6 +33,15 @@
  *   in double -- NOT the separable product of 1-D factors (separability,
  *   §III-A and §IV-C, is checked by the tests, not assumed here).
  *
+ *   Box form (value = 1): the voxel holds the integral of the normalised
+ *   Gaussian over the voxel box (§III-A Eq. 2-5), i.e. the product over
+ *   axes of (1/2)[erf((x_i + h - mu) / (sqrt(2) sigma)) - erf((x_i - mu) /
+ *   (sqrt(2) sigma))] with x_i the lower voxel edge (the sign read so that
+ *   the value is positive), inside the same cutoff windows (decided on the
+ *   voxel centres).  Tails are evaluated through erfc to avoid cancellation.
+ *   Its coordinate gradient uses d/dmu of each axis factor,
+ *   (g(x_i - mu) - g(x_i + h - mu)) / (sqrt(2 pi) sigma), g = exp(-d^2 / (2 sigma^2)).
+ *
  *   Adjoint: for L = sum_v U[v] G[v], dL/dmu_{a,alpha} =
  *   sum_{v inside} U[t_a, v] * g_a(v) * (r_alpha - mu_alpha) / sigma_t^2,
  *   the derivative of the point-sampled Gaussian (the point-sample analogue
@@ -120,6 +129,26 @@ static double cutoff_radius(float k, float sigma)
     return (double)r;
 }
 
+/* (1/2)[erf(r / (sqrt 2 sigma)) - erf(l / (sqrt 2 sigma))] for l < r: the mass
+   of the normalised 1-D Gaussian between offsets l and r. */
+static double box1d(double l, double r, double sigma)
+{
+    const double s = 1.0 / (sqrt(2.0) * sigma);
+    const double a = l * s, b = r * s;
+    if (a >= 0.0)
+        return 0.5 * (erfc(a) - erfc(b));
+    if (b <= 0.0)
+        return 0.5 * (erfc(-b) - erfc(-a));
+    return 0.5 * (erf(b) - erf(a));
+}
+
+/* d/dmu of box1d(x_lo - mu, x_hi - mu). */
+static double dbox1d(double l, double r, double sigma)
+{
+    const double s2 = sigma * sigma;
+    return (exp(-l * l / (2.0 * s2)) - exp(-r * r / (2.0 * s2))) / (sqrt(2.0 * M_PI) * sigma);
+}
+
 typedef struct {
     int D, H, W, C;
     double o[3], h[3];
@@ -198,7 +227,7 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
              const double *origin3, const double *spacing3,
              const double *origins, const double *spacings,
              const float *sigma, float cutoff_k,
-             int periodic, const double *cell3,
+             int periodic, const double *cell3, int value,
              double *out, int64_t *evals, int64_t *skipped)
 {
     const size_t plane = (size_t)H * W, vol = (size_t)D * plane;
@@ -226,9 +255,15 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
                 for (int ky = 0; ky < w.n[1]; ++ky)
                     for (int kx = 0; kx < w.n[0]; ++kx) {
                         double dx = w.del[0][kx], dy = w.del[1][ky], dz = w.del[2][kz];
-                        double d2 = dx * dx + dy * dy + dz * dz;
+                        double v;
+                        if (value == 1)
+                            v = box1d(dx - 0.5 * g.h[0], dx + 0.5 * g.h[0], sigma[t]) *
+                                box1d(dy - 0.5 * g.h[1], dy + 0.5 * g.h[1], sigma[t]) *
+                                box1d(dz - 0.5 * g.h[2], dz + 0.5 * g.h[2], sigma[t]);
+                        else
+                            v = exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s2));
                         grid[(size_t)w.idx[2][kz] * plane + (size_t)w.idx[1][ky] * W + w.idx[0][kx]]
-                            += exp(-d2 / (2.0 * s2));
+                            += v;
                     }
             ev += (int64_t)w.n[0] * w.n[1] * w.n[2];
         }
@@ -250,7 +285,7 @@ int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
              const double *origin3, const double *spacing3,
              const double *origins, const double *spacings,
              const float *sigma, float cutoff_k,
-             int periodic, const double *cell3,
+             int periodic, const double *cell3, int value,
              const double *U, double *grad)
 {
     const size_t plane = (size_t)H * W, vol = (size_t)D * plane;
@@ -276,12 +311,24 @@ int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
                 for (int ky = 0; ky < w.n[1]; ++ky)
                     for (int kx = 0; kx < w.n[0]; ++kx) {
                         double dx = w.del[0][kx], dy = w.del[1][ky], dz = w.del[2][kz];
-                        double gval = exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s2));
                         double uv = u[(size_t)w.idx[2][kz] * plane + (size_t)w.idx[1][ky] * W + w.idx[0][kx]];
-                        double f = uv * gval / s2;
-                        gx += f * dx;
-                        gy += f * dy;
-                        gz += f * dz;
+                        if (value == 1) {
+                            const double sg = sigma[t];
+                            const double lx = dx - 0.5 * g.h[0], rx = dx + 0.5 * g.h[0];
+                            const double ly = dy - 0.5 * g.h[1], ry = dy + 0.5 * g.h[1];
+                            const double lz = dz - 0.5 * g.h[2], rz = dz + 0.5 * g.h[2];
+                            const double bx = box1d(lx, rx, sg), by = box1d(ly, ry, sg),
+                                         bz = box1d(lz, rz, sg);
+                            gx += uv * dbox1d(lx, rx, sg) * by * bz;
+                            gy += uv * bx * dbox1d(ly, ry, sg) * bz;
+                            gz += uv * bx * by * dbox1d(lz, rz, sg);
+                        } else {
+                            double gval = exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s2));
+                            double f = uv * gval / s2;
+                            gx += f * dx;
+                            gy += f * dy;
+                            gz += f * dz;
+                        }
                     }
             grad[3 * a + 0] = gx;
             grad[3 * a + 1] = gy;
@@ -304,7 +351,7 @@ int pgo_voxels(int B, const int64_t *offsets, const double *xyz, const int32_t *
                const double *origin3, const double *spacing3,
                const double *origins, const double *spacings,
                const float *sigma, float cutoff_k,
-               int periodic, const double *cell3,
+               int periodic, const double *cell3, int value,
                int64_t n_samples, const int64_t *idx, double *val)
 {
     for (int64_t s = 0; s < n_samples; ++s) {
@@ -330,8 +377,14 @@ int pgo_voxels(int B, const int64_t *offsets, const double *xyz, const int32_t *
             for (int ax = 0; ax < 3 && inside; ++ax)
                 inside = axis_offset(g.o[ax], g.h[ax], vi[ax], mu[ax], g.periodic,
                                      g.L[ax], g.cut, g.rc, &d[ax]);
-            if (inside)
-                acc += exp(-(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / (2.0 * s2));
+            if (inside) {
+                if (value == 1)
+                    acc += box1d(d[0] - 0.5 * g.h[0], d[0] + 0.5 * g.h[0], sigma[c]) *
+                           box1d(d[1] - 0.5 * g.h[1], d[1] + 0.5 * g.h[1], sigma[c]) *
+                           box1d(d[2] - 0.5 * g.h[2], d[2] + 0.5 * g.h[2], sigma[c]);
+                else
+                    acc += exp(-(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / (2.0 * s2));
+            }
         }
         val[s] = acc;
     }
@@ -368,4 +421,4 @@ int64_t pgo_count_evals(int B, const int64_t *offsets, const double *xyz, const 
     return ev;
 }
 
-int pgo_version(void) { return 1; }
+int pgo_version(void) { return 2; }
