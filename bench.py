@@ -1,7 +1,7 @@
 """Benchmark of the atoms -> density-grid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mol4096]
-                    [--no-cpu] [--no-baseline]
+                    [--value point|box] [--no-cpu] [--no-baseline]
 
 A step is one pass of the forward hot path over one batch: inputs are
 staged in HBM once, then each step runs the per-atom window bounds and 1-D
@@ -21,6 +21,8 @@ Workloads (synth.WORKLOADS):
                0.16 A: bf16 (MFMA plane kernel) beside the fp32 vector form;
   adjoint1024  the coordinate gradient of 1024 molecules, 32^3 x 5 fp32
                upstream.
+--value box measures the box form (each voxel holds the normalised
+Gaussian's mass inside it) instead of the point-sampled Gaussian.
 The FP64 CPU oracle is timed on a bounded sample of the same workload, one
 thread and a thread pool (the oracle releases the GIL).
 """
@@ -187,6 +189,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="mol4096", choices=sorted(METRICS))
+    ap.add_argument("--value", default="point", choices=("point", "box"),
+                    help="voxel value: the Gaussian at the centre, or its mass in the voxel")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain fp32 baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -233,13 +237,15 @@ def main():
     ctx.set_option(pg.PG_OPT_GRAPH, 0 if args.no_graph else 1)
     launch = "direct launch" if args.no_graph else "HIP graph"
     extra = {}
-    rec = {"metric": METRICS[wl.name], "unit": "grids/s", "n_gpus": 1, "steps": args.steps,
+    value = args.value
+    metric = METRICS[wl.name] + (" [box form]" if value == "box" else "")
+    rec = {"metric": metric, "unit": "grids/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
 
     def forward_case(out_dt, form, autotune, steps, warmup):
         desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
-                            out_dt, form)
+                            out_dt, form, value)
         out = pg.empty_grid(desc, B, dev)
         if autotune and not args.no_autotune:
             log(f"[bench] autotuning {form} {out_dt}")
@@ -260,7 +266,7 @@ def main():
 
     if wl.name == "adjoint1024":
         desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
-                            torch.float32, "auto")
+                            torch.float32, "auto", value)
         U = torch.tensor(synth.upstream(wl.upstream_seed, wl.grid_shape()), device=dev)
         gxyz = torch.empty_like(xyz)
         wall, ev = timed_steps(lambda: ctx.backward(desc, bv, U, gxyz, stream), args.steps,
@@ -321,7 +327,7 @@ def main():
             if not args.no_baseline:
                 ctx_p = pg.Context(0)
                 descp = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k,
-                                     wl.cell, torch.float32, "plain")
+                                     wl.cell, torch.float32, "plain", value)
                 outp = pg.empty_grid(descp, B, dev)
                 wp, ep = timed_steps(lambda: ctx_p.forward(descp, bv, outp, stream), 3, 1, torch,
                                      stream)
@@ -334,7 +340,7 @@ def main():
         if args.save_tuning:
             ctx.tuning_save(args.save_tuning)
         traffic = None
-        if wl.kind != "crystal":
+        if wl.kind != "crystal" and value == "point":
             traffic = measured_traffic(f"window_{wl.name}_{'bf16' if esize == 2 else 'f32'}",
                                        source_digest(WINDOW_SOURCES))
         rec.update({
@@ -358,7 +364,7 @@ def main():
         desc_w = (f"{wl.name}: {B} molecules of {wl.atoms[0]}-{wl.atoms[1]} atoms "
                   f"(H/C/N/O/F p=0.5/0.3/0.1/0.08/0.02, {wl.box:g} A box)")
     rec["config"] = {"workload": f"{desc_w}, {C}x{D}x{H}x{W} grid at {wl.spacing} A, cutoff "
-                                 f"{wl.cutoff_k:g} sigma, {kind}, {launch}",
+                                 f"{wl.cutoff_k:g} sigma, {kind}, {value} form, {launch}",
                      "batch": B, "grid": [C, D, H, W], "n_atoms": int(b.n_atoms),
                      "evals_per_pass": evals}
     if kind == "forward":
@@ -377,13 +383,14 @@ def main():
             def run_one(u):
                 m, s = u
                 cpu_oracle.grad_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
-                                     Uh[m:m + s.n_mol], wl.origin, cutoff_k=wl.cutoff_k)
+                                     Uh[m:m + s.n_mol], wl.origin, cutoff_k=wl.cutoff_k,
+                                     value=value)
                 return s.n_mol
         else:
             def run_one(u):
                 s = u[1]
                 cpu_oracle.grid_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
-                                     wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell)
+                                     wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell, value=value)
                 return s.n_mol
         cpu_units = units
         log(f"[bench] FP64 CPU oracle on a bounded sample (~{args.cpu_seconds:.0f} s)")

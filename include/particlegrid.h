@@ -7,7 +7,9 @@
  * spacing, dimensions), produce a dense multi-channel grid
  *
  *     G[b][c][z][y][x] = sum over atoms a of structure b with type c of
- *                        exp(-|r(z,y,x) - mu_a|^2 / (2 sigma_c^2)),
+ *                        exp(-|r(z,y,x) - mu_a|^2 / (2 sigma_c^2))
+ *
+ * (or, with desc->value = PG_VALUE_BOX, the voxel integral of Eq. 2-5),
  *
  * with r the voxel centre origin + (i + 1/2) * spacing on each axis, one
  * channel per element type (§III-A), the squared distance replaced by the
@@ -15,8 +17,7 @@
  * after Eq. 1), and each atom truncated to a cube of half-width
  * rc_t = fl32(cutoff_k * sigma_t) (threshold truncation, §VI-B): a voxel
  * is inside iff |r_alpha - mu_alpha| <= rc_t on every axis, decided exactly
- * on the float inputs.  The Gaussian is the un-normalised point sample at
- * the voxel centre (the paper's Eq. 2-5 voxel integral is not this call).
+ * on the float inputs.
  *
  * Conventions shared by every call:
  *   - Layout: out is B x C x D x H x W, contiguous, x fastest (D = z,
@@ -50,7 +51,7 @@
 extern "C" {
 #endif
 
-#define PG_ABI_VERSION 1
+#define PG_ABI_VERSION 2
 #define PG_MAX_CHANNELS 64
 
 typedef enum pg_status {
@@ -67,6 +68,16 @@ typedef enum pg_status {
 } pg_status;
 
 enum { PG_OUT_F32 = 0, PG_OUT_BF16 = 1 };
+
+/* What a voxel holds.  POINT: the un-normalised Gaussian exp(-|r - mu|^2 /
+   (2 sigma^2)) sampled at the voxel centre (§III-A Eq. 1 without the
+   prefactor).  BOX: the integral of the normalised Gaussian over the voxel
+   box (§III-A Eq. 2-5), the product over axes of
+   (1/2)[erf((x_i + h - mu) / (sqrt(2) sigma)) - erf((x_i - mu) / (sqrt(2) sigma))]
+   with x_i the lower voxel edge; a channel then sums to its atom count
+   (Eq. 6) up to the cutoff.  Both use the same cutoff windows, decided on
+   the voxel centres. */
+enum { PG_VALUE_POINT = 0, PG_VALUE_BOX = 1 };
 
 /* Kernel form.  AUTO lets the library choose (per-shape rule, refined by
    pg_autotune).  PLAIN: one thread per voxel, one launch per structure (the
@@ -99,6 +110,7 @@ typedef struct pg_grid_desc {
     int32_t out_dtype;           /* PG_OUT_F32 or PG_OUT_BF16 (round-to-nearest-even) */
     int32_t form;                /* PG_FORM_* */
     float sigma[PG_MAX_CHANNELS];/* Gaussian width (standard deviation) per channel, > 0 */
+    int32_t value;               /* PG_VALUE_POINT or PG_VALUE_BOX */
 } pg_grid_desc;
 
 /* A ragged batch of structures (device arrays unless noted). */

@@ -35,6 +35,7 @@ PG_E_WORKSPACE, PG_E_UNSUPPORTED, PG_E_HIP, PG_E_DEVICE_DATA, PG_E_CAPACITY = 5,
 PG_OUT_F32, PG_OUT_BF16 = 0, 1
 FORMS = {"auto": 0, "plain": 1, "window": 2, "mfma": 3}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
+VALUES = {"point": 0, "box": 1}
 PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL = 1, 2, 3, 4, 5
 MAX_CHANNELS = 64
 
@@ -52,7 +53,8 @@ class GridDesc(ctypes.Structure):
                 ("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3),
                 ("cutoff_k", ctypes.c_float), ("periodic", ctypes.c_int32),
                 ("cell", ctypes.c_float * 3), ("out_dtype", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("sigma", ctypes.c_float * MAX_CHANNELS)]
+                ("form", ctypes.c_int32), ("sigma", ctypes.c_float * MAX_CHANNELS),
+                ("value", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
@@ -130,9 +132,11 @@ def _f3(v) -> Tuple[float, float, float]:
 
 def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigma=(),
               cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32,
-              form: Union[str, int] = "auto") -> GridDesc:
+              form: Union[str, int] = "auto", value: Union[str, int] = "point") -> GridDesc:
     """Build a pg_grid_desc (host struct).  dims = (D, H, W) = (z, y, x);
-    origin / spacing / cell in x, y, z order; sigma one value per channel."""
+    origin / spacing / cell in x, y, z order; sigma one value per channel;
+    value "point" (the Gaussian at voxel centres) or "box" (the normalised
+    Gaussian's mass in each voxel)."""
     d = GridDesc()
     d.C = int(C)
     d.D, d.H, d.W = (int(x) for x in dims)
@@ -148,6 +152,7 @@ def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigm
     else:
         raise ValueError(f"unsupported out_dtype {out_dtype}")
     d.form = FORMS[form] if isinstance(form, str) else int(form)
+    d.value = VALUES[value] if isinstance(value, str) else int(value)
     sig = [float(s) for s in sigma]
     if len(sig) > MAX_CHANNELS:
         raise ValueError(f"at most {MAX_CHANNELS} channels")
@@ -339,15 +344,15 @@ class GridFn(torch.autograd.Function):
 def grid(xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor, sigma: Sequence[float], *,
          dims: Sequence[int], spacing=0.5, origin=(0.0, 0.0, 0.0), origins=None, spacings=None,
          cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32, form: str = "auto",
-         n_channels: Optional[int] = None, max_atoms: Optional[int] = None,
-         ctx: Optional[Context] = None) -> torch.Tensor:
+         value: str = "point", n_channels: Optional[int] = None,
+         max_atoms: Optional[int] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """Density grids (B, C, D, H, W) for a ragged batch (differentiable in xyz).
 
     xyz (n_atoms, 3) float32, types (n_atoms,) int, offsets (B+1,) int CSR,
     all on the same device; sigma: one width per channel (C = len(sigma)
-    unless n_channels is given)."""
+    unless n_channels is given); value "point" or "box" as in make_desc."""
     C = int(n_channels if n_channels is not None else len(sigma))
-    desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form)
+    desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form, value)
     pgctx = ctx if ctx is not None else default_context(xyz.device)
     return GridFn.apply(xyz, types, offsets, origins, spacings, desc, max_atoms, pgctx)
 

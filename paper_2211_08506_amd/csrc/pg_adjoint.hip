@@ -1,11 +1,13 @@
 // pg_adjoint.hip -- coordinate adjoint of the density grid on gfx950.
 //
-// For L = sum_v U[v] G[v] and the point-sampled Gaussian of §III-A Eq. 1,
-//   dL/dmu_{a,alpha} = sum_{v in window(a)} U[b, t_a, v] g_a(v) d_alpha(v) / sigma^2,
-// with d = r - mu (nearest image when periodic) and g_a the atom's
-// separable Gaussian.  This is the point-sample counterpart of the
-// separable coordinate gradient of §IV-C (chain rule through the product
-// of per-axis factors); the cutoff edge contributes nothing (the map is
+// For L = sum_v U[v] G[v] with G the product of per-axis factors
+// phi_x phi_y phi_z (the point-sampled Gaussian of §III-A Eq. 1, or the
+// voxel masses of Eq. 2-5),
+//   dL/dmu_{a,x} = sum_{v in window(a)} U[b, t_a, v] phi_x'(v) phi_y(v) phi_z(v),
+// and likewise for y and z -- the separable coordinate gradient of §IV-C.
+// For the point sample phi' = phi d / sigma^2 (d = r - mu, nearest image
+// when periodic); for the box, phi' = (g(lower edge) - g(upper edge)) /
+// (sqrt(2 pi) sigma).  The cutoff edge contributes nothing (the map is
 // differentiable almost everywhere).
 //
 // One wave per atom, any structure size: the wave builds its atom's 1-D
@@ -35,11 +37,11 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     const long long a = (long long)blockIdx.x * waves + wave;
     const bool active = a < p.n_atoms;
     const int NT = p.W + p.H + p.D;
-    // per-wave slice: idx[NT] (int) | phi[NT] | del[NT] | 3 range records
+    // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | 3 range records
     int *idx = (int *)(smem + (size_t)wave * (NT * 12 + 3 * sizeof(AxisRanges)));
     float *phi = (float *)(idx + NT);
-    float *del = phi + NT;
-    AxisRanges *rg = (AxisRanges *)(del + NT);
+    float *dphi = phi + NT;
+    AxisRanges *rg = (AxisRanges *)(dphi + NT);
     const int base[3] = {0, p.W, p.W + p.H};
     const int N[3] = {p.W, p.H, p.D};   // indexed by the compile-time axis only
 
@@ -82,10 +84,11 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                 const int len = R.hi[r] - R.lo[r] + 1;
                 for (int k = lane; k < len; k += 64) {
                     const int i = R.lo[r] + k;
-                    const float d = offset_at(R.bh[r], R.bl[r], h[q], i);
                     idx[base[q] + k0 + k] = i;
-                    del[base[q] + k0 + k] = d;
-                    phi[base[q] + k0 + k] = gauss1d(d, p.inv2s2[t]);
+                    phi[base[q] + k0 + k] = factor1d(p.box != 0, R.bh[r], R.bl[r], h[q], i,
+                                                     p.inv2s2[t], p.isq2s[t]);
+                    dphi[base[q] + k0 + k] = dfactor1d(p.box != 0, R.bh[r], R.bl[r], h[q], i,
+                                                       p.inv2s2[t], p.invs2[t], p.inorm[t]);
                 }
                 k0 += len;
             }
@@ -107,20 +110,19 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
             const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
             const float u = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
             const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
-            const float w = u * (fx * fy * fz);
-            gx = __builtin_fmaf(w, del[kx], gx);
-            gy = __builtin_fmaf(w, del[base[1] + ky], gy);
-            gz = __builtin_fmaf(w, del[base[2] + kz], gz);
+            const float dx = dphi[kx], dy = dphi[base[1] + ky], dz = dphi[base[2] + kz];
+            gx = __builtin_fmaf(u, dx * (fy * fz), gx);
+            gy = __builtin_fmaf(u, fx * (dy * fz), gy);
+            gz = __builtin_fmaf(u, (fx * fy) * dz, gz);
         }
     }
     gx = wave_sum(gx);
     gy = wave_sum(gy);
     gz = wave_sum(gz);
     if (active && lane == 0) {
-        const float s = t >= 0 ? p.invs2[t] : 0.f;
-        p.grad_xyz[3 * a + 0] = gx * s;
-        p.grad_xyz[3 * a + 1] = gy * s;
-        p.grad_xyz[3 * a + 2] = gz * s;
+        p.grad_xyz[3 * a + 0] = t >= 0 ? gx : 0.f;
+        p.grad_xyz[3 * a + 1] = t >= 0 ? gy : 0.f;
+        p.grad_xyz[3 * a + 2] = t >= 0 ? gz : 0.f;
     }
 }
 

@@ -119,6 +119,8 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
         return PG_E_PARAM;
     if (d->form < PG_FORM_AUTO || d->form > PG_FORM_MFMA)
         return PG_E_PARAM;
+    if (d->value != PG_VALUE_POINT && d->value != PG_VALUE_BOX)
+        return PG_E_PARAM;
     for (int q = 0; q < 3; ++q) {
         if (!finite_pos(d->spacing[q]) || !std::isfinite(d->origin[q]))
             return PG_E_PARAM;
@@ -244,8 +246,9 @@ std::string tuning_key(const pg_grid_desc *d, const pg_batch *b, int vec)
     while (ma < b->max_atoms)
         ma <<= 1;
     char buf[160];
-    std::snprintf(buf, sizeof buf, "C%d_D%d_H%d_W%d_%s_p%d_v%d_nb%d_ma%d", d->C, d->D, d->H,
-                  d->W, d->out_dtype == PG_OUT_BF16 ? "bf16" : "f32", d->periodic, vec, nb, ma);
+    std::snprintf(buf, sizeof buf, "C%d_D%d_H%d_W%d_%s_p%d_v%d_nb%d_ma%d%s", d->C, d->D, d->H,
+                  d->W, d->out_dtype == PG_OUT_BF16 ? "bf16" : "f32", d->periodic, vec, nb, ma,
+                  d->value == PG_VALUE_BOX ? "_box" : "");
     return buf;
 }
 
@@ -381,7 +384,10 @@ void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const 
         p.rc[c] = rc_of(d, c);
         p.inv2s2[c] = (float)(1.0 / (2.0 * s * s));
         p.invs2[c] = (float)(1.0 / (s * s));
+        p.isq2s[c] = (float)(1.0 / (std::sqrt(2.0) * s));
+        p.inorm[c] = (float)(1.0 / (std::sqrt(2.0 * M_PI) * s));
     }
+    p.box = d->value == PG_VALUE_BOX;
 }
 
 hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, GridParams &p,

@@ -367,18 +367,19 @@ __global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalPa
     if (k >= (long long)q.ecount[mc])
         return;
     const AtomWindow &w = q.table[q.zlist[32 * b0 + k].atom];
-    const float inv2s2 = p.inv2s2[c];
+    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c];
+    const bool box = p.box != 0;
     uint16_t *xo = q.xop + (size_t)gb * W * 32 + kl;
     uint16_t *yo = q.yop + (size_t)gb * H * 32 + kl;
     for (int r = 0; r < w.n[0]; ++r) {
         const float bh = w.bh[0][r], bl = w.bl[0][r];
         for (int v = w.lo[0][r] + rg; v <= w.hi[0][r]; v += 8)
-            xo[(size_t)v * 32] = bf16_bits(gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2));
+            xo[(size_t)v * 32] = bf16_bits(factor1d(box, bh, bl, p.h[0], v, inv2s2, isq2s));
     }
     for (int r = 0; r < w.n[1]; ++r) {
         const float bh = w.bh[1][r], bl = w.bl[1][r];
         for (int v = w.lo[1][r] + rg; v <= w.hi[1][r]; v += 8)
-            yo[(size_t)v * 32] = bf16_bits(gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2));
+            yo[(size_t)v * 32] = bf16_bits(factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s));
     }
 }
 
@@ -419,14 +420,14 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
         nkb = 0;
     }
     const long long rb = run_block(q, mc);
-    const float inv2s2 = p.inv2s2[c], hz = p.h[2];
+    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c], hz = p.h[2];
     for (int i = tid; i < nkb * 32; i += blockDim.x) {
         const uint32_t k = (uint32_t)kb0 * 32 + i;
         float g = 0.f;
         if (k < n_img) {
             const ZEntry ze = q.zlist[32 * rb + k];
             if (z >= range_lo(ze.range) && z <= range_hi(ze.range))
-                g = gauss1d(offset_at(ze.bh, ze.bl, hz, z), inv2s2);
+                g = factor1d(p.box != 0, ze.bh, ze.bl, hz, z, inv2s2, isq2s);
         }
         gzs[i] = g;
     }
@@ -552,7 +553,8 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
     const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
     const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
     const long long eb = 32ll * run_block(q, mc);
-    const float inv2s2 = p.inv2s2[c];
+    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c];
+    const bool box = p.box != 0;
     const int ly = 4 * (lane >> 3), lx = 4 * (lane & 7);
     float acc[TMAX][4][4];
 #pragma unroll
@@ -576,7 +578,7 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
             if (k < kn) {
                 const ZEntry ze = q.zlist[eb + k0 + k];
                 if (z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
-                    const float g = gauss1d(offset_at(ze.bh, ze.bl, p.h[2], z), inv2s2);
+                    const float g = factor1d(box, ze.bh, ze.bl, p.h[2], z, inv2s2, isq2s);
                     const AtomWindow &w = q.table[ze.atom];
                     uint32_t tx = 0u, ty = 0u;   // tile columns / rows the windows meet
                     for (int r = 0; r < w.n[0]; ++r) {
@@ -584,14 +586,14 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
                         for (int t = w.lo[0][r] >> 5; t <= (w.hi[0][r] >> 5); ++t)
                             tx |= 1u << t;
                         for (int v = w.lo[0][r] + part; v <= w.hi[0][r]; v += 8)
-                            gx[k * W32 + v] = gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2);
+                            gx[k * W32 + v] = factor1d(box, bh, bl, p.h[0], v, inv2s2, isq2s);
                     }
                     for (int r = 0; r < w.n[1]; ++r) {
                         const float bh = w.bh[1][r], bl = w.bl[1][r];
                         for (int t = w.lo[1][r] >> 5; t <= (w.hi[1][r] >> 5); ++t)
                             ty |= 1u << t;
                         for (int v = w.lo[1][r] + part; v <= w.hi[1][r]; v += 8)
-                            gy[k * H32 + v] = g * gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2);
+                            gy[k * H32 + v] = g * factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s);
                     }
                     if (part == 0)
                         for (int tr = 0; tr < nty; ++tr)

@@ -218,6 +218,52 @@ __device__ __forceinline__ float gauss1d(float d, float inv2s2)
     return expf(-(d * d) * inv2s2);
 }
 
+// Offset of the lower edge of voxel i from the atom, o + i h - mu (- n L),
+// from the float-float base, rounded once.
+__device__ __forceinline__ float edge_at(float bh, float bl, float h, int i)
+{
+    float p, pe;
+    two_prod((float)i, h, p, pe);
+    float s, e;
+    two_sum(bh, p, s, e);
+    return s + ((e + pe) + bl);
+}
+
+// Mass of the normalised 1-D Gaussian between edge offsets l < r:
+// (1/2)[erf(r s) - erf(l s)], s = 1 / (sqrt(2) sigma); on a tail the
+// complementary form, so the difference does not cancel.
+__device__ __forceinline__ float box1d(float l, float r, float isq2s)
+{
+    const float a = l * isq2s, b = r * isq2s;
+    if (a >= 0.f)
+        return 0.5f * (erfcf(a) - erfcf(b));
+    if (b <= 0.f)
+        return 0.5f * (erfcf(-b) - erfcf(-a));
+    return 0.5f * (erff(b) - erff(a));
+}
+
+// The value of window element i on one axis: the point sample at the voxel
+// centre, or (box) the voxel's Gaussian mass.
+__device__ __forceinline__ float factor1d(bool box, float bh, float bl, float h, int i,
+                                          float inv2s2, float isq2s)
+{
+    if (box)
+        return box1d(edge_at(bh, bl, h, i), edge_at(bh, bl, h, i + 1), isq2s);
+    return gauss1d(offset_at(bh, bl, h, i), inv2s2);
+}
+
+// d/dmu of factor1d: point, g(d) d / sigma^2; box, (g(l) - g(r)) / (sqrt(2 pi) sigma).
+__device__ __forceinline__ float dfactor1d(bool box, float bh, float bl, float h, int i,
+                                           float inv2s2, float invs2, float inorm)
+{
+    if (box) {
+        const float l = edge_at(bh, bl, h, i), r = edge_at(bh, bl, h, i + 1);
+        return (gauss1d(l, inv2s2) - gauss1d(r, inv2s2)) * inorm;
+    }
+    const float d = offset_at(bh, bl, h, i);
+    return gauss1d(d, inv2s2) * d * invs2;
+}
+
 // ---------------------------------------------------------------------------
 // Output conversion and vector stores
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ struct DeviceError {
 
 // Everything a forward / backward launch needs.  Per-channel constants are
 // precomputed on the host: rc = fl32(k * sigma), inv2s2 = fl32(1/(2 sigma^2)),
-// invs2 = fl32(1/sigma^2).
+// invs2 = fl32(1/sigma^2), and for the box form isq2s, inorm.
 struct GridParams {
     const float *xyz;
     const int32_t *types;
@@ -43,6 +43,9 @@ struct GridParams {
     float rc[PG_MAX_CHANNELS];
     float inv2s2[PG_MAX_CHANNELS];
     float invs2[PG_MAX_CHANNELS];
+    int32_t box;             // voxel integral (PG_VALUE_BOX) instead of the point sample
+    float isq2s[PG_MAX_CHANNELS];   // fl32(1 / (sqrt(2) sigma)), box form
+    float inorm[PG_MAX_CHANNELS];   // fl32(1 / (sqrt(2 pi) sigma)), box-form derivative
 };
 
 // Per-atom window table written by the prep kernel (plain form).

@@ -5,7 +5,8 @@
 // plain: one launch per structure, one thread per output element; each
 //        thread visits every atom of its structure, tests the three axis
 //        windows and adds the 3-D Gaussian exp(-|r - mu|^2 / (2 sigma^2))
-//        (§III-A Eq. 1, point-sampled, without the prefactor).  This is the
+//        (§III-A Eq. 1, point-sampled, without the prefactor), or for the box
+//        form the product of the three per-axis voxel masses.  This is the
 //        straightforward GPU transcription of the definition; the batched
 //        window kernel is measured against it.
 #include "pg_device.hpp"
@@ -43,26 +44,33 @@ __global__ void __launch_bounds__(256) plain_kernel(GridParams p)
     int a0 = p.offsets[m], a1 = p.offsets[m + 1];
     if (a0 < 0 || a1 < a0 || (long long)a1 > p.n_atoms)
         a0 = a1 = 0;   // malformed offsets: nothing is read
-    const float inv2s2 = p.inv2s2[c];
+    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c];
+    const bool box = p.box != 0;
     float acc = 0.f;
     for (int a = a0; a < a1; ++a) {
         if (tab[a].type != c)
             continue;
-        float d2 = 0.f;
+        float d2 = 0.f, mass = 1.f;
         bool inside = true;
         for (int q = 0; q < 3 && inside; ++q) {
             bool hit = false;
             for (int r = 0; r < tab[a].n[q]; ++r) {
                 if (idx[q] >= tab[a].lo[q][r] && idx[q] <= tab[a].hi[q][r]) {
-                    const float d = offset_at(tab[a].bh[q][r], tab[a].bl[q][r], h[q], idx[q]);
-                    d2 = __builtin_fmaf(d, d, d2);
+                    const float bh = tab[a].bh[q][r], bl = tab[a].bl[q][r];
+                    if (box) {
+                        mass *= box1d(edge_at(bh, bl, h[q], idx[q]), edge_at(bh, bl, h[q], idx[q] + 1),
+                                      isq2s);
+                    } else {
+                        const float d = offset_at(bh, bl, h[q], idx[q]);
+                        d2 = __builtin_fmaf(d, d, d2);
+                    }
                     hit = true;
                 }
             }
             inside = hit;
         }
         if (inside)
-            acc += expf(-d2 * inv2s2);
+            acc += box ? mass : expf(-d2 * inv2s2);
     }
     const float v[1] = {acc};
     store_vec<T, 1>((T *)p.out + (size_t)m * p.C * vol + e, v, false);

@@ -178,7 +178,8 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                 const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
                 for (int r = 0; r < R.n; ++r) {
                     if (i >= R.lo[r] && i <= R.hi[r]) {
-                        v = gauss1d(offset_at(R.bh[r], R.bl[r], hq, i), p.inv2s2[t]);
+                        v = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[t],
+                                     p.isq2s[t]);
                         if (ax == 2)
                             atomicOr(&masks[(size_t)(t * D + i) * MW + (a >> 6)], 1ull << (a & 63));
                     }

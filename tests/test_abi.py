@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_abi_version_and_status_strings():
-    assert pg.abi_version() == 1
+    assert pg.abi_version() == 2
     lib = pg._lib()
     for s in range(0, 10):
         assert lib.pg_status_str(s)
@@ -40,7 +40,7 @@ def desc_ok(**kw):
     d = pg.make_desc(kw.pop("C", 5), kw.pop("dims", (32, 32, 32)), kw.pop("spacing", 0.5),
                      kw.pop("origin", (-8, -8, -8)), kw.pop("sigma", [0.4, 0.475, 0.55, 0.625, 0.7]),
                      kw.pop("cutoff_k", 3.0), kw.pop("cell", None), kw.pop("out_dtype", "f32"),
-                     kw.pop("form", "auto"))
+                     kw.pop("form", "auto"), kw.pop("value", "point"))
     assert not kw
     return d
 
@@ -66,6 +66,7 @@ def test_validate_accepts_good_request():
     assert validate(desc_ok(), batch_ok()) == pg.PG_OK
     assert validate(desc_ok(out_dtype="bf16"), batch_ok()) == pg.PG_OK
     assert validate(desc_ok(cutoff_k=0.0), batch_ok()) == pg.PG_OK
+    assert validate(desc_ok(value="box"), batch_ok()) == pg.PG_OK
     assert validate(desc_ok(), batch_ok(n_mol=0, n_atoms=0, max_atoms=0)) == pg.PG_OK
 
 
@@ -73,7 +74,7 @@ def test_validate_accepts_good_request():
     ("C", 0, pg.PG_E_SHAPE), ("C", 65, pg.PG_E_SHAPE), ("D", 0, pg.PG_E_SHAPE),
     ("W", -3, pg.PG_E_SHAPE), ("cutoff_k", -1.0, pg.PG_E_PARAM),
     ("cutoff_k", float("nan"), pg.PG_E_PARAM), ("out_dtype", 7, pg.PG_E_PARAM),
-    ("form", 9, pg.PG_E_PARAM),
+    ("form", 9, pg.PG_E_PARAM), ("value", 2, pg.PG_E_PARAM), ("value", -1, pg.PG_E_PARAM),
 ])
 def test_validate_rejects_bad_desc(field, value, code):
     d = desc_ok()
