@@ -11,6 +11,8 @@ Functions:
   count_evals number of atom-voxel pairs inside the cutoff windows
   brute_fp64  all-voxels x all-atoms NumPy form with exact rational edge
               decisions, for tiny grids (brute.py)
+  reversal    grid reversal of §IV: local-maximum peaks and the coordinate
+              descent step on the squared grid error (reversal.py)
 
 What is computed is the point-sampled, un-normalised Gaussian of §III-A
 Eq. 1 at voxel centres (value="point"), or the integral of the normalised
