@@ -156,7 +156,8 @@ int pg_validate(const pg_grid_desc *desc, const pg_batch *batch);
 int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
                       size_t *bytes);
 
-/* Forward map (§III-A Eq. 1 point-sampled, §V coord_to_grid): writes every
+/* Forward map (§III-A Eq. 1 point-sampled, or the voxel masses of Eq. 2-5
+   under PG_VALUE_BOX; §V coord_to_grid): writes every
    element of out (B x C x D x H x W of float32 or bf16 per
    desc->out_dtype, 16-byte aligned for the vector path; any alignment is
    accepted).  ws/ws_bytes: device workspace of at least
@@ -167,11 +168,14 @@ int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batc
 int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
                     void *out, void *ws, size_t ws_bytes, void *stream);
 
-/* Adjoint (§IV-C coordinate gradient, for the point-sampled form): given
-   grad_out = dL/dG (same shape and dtype as the forward's out), writes
-   grad_xyz[a][alpha] = sum over voxels v in the window of atom a of
-   grad_out[b][t_a][v] * g_a(v) * (r_alpha(v) - mu_alpha) / sigma_t^2,
-   with nearest-image offsets when periodic.  The cutoff edge contributes
+/* Adjoint (§IV-C coordinate gradient): given grad_out = dL/dG (same shape
+   and dtype as the forward's out), writes grad_xyz[a][alpha] = sum over
+   voxels v in the window of atom a of grad_out[b][t_a][v] * dG_a(v)/dmu_alpha,
+   G_a being the product of per-axis factors phi_x phi_y phi_z.  Point form:
+   dphi/dmu = phi (r - mu) / sigma_t^2, with nearest-image offsets when
+   periodic.  Box form: dphi/dmu = (g(lower edge) - g(upper edge)) /
+   (sqrt(2 pi) sigma_t), g(x) = exp(-(x - mu)^2 / (2 sigma_t^2)) -- the erf
+   derivative of §IV-C with the minus of its exponent restored.  The cutoff edge contributes
    nothing (derivative almost everywhere).  grad_xyz: n_atoms x 3 float32,
    fully overwritten (skipped atoms get 0).
    Errors: as pg_grid_forward. */
@@ -228,6 +232,60 @@ typedef struct pg_plan_info {
 } pg_plan_info;
 int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
             const void *out, pg_plan_info *info);
+
+/* ---- Grid reversal (§IV): coordinates back from a grid ---------------- */
+
+/* Initial coordinates of grid reversal (§IV-A step 1; §IV-B locates atoms
+   as the grid's local maxima).  grid: B x C x D x H x W float32 (device,
+   the layout of pg_grid_forward's output); desc supplies C, D, H, W,
+   origin and spacing (other fields are not read) and must have out_dtype
+   PG_OUT_F32.  Voxel v of channel c is a peak when grid[v] > threshold and,
+   among its 26 neighbours inside the grid (same channel, no wrap), grid[v]
+   is greater than every neighbour earlier in raster order (z, then y, then
+   x) and not less than any later one, so a plateau of equal maxima yields
+   its first voxel.  The peaks of structure b are written in raster order
+   (channel, z, y, x) from index offsets_out[b] on: xyz_out (capacity x 3
+   float32) receives the voxel centre o + (i + 1/2) h evaluated in double
+   and rounded once to float32 (o, h from origins / spacings, B x 3 device
+   arrays, when not NULL, else from desc), types_out (capacity int32) the
+   channel.  offsets_out (B + 1 int32, device) receives the CSR bounds, each
+   clamped to capacity; *n_found (device int64) the total number of peaks,
+   which may exceed capacity (peaks past capacity are not written).  The
+   outputs form the pg_batch of pg_reversal_step.  Asynchronous on stream;
+   no workspace.
+   Errors: PG_E_NULL, PG_E_SHAPE (bad dims, capacity outside [0, 2^31), a
+   structure of 2^31 or more elements), PG_E_PARAM (non-finite threshold,
+   out_dtype not F32, bad origin or spacing), PG_E_HIP. */
+int pg_find_peaks(pg_ctx *ctx, const pg_grid_desc *desc, const float *grid, int32_t n_mol,
+                  const float *origins, const float *spacings, float threshold, int64_t capacity,
+                  float *xyz_out, int32_t *types_out, int32_t *offsets_out, int64_t *n_found,
+                  void *stream);
+
+/* Bytes of caller-provided device workspace pg_reversal_step needs for
+   this request (0 is possible).  Host only; ctx may be NULL. */
+int pg_reversal_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc,
+                               const pg_batch *batch, size_t *bytes);
+
+/* One coordinate step of grid reversal (§IV-A steps 2-4, §IV-C).  With
+   G' the forward map of batch under desc (out_dtype must be PG_OUT_F32)
+   and T = target (B x C x D x H x W float32, device):
+     residual[b]  = 2 (G' - T)                  B x C x D x H x W float32
+     loss[b]      = sum over structure b of (G' - T)^2      B float32
+     grad_xyz     = the pg_grid_backward of residual        n_atoms x 3
+     xyz_update   = xyz - lr * grad_xyz                     n_atoms x 3
+   grad_xyz and xyz_update may be NULL (not written); xyz_update may be
+   batch->xyz itself (update in place).  On the molecule window form the
+   forward kernel forms the residual and the loss as it goes (G' is never
+   stored; per-lane FP32 partial sums, FP64 across a workgroup); other forms
+   store G' in residual and then form both in one pass (FP64 partial sums).
+   The loss is deterministic for a given launch configuration.  Under
+   PG_OPT_GRAPH the whole step is captured once per argument set and
+   replayed.  ws: pg_reversal_workspace_size() bytes.
+   Errors: as pg_grid_forward; PG_E_PARAM also for out_dtype not F32 or a
+   non-finite lr. */
+int pg_reversal_step(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                     const float *target, float *residual, float *loss, float *grad_xyz,
+                     float *xyz_update, float lr, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

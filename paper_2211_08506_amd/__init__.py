@@ -76,7 +76,8 @@ _LIB_LOCK = threading.Lock()
 EXPORTS = ("pg_abi_version", "pg_status_str", "pg_create", "pg_destroy", "pg_validate",
            "pg_workspace_size", "pg_grid_forward", "pg_grid_backward", "pg_autotune",
            "pg_tuning_save", "pg_tuning_load", "pg_set_option", "pg_get_device_error",
-           "pg_last_hip_error", "pg_plan")
+           "pg_last_hip_error", "pg_plan", "pg_find_peaks", "pg_reversal_workspace_size",
+           "pg_reversal_step")
 
 
 def _lib():
@@ -89,7 +90,7 @@ def _lib():
             return _LIB
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              "`python -m paper_2211_08506_amd.build` (or __graft_entry__.build())")
+                              "`python paper_2211_08506_amd/build.py` (or __graft_entry__.build())")
         lib = ctypes.CDLL(LIB_PATH)
         vp, P = ctypes.c_void_p, ctypes.POINTER
         lib.pg_abi_version.restype = ctypes.c_int
@@ -110,6 +111,11 @@ def _lib():
         lib.pg_get_device_error.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int64)]
         lib.pg_last_hip_error.argtypes = [vp]
         lib.pg_plan.argtypes = [vp, P(GridDesc), P(Batch), vp, P(PlanInfo)]
+        lib.pg_find_peaks.argtypes = [vp, P(GridDesc), vp, ctypes.c_int32, vp, vp, ctypes.c_float,
+                                      ctypes.c_int64, vp, vp, vp, vp, vp]
+        lib.pg_reversal_workspace_size.argtypes = [vp, P(GridDesc), P(Batch), P(ctypes.c_size_t)]
+        lib.pg_reversal_step.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, vp, vp, vp,
+                                         ctypes.c_float, vp, ctypes.c_size_t, vp]
         for name in EXPORTS:
             getattr(lib, name).restype = ctypes.c_int if name != "pg_status_str" else ctypes.c_char_p
         _LIB = lib
@@ -290,6 +296,64 @@ class Context:
                                   _ptr(out), _ptr(ws), nbytes, s.cuda_stream, int(reps)),
                "pg_autotune")
 
+    def find_peaks(self, desc: GridDesc, grid: torch.Tensor, threshold: float,
+                   origins: Optional[torch.Tensor] = None, spacings: Optional[torch.Tensor] = None,
+                   capacity: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None):
+        """Local maxima of every channel of a float32 grid batch (pg_find_peaks)
+        -> (xyz (n, 3), types (n,), offsets (B + 1,)) device tensors.  Reads
+        the peak count back to the host; with capacity None the output is
+        sized to hold every peak."""
+        if grid.dtype != torch.float32 or not grid.is_contiguous() or grid.dim() != 5:
+            raise ValueError("grid must be a contiguous (B, C, D, H, W) float32 tensor")
+        dev = grid.device
+        B = int(grid.shape[0])
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cap = int(capacity) if capacity is not None else max(1024, 64 * B)
+        o_t = None if origins is None else origins.to(dev, torch.float32).contiguous()
+        s_t = None if spacings is None else spacings.to(dev, torch.float32).contiguous()
+        n_found = torch.zeros(1, dtype=torch.int64, device=dev)
+        while True:
+            xyz = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+            types = torch.empty(cap, dtype=torch.int32, device=dev)
+            offsets = torch.empty(B + 1, dtype=torch.int32, device=dev)
+            _check(_lib().pg_find_peaks(self.handle, ctypes.byref(desc), _ptr(grid), B,
+                                        _ptr(o_t), _ptr(s_t), float(threshold), cap, _ptr(xyz),
+                                        _ptr(types), _ptr(offsets), _ptr(n_found),
+                                        s.cuda_stream), "pg_find_peaks")
+            s.synchronize()
+            n = int(n_found.item())
+            if n <= cap or capacity is not None:
+                n = min(n, cap)
+                return xyz[:n], types[:n], offsets
+            cap = n
+
+    def reversal_workspace_size(self, desc: GridDesc, batch: BatchView) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib().pg_reversal_workspace_size(self.handle, ctypes.byref(desc),
+                                                 ctypes.byref(batch.c), ctypes.byref(n)),
+               "pg_reversal_workspace_size")
+        return int(n.value)
+
+    def reversal_step(self, desc: GridDesc, batch: BatchView, target: torch.Tensor,
+                      residual: torch.Tensor, loss: torch.Tensor,
+                      grad_xyz: Optional[torch.Tensor] = None,
+                      xyz_update: Optional[torch.Tensor] = None, lr: float = 0.0,
+                      stream: Optional[torch.cuda.Stream] = None):
+        """One grid-reversal step (pg_reversal_step): residual = 2 (G' - T),
+        loss per structure, and optionally the gradient and xyz - lr * grad
+        (xyz_update may be batch.xyz for an in-place step)."""
+        for name, t in (("target", target), ("residual", residual), ("loss", loss)):
+            if t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 tensor")
+        nbytes = self.reversal_workspace_size(desc, batch)
+        ws = self.workspace(nbytes)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(_lib().pg_reversal_step(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
+                                       _ptr(target), _ptr(residual), _ptr(loss), _ptr(grad_xyz),
+                                       _ptr(xyz_update), float(lr), _ptr(ws), nbytes,
+                                       s.cuda_stream), "pg_reversal_step")
+        return loss
+
     def tuning_save(self, path: str):
         _check(_lib().pg_tuning_save(self.handle, path.encode()), "pg_tuning_save")
 
@@ -355,6 +419,36 @@ def grid(xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor, sigma: S
     desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form, value)
     pgctx = ctx if ctx is not None else default_context(xyz.device)
     return GridFn.apply(xyz, types, offsets, origins, spacings, desc, max_atoms, pgctx)
+
+
+def reverse(target: torch.Tensor, sigma: Sequence[float], *, spacing=0.5,
+            origin=(0.0, 0.0, 0.0), threshold: float = 0.05, lr: float = 0.02, steps: int = 100,
+            tol: float = 0.0, check_every: int = 10, cutoff_k: float = 3.0, cell=None,
+            value: str = "point", ctx: Optional[Context] = None):
+    """Grid reversal (§IV-A): atoms back from a batch of float32 grids
+    (B, C, D, H, W).  Starts from the local maxima above `threshold`, then
+    takes gradient steps xyz <- xyz - lr * dL/dxyz on L = sum (G' - T)^2
+    until every structure's loss is below tol (checked every check_every
+    steps) or `steps` steps are done.  Returns (xyz, types, offsets, loss)."""
+    if target.dtype != torch.float32:
+        raise ValueError("target must be float32")
+    target = target.contiguous()
+    B, C, D, H, W = (int(x) for x in target.shape)
+    pgctx = ctx if ctx is not None else default_context(target.device)
+    desc = make_desc(C, (D, H, W), spacing, origin, sigma, cutoff_k, cell, torch.float32, "auto",
+                     value)
+    xyz, types, offsets = pgctx.find_peaks(desc, target, threshold)
+    xyz = xyz.clone()
+    batch = BatchView(xyz, types, offsets)
+    residual = torch.empty_like(target)
+    loss = torch.empty(B, dtype=torch.float32, device=target.device)
+    for k in range(steps):
+        pgctx.reversal_step(desc, batch, target, residual, loss, None, batch.xyz, lr)
+        if tol > 0 and (k + 1) % check_every == 0 and float(loss.max().item()) < tol:
+            break
+    # the loss at the final coordinates
+    pgctx.reversal_step(desc, batch, target, residual, loss)
+    return batch.xyz, types, offsets, loss
 
 
 def lib_path() -> str:

@@ -1,6 +1,9 @@
 """Build the gfx950 HIP library libparticlegrid.so in-tree.
 
-    python -m paper_2211_08506_amd.build        (or build() from Python)
+    python paper_2211_08506_amd/build.py        (or __graft_entry__.build())
+
+(Run as a file: importing it through the package would first load the
+library it is about to rebuild.)
 
 Every translation unit is compiled with hipcc for gfx950 only, with FP
 contraction off (the exact window predicate relies on error-free
@@ -21,7 +24,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libparticlegrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["pg_api.cpp", "pg_window.hip", "pg_plain.hip", "pg_adjoint.hip", "pg_crystal.hip"]
+SOURCES = ["pg_api.cpp", "pg_window.hip", "pg_plain.hip", "pg_adjoint.hip", "pg_crystal.hip",
+           "pg_reversal.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -14,7 +14,9 @@
 // factor and offset lists over the window (per-wave LDS), then its lanes
 // sweep the window with x fastest -- lanes of one window row read
 // consecutive addresses -- and the three partial sums are reduced across
-// the wave.  No atomics; each atom's gradient is written by one lane.
+// the wave.  No atomics; each atom's gradient is written by one lane, which
+// in a grid-reversal step also writes the updated coordinates
+// xyz - lr * gradient.
 #include "pg_device.hpp"
 #include "pg_launch.hpp"
 
@@ -120,9 +122,16 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     gy = wave_sum(gy);
     gz = wave_sum(gz);
     if (active && lane == 0) {
-        p.grad_xyz[3 * a + 0] = t >= 0 ? gx : 0.f;
-        p.grad_xyz[3 * a + 1] = t >= 0 ? gy : 0.f;
-        p.grad_xyz[3 * a + 2] = t >= 0 ? gz : 0.f;
+        const float g[3] = {t >= 0 ? gx : 0.f, t >= 0 ? gy : 0.f, t >= 0 ? gz : 0.f};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (p.grad_xyz)
+                p.grad_xyz[3 * a + q] = g[q];
+            // a grid-reversal step: the coordinate update (only this wave
+            // reads or writes atom a, so xyz_upd may alias xyz)
+            if (p.xyz_upd)
+                p.xyz_upd[3 * a + q] = __builtin_fmaf(-p.lr, g[q], mu[q]);
+        }
     }
 }
 

@@ -442,28 +442,22 @@ std::string graph_key(const pg_grid_desc *d, const pg_batch *b, const Plan &P, c
     return k;
 }
 
-int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *out, void *ws,
-                 size_t ws_bytes, hipStream_t s, const Plan &P)
+// Run a launch sequence directly, or (graph option on) capture it once per
+// distinct key on the context's capture stream and replay the cached graph.
+template <class F>
+int run_launches(pg_ctx *ctx, bool graph, const std::string &key, hipStream_t s, F &&launch)
 {
-    if (b->n_mol > 0 && !out)
-        return PG_E_NULL;
-    if (ws_bytes < P.ws || (P.ws > 0 && !ws))
-        return PG_E_WORKSPACE;
-
-    GridParams p;
-    fill_params(p, ctx, d, b, P, out, ws);
-    if (!ctx->use_graph || b->n_mol == 0) {
-        hipError_t e = launch_forward(ctx, d, P, p, s);
+    if (!graph) {
+        hipError_t e = launch(s);
         return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
     }
-    const std::string key = graph_key(d, b, P, out, ws, ws_bytes);
     auto it = std::find_if(ctx->graphs.begin(), ctx->graphs.end(),
                            [&](const GraphEntry &g) { return g.key == key; });
     if (it == ctx->graphs.end()) {
         hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess)
             return hip_fail(ctx, e);
-        hipError_t le = launch_forward(ctx, d, P, p, ctx->cap_stream);
+        hipError_t le = launch(ctx->cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(ctx->cap_stream, &g);
         if (le != hipSuccess || e != hipSuccess) {
@@ -489,6 +483,54 @@ int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *ou
     }
     hipError_t e = hipGraphLaunch(it->exec, s);
     return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+}
+
+int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *out, void *ws,
+                 size_t ws_bytes, hipStream_t s, const Plan &P)
+{
+    if (b->n_mol > 0 && !out)
+        return PG_E_NULL;
+    if (ws_bytes < P.ws || (P.ws > 0 && !ws))
+        return PG_E_WORKSPACE;
+    GridParams p;
+    fill_params(p, ctx, d, b, P, out, ws);
+    const bool graph = ctx->use_graph && b->n_mol > 0;
+    return run_launches(ctx, graph, graph ? graph_key(d, b, P, out, ws, ws_bytes) : std::string(),
+                        s, [&](hipStream_t st) {
+                            GridParams q = p;
+                            return launch_forward(ctx, d, P, q, st);
+                        });
+}
+
+// Grid reversal step: the forward plan of the residual buffer, whether the
+// molecule window kernel forms the residual itself (fused), and the
+// workspace (the forward's, then FP64 partial loss sums when not fused).
+struct RevPlan {
+    Plan P;
+    bool fused = false;
+    size_t partial_off = 0;
+    size_t ws = 0;
+};
+
+int reversal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b,
+                  const float *residual, const float *target, RevPlan &R)
+{
+    if (d && d->out_dtype != PG_OUT_F32)
+        return PG_E_PARAM;
+    int s = make_plan(ctx, d, b, residual, R.P);
+    if (s != PG_OK)
+        return s;
+    const int max_lds = ctx ? ctx->max_lds : 65536;
+    // the residual variant adds 128 bytes of static LDS for its loss sums
+    R.fused = R.P.form == PG_FORM_WINDOW && !R.P.crystal && R.P.lds + 128 <= (size_t)max_lds;
+    if (R.fused && target)
+        R.P.vec = std::min(R.P.vec, pick_vec(d, target));
+    R.partial_off = align256(R.P.ws);
+    R.ws = R.fused ? R.P.ws
+                   : R.partial_off + (size_t)b->n_mol *
+                                         residual_chunks((long long)d->C * d->D * d->H * d->W) *
+                                         sizeof(double);
+    return PG_OK;
 }
 
 void drop_graphs(pg_ctx *ctx)
@@ -652,6 +694,129 @@ int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     p.grad_xyz = grad_xyz;
     hipError_t e = launch_adjoint(p, desc->out_dtype, (hipStream_t)stream);
     return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+}
+
+int pg_find_peaks(pg_ctx *ctx, const pg_grid_desc *desc, const float *grid, int32_t n_mol,
+                  const float *origins, const float *spacings, float threshold, int64_t capacity,
+                  float *xyz_out, int32_t *types_out, int32_t *offsets_out, int64_t *n_found,
+                  void *stream)
+{
+    if (!ctx || !desc || !offsets_out || !n_found)
+        return PG_E_NULL;
+    if (n_mol < 0 || capacity < 0 || capacity > INT32_MAX)
+        return PG_E_SHAPE;
+    if (desc->C < 1 || desc->C > PG_MAX_CHANNELS || desc->D < 1 || desc->H < 1 || desc->W < 1)
+        return PG_E_SHAPE;
+    if ((long long)desc->C * desc->D * desc->H * desc->W >= (1ll << 31))
+        return PG_E_SHAPE;
+    if (desc->out_dtype != PG_OUT_F32 || !std::isfinite(threshold))
+        return PG_E_PARAM;
+    for (int q = 0; q < 3; ++q) {
+        if (!origins && !std::isfinite(desc->origin[q]))
+            return PG_E_PARAM;
+        if (!spacings && !finite_pos(desc->spacing[q]))
+            return PG_E_PARAM;
+    }
+    if ((n_mol > 0 && !grid) || (capacity > 0 && (!xyz_out || !types_out)))
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    PeakParams p;
+    std::memset(&p, 0, sizeof p);
+    p.grid = grid;
+    p.origins = origins;
+    p.spacings = spacings;
+    p.xyz = xyz_out;
+    p.types = types_out;
+    p.offsets = offsets_out;
+    p.n_found = (long long *)n_found;
+    p.capacity = capacity;
+    for (int q = 0; q < 3; ++q) {
+        p.o[q] = desc->origin[q];
+        p.h[q] = desc->spacing[q];
+    }
+    p.thr = threshold;
+    p.n_mol = n_mol;
+    p.C = desc->C;
+    p.D = desc->D;
+    p.H = desc->H;
+    p.W = desc->W;
+    hipError_t e = launch_peaks(p, (hipStream_t)stream);
+    return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+}
+
+int pg_reversal_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                               size_t *bytes)
+{
+    if (!bytes)
+        return PG_E_NULL;
+    *bytes = 0;
+    RevPlan R;
+    int s = reversal_plan(ctx, desc, batch, nullptr, nullptr, R);
+    if (s != PG_OK)
+        return s;
+    *bytes = R.ws;
+    return PG_OK;
+}
+
+int pg_reversal_step(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                     const float *target, float *residual, float *loss, float *grad_xyz,
+                     float *xyz_update, float lr, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return PG_E_NULL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    RevPlan R;
+    int s = reversal_plan(ctx, desc, batch, residual, target, R);
+    if (s != PG_OK)
+        return s;
+    if (!std::isfinite(lr))
+        return PG_E_PARAM;
+    if (batch->n_mol > 0 && (!target || !residual || !loss))
+        return PG_E_NULL;
+    if (ws_bytes < R.ws || (R.ws > 0 && !ws))
+        return PG_E_WORKSPACE;
+    if (batch->n_mol == 0)
+        return PG_OK;
+    DeviceGuard g(ctx->device);
+    GridParams p;
+    fill_params(p, ctx, desc, batch, R.P, residual, ws);
+    double *partial = (double *)((unsigned char *)ws + R.partial_off);
+    auto launch = [&](hipStream_t st) -> hipError_t {
+        GridParams q = p;
+        if (R.fused) {
+            q.target = target;
+            q.loss = loss;
+        }
+        hipError_t e = launch_forward(ctx, desc, R.P, q, st);
+        if (e != hipSuccess)
+            return e;
+        if (!R.fused) {
+            q = p;
+            q.target = target;
+            q.loss = loss;
+            e = launch_residual(q, partial, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        if (batch->n_atoms > 0 && (grad_xyz || xyz_update)) {
+            q = p;
+            q.grad_xyz = grad_xyz;
+            q.xyz_upd = xyz_update;
+            q.lr = lr;
+            e = launch_adjoint(q, PG_OUT_F32, st);
+        }
+        return e;
+    };
+    std::string key;
+    if (ctx->use_graph) {
+        key = graph_key(desc, batch, R.P, residual, ws, ws_bytes);
+        const void *ptrs[] = {target, loss, grad_xyz, xyz_update};
+        key.append("reversal");
+        key.append((const char *)ptrs, sizeof ptrs);
+        key.append((const char *)&lr, sizeof lr);
+    }
+    return run_launches(ctx, ctx->use_graph != 0, key, (hipStream_t)stream, launch);
 }
 
 int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, void *out, void *ws,

@@ -37,7 +37,15 @@ size_t crystal_zsort_lds(int D);
 hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form, int out_dtype,
                           size_t lds, hipStream_t s);
 
-// Coordinate adjoint, one wave per atom (pg_adjoint.hip).
+// Coordinate adjoint, one wave per atom (pg_adjoint.hip); with p.xyz_upd it
+// also writes xyz - p.lr * gradient.
 hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s);
+
+// Grid reversal (pg_reversal.hip): the local-maximum peak search, and the
+// residual / loss pass over a stored forward grid (p.out, float32) with
+// per-chunk FP64 partial sums in `partial` (n_mol x residual_chunks doubles).
+hipError_t launch_peaks(const PeakParams &p, hipStream_t s);
+int residual_chunks(long long per_mol);
+hipError_t launch_residual(const GridParams &p, double *partial, hipStream_t s);
 
 }  // namespace pg

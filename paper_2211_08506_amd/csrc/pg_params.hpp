@@ -46,6 +46,29 @@ struct GridParams {
     int32_t box;             // voxel integral (PG_VALUE_BOX) instead of the point sample
     float isq2s[PG_MAX_CHANNELS];   // fl32(1 / (sqrt(2) sigma)), box form
     float inorm[PG_MAX_CHANNELS];   // fl32(1 / (sqrt(2 pi) sigma)), box-form derivative
+    // grid reversal: the forward writes 2 (G - target) and the per-structure
+    // loss sum (G - target)^2 instead of G; the adjoint may also write
+    // xyz - lr * gradient
+    const float *target;
+    float *loss;
+    float *xyz_upd;
+    float lr;
+};
+
+// Peak search of grid reversal: local maxima of every channel of a batch of
+// float32 grids, written as a CSR batch of voxel-centre positions.
+struct PeakParams {
+    const float *grid;
+    const float *origins;    // per-structure, or nullptr
+    const float *spacings;   // per-structure, or nullptr
+    float *xyz;              // capacity x 3
+    int32_t *types;          // capacity
+    int32_t *offsets;        // n_mol + 1: counts, then the clamped CSR bounds
+    long long *n_found;
+    long long capacity;
+    float o[3], h[3];
+    float thr;
+    int32_t n_mol, C, D, H, W;
 };
 
 // Per-atom window table written by the prep kernel (plain form).

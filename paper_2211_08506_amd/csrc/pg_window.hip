@@ -16,7 +16,10 @@
 //      zeros included -- with a 16-byte store, so one store instruction of a
 //      wave covers 1 KiB of contiguous output.
 // Steps 1-2 run once per structure out of LDS-resident data, so the store
-// stream of step 3 needs no global loads.  Every output element is written
+// stream of step 3 needs no global loads.  In the residual mode of a grid
+// reversal step (§IV-A, §IV-C) step 3 also reads the target run, writes
+// 2 (G - target) in place of G and sums (G - target)^2 per structure
+// (per-lane FP32 partial sums, FP64 across the workgroup).  Every output element is written
 // exactly once, with no atomics on the output; each voxel's sum runs over
 // atoms in index order, so results are bitwise reproducible for every
 // launch shape.
@@ -80,7 +83,7 @@ __device__ __forceinline__ void load_row(const float *r, float (&v)[VEC])
     }
 }
 
-template <typename T, int VEC, int U>
+template <typename T, int VEC, int U, bool RES>
 __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -192,6 +195,8 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
         // ---- 3. stream the planes: each lane owns U runs per pass, so a
         // wave issues U back-to-back 16-byte stores per pass
         T *out = (T *)p.out + (size_t)m * mol_elems;
+        const float *tgt = RES ? p.target + (size_t)m * mol_elems : nullptr;
+        float sq = 0.f;
         for (int pl = wave; pl < planes; pl += nwaves) {
             const int z = pl % D;
             unsigned long long mk[4];
@@ -238,33 +243,71 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (ok[u])
+                    if (ok[u]) {
+                        if constexpr (RES) {
+                            float tv[VEC];
+                            load_row<VEC>(tgt + (size_t)pl * plane_elems +
+                                              (size_t)(j0 + 64 * u) * VEC, tv);
+#pragma unroll
+                            for (int k = 0; k < VEC; ++k) {
+                                const float r = acc[u][k] - tv[k];
+                                sq = __builtin_fmaf(r, r, sq);
+                                acc[u][k] = 2.f * r;
+                            }
+                        }
                         store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], nt);
+                    }
+            }
+        }
+        if constexpr (RES) {
+            __shared__ double red[16];
+            double d = sq;
+#pragma unroll
+            for (int w = 32; w >= 1; w >>= 1)
+                d += __shfl_xor(d, w, 64);
+            if (lane == 0)
+                red[wave] = d;
+            __syncthreads();
+            if (tid == 0) {
+                double a = 0.0;
+                for (int w = 0; w < nwaves; ++w)
+                    a += red[w];
+                p.loss[m] = (float)a;
             }
         }
         __syncthreads();
     }
 }
 
-template <typename T, int VEC, int U>
+template <typename T, int VEC, int U, bool RES>
 static const void *window_fn()
 {
-    return (const void *)window_mol_kernel<T, VEC, U>;
+    return (const void *)window_mol_kernel<T, VEC, U, RES>;
 }
 
-template <typename T, int VEC>
+template <typename T, int VEC, bool RES = false>
 static const void *window_fn_u(int unroll)
 {
     switch (unroll) {
-    case 1: return window_fn<T, VEC, 1>();
-    case 2: return window_fn<T, VEC, 2>();
-    case 4: return window_fn<T, VEC, 4>();
+    case 1: return window_fn<T, VEC, 1, RES>();
+    case 2: return window_fn<T, VEC, 2, RES>();
+    case 4: return window_fn<T, VEC, 4, RES>();
     }
     return nullptr;
 }
 
-static const void *window_kernel_fn(int out_dtype, int vec, int unroll)
+static const void *window_kernel_fn(int out_dtype, int vec, int unroll, bool residual)
 {
+    if (residual) {
+        if (out_dtype != PG_OUT_F32)
+            return nullptr;
+        switch (vec) {
+        case 4: return window_fn_u<float, 4, true>(unroll);
+        case 2: return window_fn_u<float, 2, true>(unroll);
+        case 1: return window_fn_u<float, 1, true>(unroll);
+        }
+        return nullptr;
+    }
     if (out_dtype == PG_OUT_F32) {
         switch (vec) {
         case 4: return window_fn_u<float, 4>(unroll);
@@ -285,7 +328,7 @@ static const void *window_kernel_fn(int out_dtype, int vec, int unroll)
 hipError_t launch_window(const GridParams &p, int out_dtype, int vec, int unroll, int block,
                          int grid, size_t lds, hipStream_t s)
 {
-    const void *k = window_kernel_fn(out_dtype, vec, unroll);
+    const void *k = window_kernel_fn(out_dtype, vec, unroll, p.target != nullptr);
     if (!k)
         return hipErrorInvalidValue;
     if (p.n_mol == 0)

@@ -165,6 +165,30 @@ def test_workspace_and_plan_host_only():
     assert info.binned == 0
 
 
+def test_reversal_workspace_host_only():
+    """The molecule window form forms the residual in its forward kernel (no
+    workspace); other forms need FP64 partial loss sums (one per 4096
+    elements of each structure) after their own workspace; bf16 grids are
+    refused (the residual and the loss are float32)."""
+    lib = pg._lib()
+    n = ctypes.c_size_t(123)
+    ws = lambda d, b: (lib.pg_reversal_workspace_size(None, ctypes.byref(d), ctypes.byref(b),
+                                                       ctypes.byref(n)), n.value)
+    assert ws(desc_ok(form="window"), batch_ok()) == (0, 0)
+    per_mol = 5 * 32 * 32 * 32
+    chunks = -(-per_mol // 4096)
+    st, plain = ws(desc_ok(form="plain"), batch_ok())
+    assert st == 0 and plain >= 4 * chunks * 8 + 40 * 100
+    big = batch_ok(n_atoms=4000, max_atoms=1000)
+    _, fwd = (lib.pg_workspace_size(None, ctypes.byref(desc_ok(form="window")), ctypes.byref(big),
+                                    ctypes.byref(n)), n.value)
+    st, rev = ws(desc_ok(form="window"), big)
+    assert st == 0 and rev == -(-fwd // 256) * 256 + 4 * chunks * 8
+    assert ws(desc_ok(out_dtype="bf16"), batch_ok())[0] == pg.PG_E_PARAM
+    assert lib.pg_reversal_workspace_size(None, ctypes.byref(desc_ok()), ctypes.byref(batch_ok()),
+                                          None) == pg.PG_E_NULL
+
+
 def test_null_context_calls_fail_cleanly():
     lib = pg._lib()
     d = desc_ok()
@@ -172,5 +196,9 @@ def test_null_context_calls_fail_cleanly():
     assert lib.pg_grid_forward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, None, 0, None) == pg.PG_E_NULL
     assert lib.pg_grid_backward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, 0x1000, None, 0, None) == pg.PG_E_NULL
     assert lib.pg_set_option(None, 1, 1) == pg.PG_E_NULL
+    assert lib.pg_find_peaks(None, ctypes.byref(d), 0x1000, 4, None, None, 0.1, 16, 0x1000,
+                             0x1000, 0x1000, 0x1000, None) == pg.PG_E_NULL
+    assert lib.pg_reversal_step(None, ctypes.byref(d), ctypes.byref(b), 0x1000, 0x1000, 0x1000,
+                                None, None, 0.1, None, 0, None) == pg.PG_E_NULL
     assert lib.pg_destroy(None) == pg.PG_E_NULL
     assert lib.pg_create(None, 0) == pg.PG_E_NULL
