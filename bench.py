@@ -20,7 +20,9 @@ Workloads (synth.WORKLOADS):
   crystal8     8 periodic 20 A cells of 2000-20000 atoms, 128^3 x 8 at
                0.16 A: bf16 (MFMA plane kernel) beside the fp32 vector form;
   adjoint1024  the coordinate gradient of 1024 molecules, 32^3 x 5 fp32
-               upstream.
+               upstream;
+  reversal1024 one grid-reversal step (residual, loss, coordinate gradient
+               and update) of 1024 molecules against fp32 32^3 x 5 targets.
 --value box measures the box form (each voxel holds the normalised
 Gaussian's mass inside it) instead of the point-sampled Gaussian.
 The FP64 CPU oracle is timed on a bounded sample of the same workload, one
@@ -47,6 +49,8 @@ METRICS = {
     "mol4096x48": "grids/sec + HBM GB/s (48³×5ch, batch 4096, 5-60 atoms): batched BF16",
     "crystal8": "grids/sec + HBM GB/s (128³×8ch periodic cells, batch 8): BF16 MFMA vs FP32 window",
     "adjoint1024": "grids/sec (adjoint dL/dxyz, 32³×5ch FP32 upstream, batch 1024)",
+    "reversal1024": "grids/sec (grid-reversal step: residual + loss + dL/dxyz + update, "
+                    "32³×5ch FP32, batch 1024)",
 }
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
@@ -285,6 +289,48 @@ def main():
                     "evals_per_s": evals / (ev["mean"] / 1e3),
                     "upstream_bytes_read_dense": B * vox * 4})
         kind = "adjoint"
+    elif wl.name == "reversal1024":
+        desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
+                            torch.float32, "auto", value)
+        # targets: the grids of the generating coordinates; the step starts
+        # from displaced coordinates and updates them in place
+        target = pg.empty_grid(desc, B, dev)
+        ctx.forward(desc, bv, target, stream)
+        x0 = b.xyz + synth.perturbation(wl.upstream_seed, b.n_atoms, 0.15)
+        bvp = pg.BatchView(torch.tensor(x0, device=dev), types, offs, offsets_host=b.offsets)
+        residual = torch.empty_like(target)
+        loss = torch.empty(B, dtype=torch.float32, device=dev)
+        lr = 0.01 if value == "point" else 2.0
+        plan = ctx.plan(desc, bvp, residual)
+        loss0 = None
+
+        def step():
+            ctx.reversal_step(desc, bvp, target, residual, loss, None, bvp.xyz, lr, stream)
+
+        step()
+        torch.cuda.synchronize()
+        loss0 = float(loss.sum().item())
+        wall, ev = timed_steps(step, args.steps, args.warmup, torch, stream)
+        loss1 = float(loss.sum().item())
+        # algorithmic bytes: the target read and the residual written once,
+        # the residual re-read inside every window by the adjoint, the
+        # inputs, and the coordinates read and written
+        alg = 8 * B * vox + evals * 4 + in_bytes + 24 * b.n_atoms
+        achieved = alg / (ev["mean"] / 1e3) / 1e9
+        log(f"[bench] reversal step: plan {plan}")
+        log(f"[bench]   {wall:.3f} ms/step wall, {ev['mean']:.3f} ms (events), "
+            f"{B / (wall / 1e3) / 1e6:.3f} M grids/s, {achieved:.0f} GB/s algorithmic; "
+            f"loss {loss0:.4e} -> {loss1:.4e} over {args.steps + args.warmup + 1} steps")
+        kname = (f"whole step: window_mol_kernel<float,{plan['vec']},{plan['unroll']},residual>"
+                 " + adjoint_kernel<float> (update)")
+        rec.update({"value": B / (wall / 1e3), "ms_per_step": wall, "dtype": "f32",
+                    "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                                 "traffic": None, "kernel": kname,
+                                 "algorithmic_bytes_per_launch": alg, "launch_ms": ev},
+                    "loss_first_step": loss0, "loss_last_step": loss1})
+        kind = "reversal step"
+        Th = target.cpu().numpy()
     else:
         out_dt = torch.bfloat16 if wl.out_dtype == "bf16" or wl.kind == "crystal" else torch.float32
         desc, out, main_res = forward_case(out_dt, "auto", True, args.steps, args.warmup)
@@ -367,8 +413,10 @@ def main():
                                  f"{wl.cutoff_k:g} sigma, {kind}, {value} form, {launch}",
                      "batch": B, "grid": [C, D, H, W], "n_atoms": int(b.n_atoms),
                      "evals_per_pass": evals}
-    if kind == "forward":
+    if kind in ("forward", "reversal step"):
         rec["config"]["plan"] = plan
+    if kind == "reversal step":
+        rec["config"]["start"] = "generating coordinates displaced by U(-0.15, 0.15) A per axis"
 
     cpu = None
     if not args.no_cpu:
@@ -377,7 +425,17 @@ def main():
         import oracle as cpu_oracle
         chunk = 1 if wl.kind == "crystal" else 16
         units = [(m, b.subset(range(m, min(B, m + chunk)))) for m in range(0, B, chunk)]
-        if kind == "adjoint":
+        if kind == "reversal step":
+            from oracle import reversal as cpu_reversal
+
+            def run_one(u):
+                m, s = u
+                a0, a1 = b.offsets[m], b.offsets[m + s.n_mol]
+                cpu_reversal.reversal_step(x0[a0:a1], s.types, s.offsets, sig, wl.dims,
+                                           wl.spacing, Th[m:m + s.n_mol], lr, wl.origin,
+                                           cutoff_k=wl.cutoff_k, value=value)
+                return s.n_mol
+        elif kind == "adjoint":
             Uh = synth.upstream(wl.upstream_seed, wl.grid_shape())
 
             def run_one(u):

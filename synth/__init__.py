@@ -143,6 +143,12 @@ def upstream(seed: int, shape: Sequence[int]) -> np.ndarray:
     return rng_for(seed).standard_normal(size=tuple(shape), dtype=np.float32)
 
 
+def perturbation(seed: int, n_atoms: int, amp: float) -> np.ndarray:
+    """Coordinate displacements, i.i.d. uniform in [-amp, amp] A per axis,
+    float32 (the starting point of a grid-reversal workload)."""
+    return rng_for(seed).uniform(-amp, amp, size=(n_atoms, 3)).astype(np.float32)
+
+
 @dataclasses.dataclass
 class Workload:
     """A named workload: the batch recipe plus the grid geometry."""
@@ -232,4 +238,9 @@ WORKLOADS = {
     "adjoint1024": Workload("adjoint1024", 6, 1024, (32, 32, 32), 5, 0.5,
                             _centered_origin(32, 0.5), atoms=(5, 29), box=12.0,
                             upstream_seed=7),
+    # grid reversal: 1024 molecules of 5..29 atoms, 32^3 x 5 ch float32
+    # targets, coordinates displaced by up to 0.15 A per axis (seed 9)
+    "reversal1024": Workload("reversal1024", 8, 1024, (32, 32, 32), 5, 0.5,
+                             _centered_origin(32, 0.5), atoms=(5, 29), box=12.0,
+                             upstream_seed=9),
 }
