@@ -54,16 +54,17 @@ def _load():
         from .build import build
         build()
     lib = ctypes.CDLL(_LIB_PATH)
-    lib.pgo_grid.argtypes = _COMMON + [ctypes.c_int, _dp, _i64p, _i64p]
+    lib.pgo_grid.argtypes = _COMMON + [ctypes.c_int, _dp, ctypes.c_int, _dp, _i64p, _i64p]
     lib.pgo_grid.restype = ctypes.c_int
-    lib.pgo_grad.argtypes = _COMMON + [ctypes.c_int, _dp, _dp]
+    lib.pgo_grad.argtypes = _COMMON + [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp]
     lib.pgo_grad.restype = ctypes.c_int
-    lib.pgo_voxels.argtypes = _COMMON + [ctypes.c_int, ctypes.c_int64, _i64p, _dp]
+    lib.pgo_voxels.argtypes = _COMMON + [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int64, _i64p,
+                                         _dp]
     lib.pgo_voxels.restype = ctypes.c_int
     lib.pgo_count_evals.argtypes = _COMMON
     lib.pgo_count_evals.restype = ctypes.c_int64
     lib.pgo_version.restype = ctypes.c_int
-    if lib.pgo_version() != 2:
+    if lib.pgo_version() != 3:
         raise ImportError(f"{_LIB_PATH} is stale: rebuild it with oracle/build.py")
     _lib = lib
     return lib
@@ -87,14 +88,23 @@ class _Args:
     """Marshals one call's inputs into contiguous arrays of the C types."""
 
     def __init__(self, xyz, types, offsets, sigma, dims, spacing, origin,
-                 cutoff_k, cell, origins, spacings, n_types):
+                 cutoff_k, cell, origins, spacings, n_types, weights=None):
         self.xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
         self.types = np.ascontiguousarray(np.asarray(types, dtype=np.int32).reshape(-1))
         self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64).reshape(-1))
         self.sigma = np.ascontiguousarray(np.asarray(sigma, dtype=np.float32).reshape(-1))
-        self.C = int(n_types if n_types is not None else self.sigma.shape[0])
-        if self.sigma.shape[0] < self.C:
-            raise ValueError("sigma must have one entry per channel")
+        self.n_sig = int(self.sigma.shape[0])
+        if weights is not None:
+            # weighted channels: C comes from the weights, sigma is per type
+            self.weights = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+            if self.weights.ndim != 2 or self.weights.shape[0] != self.xyz.shape[0]:
+                raise ValueError("weights must have shape (n_atoms, C)")
+            self.C = int(self.weights.shape[1])
+        else:
+            self.weights = None
+            self.C = int(n_types if n_types is not None else self.sigma.shape[0])
+            if self.sigma.shape[0] < self.C:
+                raise ValueError("sigma must have one entry per channel")
         self.D, self.H, self.W = (int(d) for d in dims)
         self.B = int(self.offsets.shape[0] - 1)
         # Grid geometry (origin, spacing, cell) is single precision in the
@@ -124,6 +134,9 @@ class _Args:
                 _ptr(self.sigma, _f32p), ctypes.c_float(self.k), int(self.periodic),
                 _ptr(self.cell, _dp)]
 
+    def weighting(self):
+        return [_ptr(self.weights, _dp), self.n_sig]
+
     @property
     def shape(self):
         return (self.B, self.C, self.D, self.H, self.W)
@@ -131,15 +144,17 @@ class _Args:
 
 def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3.0,
               cell=None, origins=None, spacings=None, n_types=None, return_stats=False,
-              value="point"):
-    """Dense FP64 grids, shape (B, C, D, H, W), x fastest."""
+              value="point", weights=None):
+    """Dense FP64 grids, shape (B, C, D, H, W), x fastest.  With weights
+    (n_atoms, C), atom a adds weights[a, c] times its Gaussian (width
+    sigma[types[a]]) to every channel c."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
-              origins, spacings, n_types)
+              origins, spacings, n_types, weights)
     out = np.empty(a.shape, dtype=np.float64)
     ev = ctypes.c_int64(0)
     sk = ctypes.c_int64(0)
-    rc = _load().pgo_grid(*a.common(), VALUES[value], _ptr(out, _dp), ctypes.byref(ev),
-                          ctypes.byref(sk))
+    rc = _load().pgo_grid(*a.common(), VALUES[value], *a.weighting(), _ptr(out, _dp),
+                          ctypes.byref(ev), ctypes.byref(sk))
     if rc != 0:
         raise MemoryError("pgo_grid failed")
     if return_stats:
@@ -148,27 +163,32 @@ def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3
 
 
 def grad_fp64(xyz, types, offsets, sigma, dims, spacing, U, origin=None, cutoff_k=3.0,
-              cell=None, origins=None, spacings=None, n_types=None, value="point"):
-    """dL/dxyz for L = sum(U * G), shape (n_atoms, 3) float64."""
+              cell=None, origins=None, spacings=None, n_types=None, value="point",
+              weights=None, return_weight_grad=False):
+    """dL/dxyz for L = sum(U * G), shape (n_atoms, 3) float64; with weights
+    and return_weight_grad, also dL/dweights (n_atoms, C)."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
-              origins, spacings, n_types)
+              origins, spacings, n_types, weights)
     u = np.ascontiguousarray(np.asarray(U, dtype=np.float64).reshape(a.shape))
     g = np.empty((a.xyz.shape[0], 3), dtype=np.float64)
-    rc = _load().pgo_grad(*a.common(), VALUES[value], _ptr(u, _dp), _ptr(g, _dp))
+    gw = np.empty((a.xyz.shape[0], a.C), dtype=np.float64) if weights is not None else None
+    rc = _load().pgo_grad(*a.common(), VALUES[value], *a.weighting(), _ptr(u, _dp),
+                          _ptr(g, _dp), _ptr(gw, _dp))
     if rc != 0:
         raise MemoryError("pgo_grad failed")
-    return g
+    return (g, gw) if return_weight_grad else g
 
 
 def voxels_fp64(xyz, types, offsets, sigma, dims, spacing, idx, origin=None, cutoff_k=3.0,
-                cell=None, origins=None, spacings=None, n_types=None, value="point"):
+                cell=None, origins=None, spacings=None, n_types=None, value="point",
+                weights=None):
     """Grid values at sampled voxels; idx is (S, 5) rows of (b, c, z, y, x)."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
-              origins, spacings, n_types)
+              origins, spacings, n_types, weights)
     q = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 5))
     v = np.empty(q.shape[0], dtype=np.float64)
-    rc = _load().pgo_voxels(*a.common(), VALUES[value], ctypes.c_int64(q.shape[0]),
-                            _ptr(q, _i64p), _ptr(v, _dp))
+    rc = _load().pgo_voxels(*a.common(), VALUES[value], *a.weighting(),
+                            ctypes.c_int64(q.shape[0]), _ptr(q, _i64p), _ptr(v, _dp))
     if rc != 0:
         raise ValueError("sample index out of range")
     return v

@@ -48,8 +48,16 @@
  *   of the separable coordinate gradient of §IV-C), cutoff-edge jumps
  *   excluded (derivative almost everywhere).
  *
- *   Atoms with a type outside [0, C) or a non-finite coordinate are skipped
- *   and counted.
+ *   Weighted channels (weights != NULL; the learned-embedding grids the
+ *   Discussion proposes, and the weighted grids mentioned after Eq. 6): atom
+ *   a adds weights[a][c] times its Gaussian to every channel c, the
+ *   Gaussian's width still being sigma of its type t_a, which then indexes
+ *   a table of n_sig widths independent of the channel count.  One-hot
+ *   weights (weights[a][c] = [c == t_a]) give the unweighted grid.  The
+ *   adjoint then also yields dL/dweights[a][c] = sum_v U[c, v] g_a(v).
+ *
+ *   Atoms with a type outside [0, C) (weighted: [0, n_sig)) or a non-finite
+ *   coordinate are skipped and counted.
  *
  * Layout: out[b][c][z][y][x], x fastest; dims (D, H, W) = (z, y, x);
  * origin / spacing / cell given in x, y, z order.
@@ -228,6 +236,7 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
              const double *origins, const double *spacings,
              const float *sigma, float cutoff_k,
              int periodic, const double *cell3, int value,
+             const double *weights, int n_sig,
              double *out, int64_t *evals, int64_t *skipped)
 {
     const size_t plane = (size_t)H * W, vol = (size_t)D * plane;
@@ -242,7 +251,7 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
         for (int64_t a = offsets[b]; a < offsets[b + 1]; ++a) {
             const double *mu = xyz + 3 * a;
             int32_t t = types[a];
-            if (!atom_ok(mu, t, C)) {
+            if (!atom_ok(mu, t, weights ? n_sig : C)) {
                 ++sk;
                 continue;
             }
@@ -251,6 +260,7 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
             window_build(&w, &g, mu);
             const double s2 = (double)sigma[t] * (double)sigma[t];
             double *grid = out + ((size_t)b * C + t) * vol;
+            const double *wa = weights ? weights + (size_t)a * C : NULL;
             for (int kz = 0; kz < w.n[2]; ++kz)
                 for (int ky = 0; ky < w.n[1]; ++ky)
                     for (int kx = 0; kx < w.n[0]; ++kx) {
@@ -262,8 +272,15 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
                                 box1d(dz - 0.5 * g.h[2], dz + 0.5 * g.h[2], sigma[t]);
                         else
                             v = exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s2));
-                        grid[(size_t)w.idx[2][kz] * plane + (size_t)w.idx[1][ky] * W + w.idx[0][kx]]
-                            += v;
+                        const size_t vox = (size_t)w.idx[2][kz] * plane +
+                                           (size_t)w.idx[1][ky] * W + w.idx[0][kx];
+                        if (!wa) {
+                            grid[vox] += v;
+                        } else {
+                            for (int c = 0; c < C; ++c)
+                                if (wa[c] != 0.0)
+                                    out[((size_t)b * C + c) * vol + vox] += wa[c] * v;
+                        }
                     }
             ev += (int64_t)w.n[0] * w.n[1] * w.n[2];
         }
@@ -279,6 +296,7 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
 /*
  * Coordinate gradient of L = sum U * G.  U has B*C*D*H*W doubles; grad has
  * n_atoms*3 doubles (x, y, z) and is overwritten (skipped atoms get 0).
+ * Weighted channels: grad_w (may be NULL) receives dL/dweights, n_atoms*C.
  */
 int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *types,
              int C, int D, int H, int W,
@@ -286,7 +304,8 @@ int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
              const double *origins, const double *spacings,
              const float *sigma, float cutoff_k,
              int periodic, const double *cell3, int value,
-             const double *U, double *grad)
+             const double *weights, int n_sig,
+             const double *U, double *grad, double *grad_w)
 {
     const size_t plane = (size_t)H * W, vol = (size_t)D * plane;
     window_t w;
@@ -299,19 +318,46 @@ int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
             const double *mu = xyz + 3 * a;
             int32_t t = types[a];
             grad[3 * a + 0] = grad[3 * a + 1] = grad[3 * a + 2] = 0.0;
-            if (!atom_ok(mu, t, C))
+            const double *wa = weights ? weights + (size_t)a * C : NULL;
+            double *gwa = (weights && grad_w) ? grad_w + (size_t)a * C : NULL;
+            if (gwa)
+                for (int c = 0; c < C; ++c)
+                    gwa[c] = 0.0;
+            if (!atom_ok(mu, t, weights ? n_sig : C))
                 continue;
             g.cut = cutoff_k != 0.0f;
             g.rc = cutoff_radius(cutoff_k, sigma[t]);
             window_build(&w, &g, mu);
             const double s2 = (double)sigma[t] * (double)sigma[t];
             const double *u = U + ((size_t)b * C + t) * vol;
+            const double *ub = U + (size_t)b * C * vol;
             double gx = 0, gy = 0, gz = 0;
             for (int kz = 0; kz < w.n[2]; ++kz)
                 for (int ky = 0; ky < w.n[1]; ++ky)
                     for (int kx = 0; kx < w.n[0]; ++kx) {
                         double dx = w.del[0][kx], dy = w.del[1][ky], dz = w.del[2][kz];
-                        double uv = u[(size_t)w.idx[2][kz] * plane + (size_t)w.idx[1][ky] * W + w.idx[0][kx]];
+                        const size_t vox = (size_t)w.idx[2][kz] * plane +
+                                           (size_t)w.idx[1][ky] * W + w.idx[0][kx];
+                        double uv;
+                        if (!wa) {
+                            uv = u[vox];
+                        } else {
+                            /* sum_c w_c U[c, v]: the upstream seen by this atom */
+                            uv = 0.0;
+                            for (int c = 0; c < C; ++c)
+                                uv += wa[c] * ub[(size_t)c * vol + vox];
+                        }
+                        if (gwa) {
+                            double gval;
+                            if (value == 1)
+                                gval = box1d(dx - 0.5 * g.h[0], dx + 0.5 * g.h[0], sigma[t]) *
+                                       box1d(dy - 0.5 * g.h[1], dy + 0.5 * g.h[1], sigma[t]) *
+                                       box1d(dz - 0.5 * g.h[2], dz + 0.5 * g.h[2], sigma[t]);
+                            else
+                                gval = exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s2));
+                            for (int c = 0; c < C; ++c)
+                                gwa[c] += ub[(size_t)c * vol + vox] * gval;
+                        }
                         if (value == 1) {
                             const double sg = sigma[t];
                             const double lx = dx - 0.5 * g.h[0], rx = dx + 0.5 * g.h[0];
@@ -352,6 +398,7 @@ int pgo_voxels(int B, const int64_t *offsets, const double *xyz, const int32_t *
                const double *origins, const double *spacings,
                const float *sigma, float cutoff_k,
                int periodic, const double *cell3, int value,
+               const double *weights, int n_sig,
                int64_t n_samples, const int64_t *idx, double *val)
 {
     for (int64_t s = 0; s < n_samples; ++s) {
@@ -365,25 +412,36 @@ int pgo_voxels(int B, const int64_t *offsets, const double *xyz, const int32_t *
         geom_t g;
         geom_for(&g, b, C, D, H, W, origin3, spacing3, origins, spacings, periodic, cell3);
         g.cut = cutoff_k != 0.0f;
-        g.rc = cutoff_radius(cutoff_k, sigma[c]);
-        const double s2 = (double)sigma[c] * (double)sigma[c];
         double acc = 0.0;
         for (int64_t a = offsets[b]; a < offsets[b + 1]; ++a) {
             const double *mu = xyz + 3 * a;
-            if (types[a] != c || !atom_ok(mu, types[a], C))
+            const int32_t t = types[a];
+            double wt = 1.0;
+            if (weights) {
+                if (!atom_ok(mu, t, n_sig))
+                    continue;
+                wt = weights[(size_t)a * C + c];
+                if (wt == 0.0)
+                    continue;
+            } else if (t != c || !atom_ok(mu, t, C)) {
                 continue;
+            }
+            g.rc = cutoff_radius(cutoff_k, sigma[t]);
+            const double s2 = (double)sigma[t] * (double)sigma[t];
             double d[3];
             int inside = 1;
             for (int ax = 0; ax < 3 && inside; ++ax)
                 inside = axis_offset(g.o[ax], g.h[ax], vi[ax], mu[ax], g.periodic,
                                      g.L[ax], g.cut, g.rc, &d[ax]);
             if (inside) {
+                double v;
                 if (value == 1)
-                    acc += box1d(d[0] - 0.5 * g.h[0], d[0] + 0.5 * g.h[0], sigma[c]) *
-                           box1d(d[1] - 0.5 * g.h[1], d[1] + 0.5 * g.h[1], sigma[c]) *
-                           box1d(d[2] - 0.5 * g.h[2], d[2] + 0.5 * g.h[2], sigma[c]);
+                    v = box1d(d[0] - 0.5 * g.h[0], d[0] + 0.5 * g.h[0], sigma[t]) *
+                        box1d(d[1] - 0.5 * g.h[1], d[1] + 0.5 * g.h[1], sigma[t]) *
+                        box1d(d[2] - 0.5 * g.h[2], d[2] + 0.5 * g.h[2], sigma[t]);
                 else
-                    acc += exp(-(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / (2.0 * s2));
+                    v = exp(-(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / (2.0 * s2));
+                acc += weights ? wt * v : v;
             }
         }
         val[s] = acc;
@@ -421,4 +479,4 @@ int64_t pgo_count_evals(int B, const int64_t *offsets, const double *xyz, const 
     return ev;
 }
 
-int pgo_version(void) { return 2; }
+int pgo_version(void) { return 3; }
