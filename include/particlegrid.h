@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define PG_ABI_VERSION 2
+#define PG_ABI_VERSION 3
 #define PG_MAX_CHANNELS 64
 
 typedef enum pg_status {
@@ -109,8 +109,10 @@ typedef struct pg_grid_desc {
     float cell[3];               /* periodic cell edges Lx Ly Lz (periodic only) */
     int32_t out_dtype;           /* PG_OUT_F32 or PG_OUT_BF16 (round-to-nearest-even) */
     int32_t form;                /* PG_FORM_* */
-    float sigma[PG_MAX_CHANNELS];/* Gaussian width (standard deviation) per channel, > 0 */
+    float sigma[PG_MAX_CHANNELS];/* Gaussian width (standard deviation) per type, > 0 */
     int32_t value;               /* PG_VALUE_POINT or PG_VALUE_BOX */
+    int32_t n_types;             /* with batch->weights: entries of sigma[] the types index
+                                    (1..64); 0 means C.  Without weights: 0 or C */
 } pg_grid_desc;
 
 /* A ragged batch of structures (device arrays unless noted). */
@@ -123,7 +125,19 @@ typedef struct pg_batch {
     int32_t n_mol;               /* B >= 0 */
     int32_t max_atoms;           /* host: upper bound of atoms in any one structure */
     int64_t n_atoms;             /* host: offsets[n_mol]; 0 allowed */
+    const float *weights;        /* n_atoms x C float32 channel weights, or NULL (see below) */
 } pg_batch;
+
+/* Weighted channels.  With batch->weights == NULL each atom feeds the one
+   channel of its type (one channel per element, §III-A), and types lie in
+   [0, C).  With weights, atom a adds weights[a][c] times its Gaussian to
+   every channel c (the learned-embedding grids of the paper's Discussion,
+   and the weighted grids mentioned after Eq. 6); its width is still
+   sigma[types[a]], types lying in [0, n_types), so the number of element
+   types is independent of the channel count.  One-hot weights give the
+   unweighted grid bit for bit.  Weighted requests take the molecule window
+   form or the plain form; the binned large-structure path returns
+   PG_E_UNSUPPORTED. */
 
 typedef struct pg_ctx pg_ctx;
 
@@ -177,11 +191,15 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
    (sqrt(2 pi) sigma_t), g(x) = exp(-(x - mu)^2 / (2 sigma_t^2)) -- the erf
    derivative of §IV-C with the minus of its exponent restored.  The cutoff edge contributes
    nothing (derivative almost everywhere).  grad_xyz: n_atoms x 3 float32,
-   fully overwritten (skipped atoms get 0).
+   fully overwritten (skipped atoms get 0).  With weighted channels the
+   atom's upstream is sum_c weights[a][c] grad_out[b][c][v], and
+   grad_weights (n_atoms x C float32, or NULL) receives
+   dL/dweights[a][c] = sum over the window of grad_out[b][c][v] G_a(v)
+   (skipped atoms get 0).  grad_xyz may be NULL when grad_weights is not.
    Errors: as pg_grid_forward. */
 int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
-                     const void *grad_out, float *grad_xyz, void *ws, size_t ws_bytes,
-                     void *stream);
+                     const void *grad_out, float *grad_xyz, float *grad_weights, void *ws,
+                     size_t ws_bytes, void *stream);
 
 /* Time the candidate kernel configurations (and, under AUTO, the forms)
    for this request on `stream`, keep the fastest in the context's tuning

@@ -54,14 +54,15 @@ class GridDesc(ctypes.Structure):
                 ("cutoff_k", ctypes.c_float), ("periodic", ctypes.c_int32),
                 ("cell", ctypes.c_float * 3), ("out_dtype", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("sigma", ctypes.c_float * MAX_CHANNELS),
-                ("value", ctypes.c_int32)]
+                ("value", ctypes.c_int32), ("n_types", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
     _fields_ = [("xyz", ctypes.c_void_p), ("types", ctypes.c_void_p),
                 ("offsets", ctypes.c_void_p), ("origins", ctypes.c_void_p),
                 ("spacings", ctypes.c_void_p), ("n_mol", ctypes.c_int32),
-                ("max_atoms", ctypes.c_int32), ("n_atoms", ctypes.c_int64)]
+                ("max_atoms", ctypes.c_int32), ("n_atoms", ctypes.c_int64),
+                ("weights", ctypes.c_void_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -101,8 +102,8 @@ def _lib():
         lib.pg_validate.argtypes = [P(GridDesc), P(Batch)]
         lib.pg_workspace_size.argtypes = [vp, P(GridDesc), P(Batch), P(ctypes.c_size_t)]
         lib.pg_grid_forward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, ctypes.c_size_t, vp]
-        lib.pg_grid_backward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, vp, ctypes.c_size_t,
-                                         vp]
+        lib.pg_grid_backward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, vp, vp,
+                                         ctypes.c_size_t, vp]
         lib.pg_autotune.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, ctypes.c_size_t, vp,
                                     ctypes.c_int]
         lib.pg_tuning_save.argtypes = [vp, ctypes.c_char_p]
@@ -138,11 +139,13 @@ def _f3(v) -> Tuple[float, float, float]:
 
 def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigma=(),
               cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32,
-              form: Union[str, int] = "auto", value: Union[str, int] = "point") -> GridDesc:
+              form: Union[str, int] = "auto", value: Union[str, int] = "point",
+              n_types: int = 0) -> GridDesc:
     """Build a pg_grid_desc (host struct).  dims = (D, H, W) = (z, y, x);
-    origin / spacing / cell in x, y, z order; sigma one value per channel;
-    value "point" (the Gaussian at voxel centres) or "box" (the normalised
-    Gaussian's mass in each voxel)."""
+    origin / spacing / cell in x, y, z order; sigma one width per type
+    (= per channel unless weighted); value "point" (the Gaussian at voxel
+    centres) or "box" (the normalised Gaussian's mass in each voxel);
+    n_types: with weighted channels, how many widths the types index."""
     d = GridDesc()
     d.C = int(C)
     d.D, d.H, d.W = (int(x) for x in dims)
@@ -159,6 +162,7 @@ def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigm
         raise ValueError(f"unsupported out_dtype {out_dtype}")
     d.form = FORMS[form] if isinstance(form, str) else int(form)
     d.value = VALUES[value] if isinstance(value, str) else int(value)
+    d.n_types = int(n_types)
     sig = [float(s) for s in sigma]
     if len(sig) > MAX_CHANNELS:
         raise ValueError(f"at most {MAX_CHANNELS} channels")
@@ -177,7 +181,8 @@ class BatchView:
 
     def __init__(self, xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor,
                  origins: Optional[torch.Tensor] = None, spacings: Optional[torch.Tensor] = None,
-                 max_atoms: Optional[int] = None, offsets_host=None):
+                 max_atoms: Optional[int] = None, offsets_host=None,
+                 weights: Optional[torch.Tensor] = None):
         dev = xyz.device
         if dev.type != "cuda":
             raise ValueError("xyz must be a device (cuda/hip) tensor")
@@ -206,6 +211,12 @@ class BatchView:
         b.n_mol = self.n_mol
         b.max_atoms = self.max_atoms
         b.n_atoms = self.n_atoms
+        self.weights = None
+        if weights is not None:
+            self.weights = weights.to(device=dev, dtype=torch.float32).contiguous()
+            if self.weights.dim() != 2 or self.weights.shape[0] != self.n_atoms:
+                raise ValueError("weights must have shape (n_atoms, C)")
+        b.weights = _ptr(self.weights)
         self.c = b
 
 
@@ -280,11 +291,12 @@ class Context:
         return out
 
     def backward(self, desc: GridDesc, batch: BatchView, grad_out: torch.Tensor,
-                 grad_xyz: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+                 grad_xyz: Optional[torch.Tensor], stream: Optional[torch.cuda.Stream] = None,
+                 grad_weights: Optional[torch.Tensor] = None):
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         _check(_lib().pg_grid_backward(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
-                                       _ptr(grad_out), _ptr(grad_xyz), None, 0, s.cuda_stream),
-               "pg_grid_backward")
+                                       _ptr(grad_out), _ptr(grad_xyz), _ptr(grad_weights), None,
+                                       0, s.cuda_stream), "pg_grid_backward")
         return grad_xyz
 
     def autotune(self, desc: GridDesc, batch: BatchView, out: torch.Tensor, reps: int = 5,
@@ -380,12 +392,14 @@ def empty_grid(desc: GridDesc, n_mol: int, device) -> torch.Tensor:
 
 
 class GridFn(torch.autograd.Function):
-    """Differentiable w.r.t. xyz: forward -> pg_grid_forward, backward ->
-    pg_grid_backward (the coordinate adjoint)."""
+    """Differentiable w.r.t. xyz and the channel weights: forward ->
+    pg_grid_forward, backward -> pg_grid_backward (the coordinate adjoint
+    and, for weighted channels, the weight gradient)."""
 
     @staticmethod
-    def forward(ctx_, xyz, types, offsets, origins, spacings, desc, max_atoms, pgctx):
-        batch = BatchView(xyz.detach(), types, offsets, origins, spacings, max_atoms=max_atoms)
+    def forward(ctx_, xyz, types, offsets, origins, spacings, weights, desc, max_atoms, pgctx):
+        batch = BatchView(xyz.detach(), types, offsets, origins, spacings, max_atoms=max_atoms,
+                          weights=None if weights is None else weights.detach())
         out = empty_grid(desc, batch.n_mol, xyz.device)
         pgctx.forward(desc, batch, out)
         ctx_.batch = batch
@@ -400,25 +414,40 @@ class GridFn(torch.autograd.Function):
         want = torch.bfloat16 if ctx_.desc.out_dtype == PG_OUT_BF16 else torch.float32
         if g.dtype != want:
             g = g.to(want)
-        grad_xyz = torch.empty_like(batch.xyz)
-        ctx_.pgctx.backward(ctx_.desc, batch, g, grad_xyz)
-        return grad_xyz, None, None, None, None, None, None, None
+        need_xyz, need_w = ctx_.needs_input_grad[0], ctx_.needs_input_grad[5]
+        grad_xyz = torch.empty_like(batch.xyz) if (need_xyz or not need_w) else None
+        grad_w = torch.empty_like(batch.weights) if need_w else None
+        ctx_.pgctx.backward(ctx_.desc, batch, g, grad_xyz, grad_weights=grad_w)
+        return (grad_xyz if need_xyz else None, None, None, None, None, grad_w, None, None,
+                None)
 
 
 def grid(xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor, sigma: Sequence[float], *,
          dims: Sequence[int], spacing=0.5, origin=(0.0, 0.0, 0.0), origins=None, spacings=None,
          cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32, form: str = "auto",
-         value: str = "point", n_channels: Optional[int] = None,
-         max_atoms: Optional[int] = None, ctx: Optional[Context] = None) -> torch.Tensor:
-    """Density grids (B, C, D, H, W) for a ragged batch (differentiable in xyz).
+         value: str = "point", weights: Optional[torch.Tensor] = None,
+         n_channels: Optional[int] = None, max_atoms: Optional[int] = None,
+         ctx: Optional[Context] = None) -> torch.Tensor:
+    """Density grids (B, C, D, H, W) for a ragged batch (differentiable in
+    xyz, and in weights when given).
 
     xyz (n_atoms, 3) float32, types (n_atoms,) int, offsets (B+1,) int CSR,
-    all on the same device; sigma: one width per channel (C = len(sigma)
-    unless n_channels is given); value "point" or "box" as in make_desc."""
-    C = int(n_channels if n_channels is not None else len(sigma))
-    desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form, value)
+    all on the same device; sigma: one width per type; value "point" or
+    "box" as in make_desc.  Without weights each type is one channel
+    (C = len(sigma) unless n_channels is given).  With weights (n_atoms, C)
+    atom a adds weights[a, c] times its Gaussian to every channel c --
+    e.g. weights = embedding[types] for a learned (T x C) embedding table,
+    whose gradient then flows through torch's indexing."""
+    if weights is not None:
+        C = int(weights.shape[1])
+        n_types = len(sigma)
+    else:
+        C = int(n_channels if n_channels is not None else len(sigma))
+        n_types = 0
+    desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form, value,
+                     n_types)
     pgctx = ctx if ctx is not None else default_context(xyz.device)
-    return GridFn.apply(xyz, types, offsets, origins, spacings, desc, max_atoms, pgctx)
+    return GridFn.apply(xyz, types, offsets, origins, spacings, weights, desc, max_atoms, pgctx)
 
 
 def reverse(target: torch.Tensor, sigma: Sequence[float], *, spacing=0.5,

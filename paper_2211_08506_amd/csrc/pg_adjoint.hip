@@ -5,6 +5,8 @@
 // voxel masses of Eq. 2-5),
 //   dL/dmu_{a,x} = sum_{v in window(a)} U[b, t_a, v] phi_x'(v) phi_y(v) phi_z(v),
 // and likewise for y and z -- the separable coordinate gradient of §IV-C.
+// With weighted channels the atom's upstream is sum_c w_c U[b, c, v], and
+// dL/dw_{a,c} = sum_v U[b, c, v] phi_x phi_y phi_z.
 // For the point sample phi' = phi d / sigma^2 (d = r - mu, nearest image
 // when periodic); for the box, phi' = (g(lower edge) - g(upper edge)) /
 // (sqrt(2 pi) sigma).  The cutoff edge contributes nothing (the map is
@@ -55,7 +57,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
         mu[1] = p.xyz[3 * a + 1];
         mu[2] = p.xyz[3 * a + 2];
         t = p.types[a];
-        if (!atom_valid(mu[0], mu[1], mu[2], t, p.C)) {
+        if (!atom_valid(mu[0], mu[1], mu[2], t, p.n_sig)) {
             if (lane == 0)
                 raise_error(p.err, PG_E_DEVICE_DATA, a);
             t = -1;
@@ -99,28 +101,59 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     }
     __syncthreads();
     float gx = 0.f, gy = 0.f, gz = 0.f;
+    const bool wtd = p.weights != nullptr;
     if (t >= 0) {
         const size_t plane = (size_t)p.H * p.W;
-        const T *U = (const T *)p.out + ((size_t)m * p.C + t) * (size_t)p.D * plane;
         const int nx = n[0], ny = n[1], nz = n[2];
         const int total = nx * ny * nz;
-        for (int e = lane; e < total; e += 64) {
-            const int kx = e % nx;
-            const int r = e / nx;
-            const int ky = r % ny;
-            const int kz = r / ny;
-            const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
-            const float u = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
-            const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
-            const float dx = dphi[kx], dy = dphi[base[1] + ky], dz = dphi[base[2] + kz];
-            gx = __builtin_fmaf(u, dx * (fy * fz), gx);
-            gy = __builtin_fmaf(u, fx * (dy * fz), gy);
-            gz = __builtin_fmaf(u, (fx * fy) * dz, gz);
+        // unweighted: the atom's own channel; weighted: every channel, each
+        // swept with its weight (and its weight gradient when asked for)
+        const int c0 = wtd ? 0 : t, c1 = wtd ? p.C : t + 1;
+        const bool want_gw = wtd && p.grad_w != nullptr;
+        for (int c = c0; c < c1; ++c) {
+            const float wc = wtd ? p.weights[(size_t)a * p.C + c] : 1.f;
+            if (wc == 0.f && !want_gw)
+                continue;
+            const T *U = (const T *)p.out + ((size_t)m * p.C + c) * (size_t)p.D * plane;
+            float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
+            for (int e = lane; e < total; e += 64) {
+                const int kx = e % nx;
+                const int r = e / nx;
+                const int ky = r % ny;
+                const int kz = r / ny;
+                const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
+                const float u = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
+                const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
+                const float dx = dphi[kx], dy = dphi[base[1] + ky], dz = dphi[base[2] + kz];
+                sx = __builtin_fmaf(u, dx * (fy * fz), sx);
+                sy = __builtin_fmaf(u, fx * (dy * fz), sy);
+                sz = __builtin_fmaf(u, (fx * fy) * dz, sz);
+                if (want_gw)
+                    sw = __builtin_fmaf(u, (fx * fy) * fz, sw);
+            }
+            if (want_gw) {
+                sw = wave_sum(sw);
+                if (lane == 0)
+                    p.grad_w[(size_t)a * p.C + c] = sw;
+            }
+            if (wtd) {
+                gx = __builtin_fmaf(wc, sx, gx);
+                gy = __builtin_fmaf(wc, sy, gy);
+                gz = __builtin_fmaf(wc, sz, gz);
+            } else {
+                gx = sx;
+                gy = sy;
+                gz = sz;
+            }
         }
     }
     gx = wave_sum(gx);
     gy = wave_sum(gy);
     gz = wave_sum(gz);
+    if (active && lane == 0 && t < 0 && wtd && p.grad_w) {
+        for (int c = 0; c < p.C; ++c)
+            p.grad_w[(size_t)a * p.C + c] = 0.f;
+    }
     if (active && lane == 0) {
         const float g[3] = {t >= 0 ? gx : 0.f, t >= 0 ? gy : 0.f, t >= 0 ? gz : 0.f};
 #pragma unroll

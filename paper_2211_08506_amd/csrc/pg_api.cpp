@@ -94,10 +94,21 @@ float rc_of(const pg_grid_desc *d, int c)
     return r;
 }
 
+// Entries of the per-type tables (sigma and what derives from it): the
+// channel count, or with weighted channels the declared number of types.
+int n_sig_of(const pg_grid_desc *d, const pg_batch *b)
+{
+    return (b && b->weights && d->n_types > 0) ? d->n_types : d->C;
+}
+
 int validate(const pg_grid_desc *d, const pg_batch *b)
 {
     if (!d || !b)
         return PG_E_NULL;
+    if (d->n_types < 0 || d->n_types > PG_MAX_CHANNELS ||
+        (!b->weights && d->n_types != 0 && d->n_types != d->C))
+        return PG_E_PARAM;
+    const int n_sig = n_sig_of(d, b);
     if (d->C < 1 || d->C > PG_MAX_CHANNELS || d->D < 1 || d->H < 1 || d->W < 1)
         return PG_E_SHAPE;
     if (d->D > 32767 || d->H > 32767 || d->W > 32767)
@@ -127,8 +138,8 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
     }
     if (!std::isfinite(d->cutoff_k) || d->cutoff_k < 0.f)
         return PG_E_PARAM;
-    for (int c = 0; c < d->C; ++c)
-        if (!finite_pos(d->sigma[c]))
+    for (int t = 0; t < n_sig; ++t)
+        if (!finite_pos(d->sigma[t]))
             return PG_E_PARAM;
     if (d->periodic != 0 && d->periodic != 1)
         return PG_E_PARAM;
@@ -141,8 +152,8 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
         for (int q = 0; q < 3; ++q) {
             if (!finite_pos(d->cell[q]))
                 return PG_E_PERIODIC;
-            for (int c = 0; c < d->C; ++c) {
-                const double rc = rc_of(d, c);
+            for (int t = 0; t < n_sig; ++t) {
+                const double rc = rc_of(d, t);
                 if (!(rc < 0.5 * (double)d->cell[q]))
                     return PG_E_PERIODIC;
                 if ((double)N[q] * d->spacing[q] + 2.0 * rc > 2.0 * (double)d->cell[q])
@@ -156,6 +167,8 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
         return PG_E_NULL;
     return PG_OK;
 }
+
+bool weighted(const pg_batch *b) { return b->weights != nullptr && b->n_atoms > 0; }
 
 struct Plan {
     int form = PG_FORM_WINDOW;
@@ -248,7 +261,8 @@ std::string tuning_key(const pg_grid_desc *d, const pg_batch *b, int vec)
     char buf[160];
     std::snprintf(buf, sizeof buf, "C%d_D%d_H%d_W%d_%s_p%d_v%d_nb%d_ma%d%s", d->C, d->D, d->H,
                   d->W, d->out_dtype == PG_OUT_BF16 ? "bf16" : "f32", d->periodic, vec, nb, ma,
-                  d->value == PG_VALUE_BOX ? "_box" : "");
+                  d->value == PG_VALUE_BOX ? (b->weights ? "_box_w" : "_box")
+                                           : (b->weights ? "_w" : ""));
     return buf;
 }
 
@@ -284,7 +298,8 @@ bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Pl
     const int W4 = (d->W + 3) & ~3;
     P.row_stride = (W4 + d->H + d->D + 3) & ~3;
     P.mask_words = (P.a_cap + 63) / 64;
-    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words).total;
+    P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words,
+                       b->weights ? d->C : 0).total;
     P.ws = 0;
     const int max_lds = ctx ? ctx->max_lds : 65536;
     return P.lds <= (size_t)max_lds;
@@ -314,6 +329,9 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
         }
     }
     P.form = form;
+    // weighted channels: the molecule window form and the plain form only
+    if (weighted(b) && (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)))
+        return PG_E_UNSUPPORTED;
     if (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits))
         return crystal_plan(ctx, d, b, form, P);
     if (form == PG_FORM_PLAIN) {
@@ -379,15 +397,17 @@ void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const 
         p.h[q] = d->spacing[q];
         p.L[q] = d->periodic ? d->cell[q] : 0.f;
     }
-    for (int c = 0; c < d->C; ++c) {
-        const double s = d->sigma[c];
-        p.rc[c] = rc_of(d, c);
-        p.inv2s2[c] = (float)(1.0 / (2.0 * s * s));
-        p.invs2[c] = (float)(1.0 / (s * s));
-        p.isq2s[c] = (float)(1.0 / (std::sqrt(2.0) * s));
-        p.inorm[c] = (float)(1.0 / (std::sqrt(2.0 * M_PI) * s));
+    p.n_sig = n_sig_of(d, b);
+    for (int t = 0; t < p.n_sig; ++t) {
+        const double s = d->sigma[t];
+        p.rc[t] = rc_of(d, t);
+        p.inv2s2[t] = (float)(1.0 / (2.0 * s * s));
+        p.invs2[t] = (float)(1.0 / (s * s));
+        p.isq2s[t] = (float)(1.0 / (std::sqrt(2.0) * s));
+        p.inorm[t] = (float)(1.0 / (std::sqrt(2.0 * M_PI) * s));
     }
     p.box = d->value == PG_VALUE_BOX;
+    p.weights = weighted(b) ? b->weights : nullptr;
 }
 
 hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, GridParams &p,
@@ -672,7 +692,8 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
 }
 
 int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
-                     const void *grad_out, float *grad_xyz, void *ws, size_t ws_bytes, void *stream)
+                     const void *grad_out, float *grad_xyz, float *grad_weights, void *ws,
+                     size_t ws_bytes, void *stream)
 {
     (void)ws;
     (void)ws_bytes;
@@ -681,7 +702,9 @@ int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     int s = validate(desc, batch);
     if (s != PG_OK)
         return s;
-    if (batch->n_atoms > 0 && (!grad_out || !grad_xyz))
+    if (grad_weights && !batch->weights)
+        return PG_E_PARAM;
+    if (batch->n_atoms > 0 && (!grad_out || (!grad_xyz && !grad_weights)))
         return PG_E_NULL;
     if (batch->n_atoms == 0)
         return PG_OK;
@@ -692,6 +715,7 @@ int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     GridParams p;
     fill_params(p, ctx, desc, batch, P, const_cast<void *>(grad_out), nullptr);
     p.grad_xyz = grad_xyz;
+    p.grad_w = grad_weights;
     hipError_t e = launch_adjoint(p, desc->out_dtype, (hipStream_t)stream);
     return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
 }

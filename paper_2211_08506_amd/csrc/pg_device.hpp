@@ -375,7 +375,7 @@ __device__ inline int write_atom_window(const GridParams &p, long long a, AtomWi
 {
     const float mu[3] = {p.xyz[3 * a], p.xyz[3 * a + 1], p.xyz[3 * a + 2]};
     const int t = p.types[a];
-    const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.C);
+    const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.n_sig);
     if (!ok)
         raise_error(p.err, PG_E_DEVICE_DATA, a);
     const int m = structure_of(p.offsets, p.n_mol, a);

@@ -11,10 +11,11 @@ namespace pg {
 
 // Byte offsets of the window kernel's dynamic LDS regions.
 struct WindowLds {
-    size_t rows, ranges, masks, types, total;
+    size_t rows, ranges, masks, types, wts, total;
 };
 
-WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words);
+// weight_ch: channels of per-atom weights held in LDS (0: unweighted)
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int weight_ch);
 
 // Persistent molecule window kernel (pg_window.hip); unroll: runs per lane
 // per pass (1, 2 or 4).

@@ -53,6 +53,12 @@ struct GridParams {
     float *loss;
     float *xyz_upd;
     float lr;
+    // weighted channels: n_atoms x C weights (nullptr: one channel per type),
+    // their gradient (backward, may be nullptr), and the number of entries
+    // of the per-type tables (rc, inv2s2, ...) the types index
+    const float *weights;
+    float *grad_w;
+    int32_t n_sig;
 };
 
 // Peak search of grid reversal: local maxima of every channel of a batch of

@@ -6,7 +6,8 @@
 //        thread visits every atom of its structure, tests the three axis
 //        windows and adds the 3-D Gaussian exp(-|r - mu|^2 / (2 sigma^2))
 //        (§III-A Eq. 1, point-sampled, without the prefactor), or for the box
-//        form the product of the three per-axis voxel masses.  This is the
+//        form the product of the three per-axis voxel masses (with weighted
+//        channels: every atom, times its weight for the channel).  This is the
 //        straightforward GPU transcription of the definition; the batched
 //        window kernel is measured against it.
 #include "pg_device.hpp"
@@ -44,12 +45,23 @@ __global__ void __launch_bounds__(256) plain_kernel(GridParams p)
     int a0 = p.offsets[m], a1 = p.offsets[m + 1];
     if (a0 < 0 || a1 < a0 || (long long)a1 > p.n_atoms)
         a0 = a1 = 0;   // malformed offsets: nothing is read
-    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c];
     const bool box = p.box != 0;
+    const float *wts = p.weights;
     float acc = 0.f;
     for (int a = a0; a < a1; ++a) {
-        if (tab[a].type != c)
+        const int t = tab[a].type;
+        float wgt = 1.f;
+        if (wts) {
+            // weighted channels: every valid atom, scaled by its weight
+            if (t < 0)
+                continue;
+            wgt = wts[(size_t)a * p.C + c];
+            if (wgt == 0.f)
+                continue;
+        } else if (t != c) {
             continue;
+        }
+        const float inv2s2 = p.inv2s2[t], isq2s = p.isq2s[t];
         float d2 = 0.f, mass = 1.f;
         bool inside = true;
         for (int q = 0; q < 3 && inside; ++q) {
@@ -69,8 +81,10 @@ __global__ void __launch_bounds__(256) plain_kernel(GridParams p)
             }
             inside = hit;
         }
-        if (inside)
-            acc += box ? mass : expf(-d2 * inv2s2);
+        if (inside) {
+            const float v = box ? mass : expf(-d2 * inv2s2);
+            acc += wts ? wgt * v : v;
+        }
     }
     const float v[1] = {acc};
     store_vec<T, 1>((T *)p.out + (size_t)m * p.C * vol + e, v, false);

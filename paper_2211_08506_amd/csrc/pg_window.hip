@@ -8,7 +8,9 @@
 //   2. fills dense 1-D factor rows phi_x[W] | phi_y[H] | phi_z[D] per atom in
 //      LDS (zeros outside the window; the separable per-axis tables of
 //      §VI-A) and, per (channel, z) plane, a bit mask of the atoms of that
-//      channel whose z-window contains the plane;
+//      channel whose z-window contains the plane (with weighted channels:
+//      of the atoms with a non-zero weight for the channel, the weights
+//      being staged in LDS too and folded into phi_z);
 //   3. streams the structure's C x D x H x W output plane by plane: each
 //      wave takes whole (c, z) planes, each lane U runs of VEC consecutive x
 //      (16 bytes each), accumulates sum_a phi_z[a][z] phi_y[a][y] phi_x[a][x..]
@@ -35,7 +37,7 @@ struct RangeRec {
 };
 
 __host__ __device__ inline WindowLds window_lds_layout(int a_cap, int row_stride, int C, int D,
-                                                      int mask_words)
+                                                      int mask_words, int weight_ch)
 {
     WindowLds L;
     size_t off = 0;
@@ -49,13 +51,15 @@ __host__ __device__ inline WindowLds window_lds_layout(int a_cap, int row_stride
     off += (size_t)C * D * mask_words * sizeof(unsigned long long);
     L.types = off;
     off += (size_t)a_cap * sizeof(int32_t);
+    L.wts = off;
+    off += (size_t)a_cap * weight_ch * sizeof(float);
     L.total = (off + 15) & ~(size_t)15;
     return L;
 }
 
-WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words)
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int weight_ch)
 {
-    return window_lds_layout(a_cap, row_stride, C, D, mask_words);
+    return window_lds_layout(a_cap, row_stride, C, D, mask_words, weight_ch);
 }
 
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v)
@@ -91,11 +95,13 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     const int RS = p.row_stride;
     const int W4 = (W + 3) & ~3;
     const int MW = p.mask_words;
-    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW);
+    const int WC = p.weights ? C : 0;
+    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW, WC);
     float *rows = (float *)(smem + lay.rows);
     RangeRec *rr = (RangeRec *)(smem + lay.ranges);
     unsigned long long *masks = (unsigned long long *)(smem + lay.masks);
     int32_t *atype = (int32_t *)(smem + lay.types);
+    float *wl = (float *)(smem + lay.wts);
 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
@@ -129,12 +135,14 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
         // ---- 1. window ranges per (atom, axis); clear plane masks
         for (int i = tid; i < planes * MW; i += nthr)
             masks[i] = 0ull;
+        for (int i = tid; i < na * WC; i += nthr)
+            wl[i] = p.weights[(size_t)a0 * C + i];
         for (int i = tid; i < na * 3; i += nthr) {
             const int a = i / 3, ax = i - 3 * a;
             const size_t ga = (size_t)a0 + a;
             const float x = p.xyz[3 * ga + 0], y = p.xyz[3 * ga + 1], zc = p.xyz[3 * ga + 2];
             const int t = p.types[ga];
-            const bool ok = atom_valid(x, y, zc, t, C);
+            const bool ok = atom_valid(x, y, zc, t, p.n_sig);
             RangeRec R;
             R.n = 0;
             if (ok) {
@@ -183,8 +191,17 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                     if (i >= R.lo[r] && i <= R.hi[r]) {
                         v = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[t],
                                      p.isq2s[t]);
-                        if (ax == 2)
-                            atomicOr(&masks[(size_t)(t * D + i) * MW + (a >> 6)], 1ull << (a & 63));
+                        if (ax == 2) {
+                            if (WC == 0) {
+                                atomicOr(&masks[(size_t)(t * D + i) * MW + (a >> 6)],
+                                         1ull << (a & 63));
+                            } else {
+                                for (int c = 0; c < C; ++c)
+                                    if (wl[a * WC + c] != 0.f)
+                                        atomicOr(&masks[(size_t)(c * D + i) * MW + (a >> 6)],
+                                                 1ull << (a & 63));
+                            }
+                        }
                     }
                 }
             }
@@ -199,6 +216,7 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
         float sq = 0.f;
         for (int pl = wave; pl < planes; pl += nwaves) {
             const int z = pl % D;
+            const int pc = pl / D;
             unsigned long long mk[4];
 #pragma unroll
             for (int w = 0; w < 4; ++w)
@@ -229,7 +247,9 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                         const int a = w * 64 + __builtin_ctzll(bits);
                         bits &= bits - 1;
                         const float *row = rows + a * RS;
-                        const float gz = row[W4 + H + z];
+                        float gz = row[W4 + H + z];
+                        if (WC)
+                            gz *= wl[a * WC + pc];
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const float gy = row[W4 + yq[u]] * gz;

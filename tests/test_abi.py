@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_abi_version_and_status_strings():
-    assert pg.abi_version() == 2
+    assert pg.abi_version() == 3
     lib = pg._lib()
     for s in range(0, 10):
         assert lib.pg_status_str(s)
@@ -165,6 +165,45 @@ def test_workspace_and_plan_host_only():
     assert info.binned == 0
 
 
+def test_weighted_channels_validation_and_plans():
+    """Weighted channels: types index n_types widths independent of C; the
+    window and plain forms take them, the binned path does not; the window
+    form stages the weights in LDS."""
+    lib = pg._lib()
+    info = pg.PlanInfo()
+    sig8 = [0.4 + 0.3 * i / 7 for i in range(8)]
+    bw = batch_ok()
+    bw.weights = 0x3000
+    d = desc_ok(C=3, sigma=sig8)
+    d.n_types = 8                      # 8 types into 3 channels
+    assert validate(d, bw) == pg.PG_OK
+    d.sigma[7] = 0.0                   # every width the types index is checked
+    assert validate(d, bw) == pg.PG_E_PARAM
+    d = desc_ok(C=3, sigma=sig8)
+    d.n_types = 65
+    assert validate(d, bw) == pg.PG_E_PARAM
+    d.n_types = 8
+    assert validate(d, batch_ok()) == pg.PG_E_PARAM     # n_types without weights must be C
+    d = desc_ok()
+    d.n_types = 5
+    assert validate(d, batch_ok()) == pg.PG_OK
+    # plans: window holds the weights in LDS; binned path refuses them
+    d = desc_ok()
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(batch_ok()), 0x10000,
+                       ctypes.byref(info)) == 0
+    lds0 = info.lds_bytes
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(bw), 0x10000, ctypes.byref(info)) == 0
+    assert info.form == pg.FORMS["window"] and info.lds_bytes == lds0 + 16 * 5 * 4
+    big = batch_ok(n_atoms=4000, max_atoms=1000)
+    big.weights = 0x3000
+    for form in ("auto", "window", "mfma"):
+        d = desc_ok(form=form, out_dtype="bf16")
+        assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000,
+                           ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
+    d = desc_ok(form="plain")
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000, ctypes.byref(info)) == 0
+
+
 def test_reversal_workspace_host_only():
     """The molecule window form forms the residual in its forward kernel (no
     workspace); other forms need FP64 partial loss sums (one per 4096
@@ -194,7 +233,8 @@ def test_null_context_calls_fail_cleanly():
     d = desc_ok()
     b = batch_ok()
     assert lib.pg_grid_forward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, None, 0, None) == pg.PG_E_NULL
-    assert lib.pg_grid_backward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, 0x1000, None, 0, None) == pg.PG_E_NULL
+    assert lib.pg_grid_backward(None, ctypes.byref(d), ctypes.byref(b), 0x1000, 0x1000, None, None,
+                                0, None) == pg.PG_E_NULL
     assert lib.pg_set_option(None, 1, 1) == pg.PG_E_NULL
     assert lib.pg_find_peaks(None, ctypes.byref(d), 0x1000, 4, None, None, 0.1, 16, 0x1000,
                              0x1000, 0x1000, 0x1000, None) == pg.PG_E_NULL
