@@ -195,6 +195,9 @@ def main():
     ap.add_argument("--workload", default="mol4096", choices=sorted(METRICS))
     ap.add_argument("--value", default="point", choices=("point", "box"),
                     help="voxel value: the Gaussian at the centre, or its mass in the voxel")
+    ap.add_argument("--embed", type=int, default=0,
+                    help="weighted channels: a dense seeded embedding of the element types "
+                         "into this many channels (molecule forward workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain fp32 baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -228,13 +231,24 @@ def main():
     xyz = torch.tensor(b.xyz, device=dev)
     types = torch.tensor(b.types, device=dev)
     offs = torch.tensor(b.offsets, device=dev)
-    bv = pg.BatchView(xyz, types, offs, offsets_host=b.offsets)
     B = b.n_mol
     C = wl.n_types
+    ntypes = 0
+    E = None
+    if args.embed:
+        if wl.kind == "crystal" or wl.name in ("adjoint1024", "reversal1024"):
+            print("bench.py: --embed applies to the molecule forward workloads", file=sys.stderr)
+            sys.exit(2)
+        table = synth.embedding(wl.seed + 100, wl.n_types, args.embed)
+        E = table[b.types]
+        C, ntypes = args.embed, wl.n_types
+    bv = pg.BatchView(xyz, types, offs, offsets_host=b.offsets,
+                      weights=None if E is None else torch.tensor(E, device=dev))
     D, H, W = wl.dims
     vox = C * D * H * W
-    in_bytes = 16 * b.n_atoms + 4 * (B + 1)
-    evals = window_evals(b, wl)
+    in_bytes = 16 * b.n_atoms + 4 * (B + 1) + (4 * C * b.n_atoms if E is not None else 0)
+    # a dense embedding adds every atom to every channel
+    evals = window_evals(b, wl) * (C if E is not None else 1)
     log(f"[bench] {b.n_atoms} atoms, {evals} atom-voxel evaluations per pass")
 
     ctx = pg.Context(0, tuning=args.tuning or "shipped")
@@ -242,14 +256,15 @@ def main():
     launch = "direct launch" if args.no_graph else "HIP graph"
     extra = {}
     value = args.value
-    metric = METRICS[wl.name] + (" [box form]" if value == "box" else "")
+    metric = METRICS[wl.name] + (" [box form]" if value == "box" else "") + \
+        (f" [embedding {wl.n_types} types -> {C} channels]" if E is not None else "")
     rec = {"metric": metric, "unit": "grids/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
 
     def forward_case(out_dt, form, autotune, steps, warmup):
         desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
-                            out_dt, form, value)
+                            out_dt, form, value, ntypes)
         out = pg.empty_grid(desc, B, dev)
         if autotune and not args.no_autotune:
             log(f"[bench] autotuning {form} {out_dt}")
@@ -373,7 +388,7 @@ def main():
             if not args.no_baseline:
                 ctx_p = pg.Context(0)
                 descp = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k,
-                                     wl.cell, torch.float32, "plain", value)
+                                     wl.cell, torch.float32, "plain", value, ntypes)
                 outp = pg.empty_grid(descp, B, dev)
                 wp, ep = timed_steps(lambda: ctx_p.forward(descp, bv, outp, stream), 3, 1, torch,
                                      stream)
@@ -386,7 +401,7 @@ def main():
         if args.save_tuning:
             ctx.tuning_save(args.save_tuning)
         traffic = None
-        if wl.kind != "crystal" and value == "point":
+        if wl.kind != "crystal" and value == "point" and E is None:
             traffic = measured_traffic(f"window_{wl.name}_{'bf16' if esize == 2 else 'f32'}",
                                        source_digest(WINDOW_SOURCES))
         rec.update({
@@ -409,6 +424,8 @@ def main():
     else:
         desc_w = (f"{wl.name}: {B} molecules of {wl.atoms[0]}-{wl.atoms[1]} atoms "
                   f"(H/C/N/O/F p=0.5/0.3/0.1/0.08/0.02, {wl.box:g} A box)")
+    if E is not None:
+        desc_w += f", weighted channels: dense U(0.1, 1) embedding of {wl.n_types} types"
     rec["config"] = {"workload": f"{desc_w}, {C}x{D}x{H}x{W} grid at {wl.spacing} A, cutoff "
                                  f"{wl.cutoff_k:g} sigma, {kind}, {value} form, {launch}",
                      "batch": B, "grid": [C, D, H, W], "n_atoms": int(b.n_atoms),
@@ -448,7 +465,8 @@ def main():
             def run_one(u):
                 s = u[1]
                 cpu_oracle.grid_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
-                                     wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell, value=value)
+                                     wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell, value=value,
+                                     weights=None if E is None else table[s.types])
                 return s.n_mol
         cpu_units = units
         log(f"[bench] FP64 CPU oracle on a bounded sample (~{args.cpu_seconds:.0f} s)")

@@ -143,6 +143,12 @@ def upstream(seed: int, shape: Sequence[int]) -> np.ndarray:
     return rng_for(seed).standard_normal(size=tuple(shape), dtype=np.float32)
 
 
+def embedding(seed: int, n_types: int, n_channels: int) -> np.ndarray:
+    """A dense channel-embedding table of the element types, i.i.d.
+    U(0.1, 1) per entry, float32 (n_types x n_channels)."""
+    return rng_for(seed).uniform(0.1, 1.0, size=(n_types, n_channels)).astype(np.float32)
+
+
 def perturbation(seed: int, n_atoms: int, amp: float) -> np.ndarray:
     """Coordinate displacements, i.i.d. uniform in [-amp, amp] A per axis,
     float32 (the starting point of a grid-reversal workload)."""
