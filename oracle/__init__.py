@@ -13,6 +13,8 @@ Functions:
               decisions, for tiny grids (brute.py)
   reversal    grid reversal of §IV: local-maximum peaks and the coordinate
               descent step on the squared grid error (reversal.py)
+  triclinic   triclinic periodic cells: lattice images passed to the
+              non-periodic map (triclinic.py)
 
 What is computed is the point-sampled, un-normalised Gaussian of §III-A
 Eq. 1 at voxel centres (value="point"), or the integral of the normalised
