@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define PG_ABI_VERSION 3
+#define PG_ABI_VERSION 4
 #define PG_MAX_CHANNELS 64
 
 typedef enum pg_status {
@@ -105,15 +105,39 @@ typedef struct pg_grid_desc {
     float origin[3];             /* lower grid corner, x y z; used when batch->origins == NULL */
     float spacing[3];            /* voxel edge hx hy hz > 0; used when batch->spacings == NULL */
     float cutoff_k;              /* cutoff in units of sigma_t (>= 0); 0 = no cutoff */
-    int32_t periodic;            /* 0/1: orthorhombic nearest image with cell[] */
-    float cell[3];               /* periodic cell edges Lx Ly Lz (periodic only) */
+    int32_t periodic;            /* PG_CELL_NONE, PG_CELL_ORTHO (cell[]) or
+                                    PG_CELL_TRICLINIC (cell_matrix[]) */
+    float cell[3];               /* orthorhombic cell edges Lx Ly Lz */
     int32_t out_dtype;           /* PG_OUT_F32 or PG_OUT_BF16 (round-to-nearest-even) */
     int32_t form;                /* PG_FORM_* */
     float sigma[PG_MAX_CHANNELS];/* Gaussian width (standard deviation) per type, > 0 */
     int32_t value;               /* PG_VALUE_POINT or PG_VALUE_BOX */
     int32_t n_types;             /* with batch->weights: entries of sigma[] the types index
                                     (1..64); 0 means C.  Without weights: 0 or C */
+    float cell_matrix[9];        /* triclinic cell, row-major: cell_matrix[3 * alpha + j] is
+                                    the alpha (x, y, z) component of lattice vector j */
 } pg_grid_desc;
+
+/* Periodic cells (§III-A: a structure's density sums the lattice
+   translations of each atom).
+   PG_CELL_ORTHO: an orthorhombic cell; every voxel uses the nearest image
+   per axis, decided exactly (rc_t < L/2 and grid extent + 2 rc_t <= 2 L).
+   PG_CELL_TRICLINIC: a general cell M = cell_matrix.  Every atom
+   contributes through each lattice image mu + M n (n integer) that
+   image's Gaussian truncated to its own cutoff cube; the cell must keep
+   the cubes of distinct images of one atom apart (for every n != 0 with
+   |n_j| <= 4: max_alpha |(M n)_alpha| > 2 rc_max), so a voxel sees at
+   most one image of each atom.  An image's position is fl32(mu_alpha +
+   ((n_0 M[alpha][0] + n_1 M[alpha][1]) + n_2 M[alpha][2])) evaluated in
+   double and rounded once; its windows are then decided exactly as for a
+   non-periodic atom.  The library expands each atom into the K images of a
+   fixed lattice range that can reach the grid (K <= 64, else
+   PG_E_PERIODIC) and runs the non-periodic map on them, so the workspace
+   grows with K.  Not with per-structure spacings, weighted channels,
+   pg_autotune or pg_reversal_step (PG_E_UNSUPPORTED).  A device error on
+   an image reports the image index atom * K + k; the expansion itself
+   reports invalid atoms by atom index. */
+enum { PG_CELL_NONE = 0, PG_CELL_ORTHO = 1, PG_CELL_TRICLINIC = 2 };
 
 /* A ragged batch of structures (device arrays unless noted). */
 typedef struct pg_batch {
@@ -158,13 +182,15 @@ int pg_destroy(pg_ctx *ctx);
 
 /* Host-only validation of a request (no HIP call, no device access).
    Checks dims, channel count, sigma/spacing/cutoff, periodic constraints
-   (rc_t < L/2 and grid extent + 2 rc_t <= 2 L on every axis, cutoff_k > 0),
-   batch sizes and non-NULL device pointers.  Returns PG_OK or the first
+   (orthorhombic: rc_t < L/2 and grid extent + 2 rc_t <= 2 L on every axis;
+   triclinic: the image-cube separation and the image count; both:
+   cutoff_k > 0), batch sizes and non-NULL device pointers.  Returns PG_OK or the first
    error found. */
 int pg_validate(const pg_grid_desc *desc, const pg_batch *batch);
 
 /* Bytes of caller-provided device workspace that pg_grid_forward and
-   pg_grid_backward need for this request (0 is possible).  Host only.
+   pg_grid_backward need for this request (0 is possible; triclinic cells
+   need it in pg_grid_backward too).  Host only.
    The form used is the one pg_grid_forward would pick (desc->form or the
    AUTO rule); ctx may be NULL (then tuned choices are not consulted). */
 int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
@@ -196,6 +222,8 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
    grad_weights (n_atoms x C float32, or NULL) receives
    dL/dweights[a][c] = sum over the window of grad_out[b][c][v] G_a(v)
    (skipped atoms get 0).  grad_xyz may be NULL when grad_weights is not.
+   ws/ws_bytes: pg_workspace_size() bytes for a triclinic cell (the image
+   expansion and the image gradients); other requests take NULL, 0.
    Errors: as pg_grid_forward. */
 int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
                      const void *grad_out, float *grad_xyz, float *grad_weights, void *ws,

@@ -22,6 +22,7 @@ import os
 import threading
 from typing import Optional, Sequence, Tuple, Union
 
+import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +37,7 @@ PG_OUT_F32, PG_OUT_BF16 = 0, 1
 FORMS = {"auto": 0, "plain": 1, "window": 2, "mfma": 3}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
 VALUES = {"point": 0, "box": 1}
+PG_CELL_NONE, PG_CELL_ORTHO, PG_CELL_TRICLINIC = 0, 1, 2
 PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL = 1, 2, 3, 4, 5
 MAX_CHANNELS = 64
 
@@ -54,7 +56,8 @@ class GridDesc(ctypes.Structure):
                 ("cutoff_k", ctypes.c_float), ("periodic", ctypes.c_int32),
                 ("cell", ctypes.c_float * 3), ("out_dtype", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("sigma", ctypes.c_float * MAX_CHANNELS),
-                ("value", ctypes.c_int32), ("n_types", ctypes.c_int32)]
+                ("value", ctypes.c_int32), ("n_types", ctypes.c_int32),
+                ("cell_matrix", ctypes.c_float * 9)]
 
 
 class Batch(ctypes.Structure):
@@ -142,7 +145,9 @@ def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigm
               form: Union[str, int] = "auto", value: Union[str, int] = "point",
               n_types: int = 0) -> GridDesc:
     """Build a pg_grid_desc (host struct).  dims = (D, H, W) = (z, y, x);
-    origin / spacing / cell in x, y, z order; sigma one width per type
+    origin / spacing in x, y, z order; cell: None, a scalar or 3 edges
+    (orthorhombic), or a 3 x 3 matrix whose column j is lattice vector j
+    (triclinic); sigma one width per type
     (= per channel unless weighted); value "point" (the Gaussian at voxel
     centres) or "box" (the normalised Gaussian's mass in each voxel);
     n_types: with weighted channels, how many widths the types index."""
@@ -152,8 +157,15 @@ def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigm
     d.origin[:] = _f3(origin)
     d.spacing[:] = _f3(spacing)
     d.cutoff_k = float(cutoff_k)
-    d.periodic = 0 if cell is None else 1
-    d.cell[:] = _f3(cell if cell is not None else 0.0)
+    if cell is None:
+        d.periodic = PG_CELL_NONE
+        d.cell[:] = (0.0, 0.0, 0.0)
+    elif np.asarray(cell).size == 9:
+        d.periodic = PG_CELL_TRICLINIC
+        d.cell_matrix[:] = [float(x) for x in np.asarray(cell, np.float64).reshape(3, 3).ravel()]
+    else:
+        d.periodic = PG_CELL_ORTHO
+        d.cell[:] = _f3(cell)
     if out_dtype in (torch.float32, "f32", PG_OUT_F32):
         d.out_dtype = PG_OUT_F32
     elif out_dtype in (torch.bfloat16, "bf16", PG_OUT_BF16):
@@ -294,9 +306,11 @@ class Context:
                  grad_xyz: Optional[torch.Tensor], stream: Optional[torch.cuda.Stream] = None,
                  grad_weights: Optional[torch.Tensor] = None):
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = self.workspace_size(desc, batch) if desc.periodic == PG_CELL_TRICLINIC else 0
+        ws = self.workspace(nbytes)
         _check(_lib().pg_grid_backward(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
-                                       _ptr(grad_out), _ptr(grad_xyz), _ptr(grad_weights), None,
-                                       0, s.cuda_stream), "pg_grid_backward")
+                                       _ptr(grad_out), _ptr(grad_xyz), _ptr(grad_weights),
+                                       _ptr(ws), nbytes, s.cuda_stream), "pg_grid_backward")
         return grad_xyz
 
     def autotune(self, desc: GridDesc, batch: BatchView, out: torch.Tensor, reps: int = 5,

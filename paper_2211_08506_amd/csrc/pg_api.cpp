@@ -101,6 +101,8 @@ int n_sig_of(const pg_grid_desc *d, const pg_batch *b)
     return (b && b->weights && d->n_types > 0) ? d->n_types : d->C;
 }
 
+int tri_check(const pg_grid_desc *d, const pg_batch *b);
+
 int validate(const pg_grid_desc *d, const pg_batch *b)
 {
     if (!d || !b)
@@ -141,9 +143,19 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
     for (int t = 0; t < n_sig; ++t)
         if (!finite_pos(d->sigma[t]))
             return PG_E_PARAM;
-    if (d->periodic != 0 && d->periodic != 1)
+    if (d->periodic != PG_CELL_NONE && d->periodic != PG_CELL_ORTHO &&
+        d->periodic != PG_CELL_TRICLINIC)
         return PG_E_PARAM;
-    if (d->periodic) {
+    if (d->periodic == PG_CELL_TRICLINIC) {
+        if (d->cutoff_k == 0.f)
+            return PG_E_PERIODIC;
+        if (b->spacings || b->weights)
+            return PG_E_UNSUPPORTED;
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(d->cell_matrix[i]))
+                return PG_E_PERIODIC;
+    }
+    if (d->periodic == PG_CELL_ORTHO) {
         if (d->cutoff_k == 0.f)
             return PG_E_PERIODIC;
         if (b->spacings)
@@ -165,10 +177,134 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
         return PG_E_NULL;
     if (b->n_atoms > 0 && (!b->xyz || !b->types))
         return PG_E_NULL;
+    if (d->periodic == PG_CELL_TRICLINIC)
+        return tri_check(d, b);
     return PG_OK;
 }
 
 bool weighted(const pg_batch *b) { return b->weights != nullptr && b->n_atoms > 0; }
+
+// Triclinic request: the image expansion (lattice range, K images per atom,
+// workspace layout) and the equivalent non-periodic request over images.
+struct Tri {
+    bool on = false;
+    TriParams q;
+    pg_grid_desc din;
+    pg_batch bin;
+    size_t off_types = 0, off_offs = 0, off_grad = 0, inner_off = 0;
+};
+
+size_t align256(size_t v);
+
+constexpr int kTriMaxImages = 64;
+constexpr int kTriCheckReach = 4;
+
+int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
+{
+    T.on = d->periodic == PG_CELL_TRICLINIC;
+    if (!T.on)
+        return PG_OK;
+    std::memset(&T.q, 0, sizeof T.q);
+    double *M = T.q.M, *Mi = T.q.Minv;
+    for (int i = 0; i < 9; ++i)
+        M[i] = d->cell_matrix[i];
+    const double det = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                       M[2] * (M[3] * M[7] - M[4] * M[6]);
+    if (!std::isfinite(det) || std::fabs(det) < 1e-12)
+        return PG_E_PERIODIC;
+    Mi[0] = (M[4] * M[8] - M[5] * M[7]) / det;
+    Mi[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+    Mi[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+    Mi[3] = (M[5] * M[6] - M[3] * M[8]) / det;
+    Mi[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+    Mi[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+    Mi[6] = (M[3] * M[7] - M[4] * M[6]) / det;
+    Mi[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+    Mi[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+    double rc_max = 0.0;
+    for (int t = 0; t < n_sig_of(d, b); ++t)
+        rc_max = std::max(rc_max, (double)rc_of(d, t));
+    // distinct images of one atom keep their cutoff cubes apart
+    const int R = kTriCheckReach;
+    for (int n0 = -R; n0 <= R; ++n0)
+        for (int n1 = -R; n1 <= R; ++n1)
+            for (int n2 = -R; n2 <= R; ++n2) {
+                if (!n0 && !n1 && !n2)
+                    continue;
+                double cheb = 0.0;
+                for (int al = 0; al < 3; ++al)
+                    cheb = std::max(cheb, std::fabs(n0 * M[3 * al] + n1 * M[3 * al + 1] +
+                                                    n2 * M[3 * al + 2]));
+                if (!(cheb > 2.0 * rc_max))
+                    return PG_E_PERIODIC;
+            }
+    // lattice range of a home-cell copy (fractional coordinates in [0, 1))
+    // whose images can reach the grid box widened by rc_max
+    const int N[3] = {d->W, d->H, d->D};
+    double gmin[3] = {1e300, 1e300, 1e300}, gmax[3] = {-1e300, -1e300, -1e300};
+    for (int c = 0; c < 8; ++c) {
+        double x[3];
+        for (int al = 0; al < 3; ++al) {
+            const double lo = (double)d->origin[al] - rc_max;
+            const double hi = (double)d->origin[al] + N[al] * (double)d->spacing[al] + rc_max;
+            x[al] = (c >> al) & 1 ? hi : lo;
+        }
+        for (int j = 0; j < 3; ++j) {
+            const double g = Mi[3 * j] * x[0] + Mi[3 * j + 1] * x[1] + Mi[3 * j + 2] * x[2];
+            gmin[j] = std::min(gmin[j], g);
+            gmax[j] = std::max(gmax[j], g);
+        }
+    }
+    long long K = 1;
+    for (int j = 0; j < 3; ++j) {
+        const double lo = std::ceil(gmin[j] - 1.0 - 1e-6), hi = std::floor(gmax[j] + 1e-6);
+        if (!(hi - lo + 1 <= kTriMaxImages))
+            return PG_E_PERIODIC;
+        T.q.klo[j] = (int32_t)lo;
+        T.q.kdim[j] = (int32_t)std::max(1.0, hi - lo + 1);
+        K *= T.q.kdim[j];
+    }
+    if (K > kTriMaxImages)
+        return PG_E_PERIODIC;
+    if ((long long)b->n_atoms * K > 2147483647LL)
+        return PG_E_SHAPE;
+    T.q.K = (int32_t)K;
+    T.q.n_mol = b->n_mol;
+    T.q.n_atoms = b->n_atoms;
+    T.din = *d;
+    T.din.periodic = PG_CELL_NONE;
+    T.bin = *b;
+    T.bin.n_atoms = b->n_atoms * K;
+    T.bin.max_atoms = (int32_t)std::min<long long>((long long)b->max_atoms * K, 2147483647LL);
+    const size_t nk = (size_t)T.bin.n_atoms;
+    T.off_types = align256(nk * 12);
+    T.off_offs = T.off_types + align256(nk * 4);
+    T.off_grad = T.off_offs + align256(((size_t)b->n_mol + 1) * 4);
+    T.inner_off = T.off_grad + align256(nk * 12);
+    return PG_OK;
+}
+
+int tri_check(const pg_grid_desc *d, const pg_batch *b)
+{
+    Tri T;
+    return tri_setup(d, b, T);
+}
+
+// Point the expansion and the inner batch at the workspace.
+void tri_bind(Tri &T, const pg_batch *b, void *ws)
+{
+    unsigned char *w = (unsigned char *)ws;
+    T.q.xyz = b->xyz;
+    T.q.types = b->types;
+    T.q.offsets = b->offsets;
+    T.q.exp_xyz = (float *)w;
+    T.q.exp_types = (int32_t *)(w + T.off_types);
+    T.q.exp_offsets = (int32_t *)(w + T.off_offs);
+    T.q.grad_img = (const float *)(w + T.off_grad);
+    T.bin.xyz = T.q.exp_xyz;
+    T.bin.types = T.q.exp_types;
+    T.bin.offsets = T.q.exp_offsets;
+}
 
 struct Plan {
     int form = PG_FORM_WINDOW;
@@ -310,6 +446,9 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
     int s = validate(d, b);
     if (s != PG_OK)
         return s;
+    // a triclinic request is planned over its images (plan_request)
+    if (d->periodic == PG_CELL_TRICLINIC)
+        return PG_E_UNSUPPORTED;
     P.vec = pick_vec(d, out);
     const bool fits = window_fits(ctx, d, b, P);
     int form = d->form;
@@ -366,6 +505,28 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
     const int n_cu = ctx ? ctx->n_cu : 256;
     P.grid = window_grid(b, P, n_cu);
     return PG_OK;
+}
+
+// Validate, then plan the request: for a triclinic cell the plan of the
+// non-periodic request over the images (T.on), whose workspace follows
+// the expansion's.  total_ws: all workspace bytes.
+int plan_request(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const void *out,
+                 Plan &P, Tri &T, size_t &total_ws)
+{
+    int s = validate(d, b);
+    if (s != PG_OK)
+        return s;
+    s = tri_setup(d, b, T);
+    if (s != PG_OK)
+        return s;
+    if (!T.on) {
+        s = make_plan(ctx, d, b, out, P);
+        total_ws = P.ws;
+        return s;
+    }
+    s = make_plan(ctx, &T.din, &T.bin, out, P);
+    total_ws = T.inner_off + P.ws;
+    return s;
 }
 
 void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b,
@@ -645,10 +806,12 @@ int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batc
         return PG_E_NULL;
     *bytes = 0;
     Plan P;
-    int s = make_plan(ctx, desc, batch, nullptr, P);
+    Tri T;
+    size_t total = 0;
+    int s = plan_request(ctx, desc, batch, nullptr, P, T, total);
     if (s != PG_OK)
         return s;
-    *bytes = P.ws;
+    *bytes = total;
     return PG_OK;
 }
 
@@ -658,7 +821,9 @@ int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, 
     if (!info)
         return PG_E_NULL;
     Plan P;
-    int s = make_plan(ctx, desc, batch, out, P);
+    Tri T;
+    size_t total = 0;
+    int s = plan_request(ctx, desc, batch, out, P, T, total);
     if (s != PG_OK)
         return s;
     info->form = P.form;
@@ -684,11 +849,39 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
         return PG_E_NULL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     Plan P;
-    int s = make_plan(ctx, desc, batch, out, P);
+    Tri T;
+    size_t total = 0;
+    int s = plan_request(ctx, desc, batch, out, P, T, total);
     if (s != PG_OK)
         return s;
     DeviceGuard g(ctx->device);
-    return forward_impl(ctx, desc, batch, out, ws, ws_bytes, (hipStream_t)stream, P);
+    if (!T.on)
+        return forward_impl(ctx, desc, batch, out, ws, ws_bytes, (hipStream_t)stream, P);
+    // triclinic: expand the atoms into their lattice images in the
+    // workspace, then the non-periodic map over the images
+    if (batch->n_mol > 0 && !out)
+        return PG_E_NULL;
+    if (ws_bytes < total || (total > 0 && !ws))
+        return PG_E_WORKSPACE;
+    if (batch->n_mol == 0)
+        return PG_OK;
+    tri_bind(T, batch, ws);
+    GridParams p;
+    fill_params(p, ctx, &T.din, &T.bin, P, out, (unsigned char *)ws + T.inner_off);
+    const int n_sig = p.n_sig;
+    std::string key;
+    if (ctx->use_graph) {
+        key = graph_key(desc, batch, P, out, ws, ws_bytes);
+        key.append("triclinic");
+    }
+    return run_launches(ctx, ctx->use_graph != 0, key, (hipStream_t)stream,
+                        [&](hipStream_t st) -> hipError_t {
+                            hipError_t e = launch_tri_expand(T.q, ctx->d_err, n_sig, st);
+                            if (e != hipSuccess)
+                                return e;
+                            GridParams q = p;
+                            return launch_forward(ctx, &T.din, P, q, st);
+                        });
 }
 
 int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
@@ -713,10 +906,36 @@ int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     Plan P;
     P.a_cap = 0;
     GridParams p;
-    fill_params(p, ctx, desc, batch, P, const_cast<void *>(grad_out), nullptr);
-    p.grad_xyz = grad_xyz;
-    p.grad_w = grad_weights;
-    hipError_t e = launch_adjoint(p, desc->out_dtype, (hipStream_t)stream);
+    Tri T;
+    s = tri_setup(desc, batch, T);
+    if (s != PG_OK)
+        return s;
+    if (!T.on) {
+        fill_params(p, ctx, desc, batch, P, const_cast<void *>(grad_out), nullptr);
+        p.grad_xyz = grad_xyz;
+        p.grad_w = grad_weights;
+        hipError_t e = launch_adjoint(p, desc->out_dtype, (hipStream_t)stream);
+        return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
+    }
+    // triclinic: the images' gradients into the workspace, then their sum
+    // onto each atom
+    Plan Pf;
+    size_t total = 0;
+    s = plan_request(ctx, desc, batch, nullptr, Pf, T, total);
+    if (s != PG_OK)
+        return s;
+    if (ws_bytes < total || !ws)
+        return PG_E_WORKSPACE;
+    tri_bind(T, batch, ws);
+    fill_params(p, ctx, &T.din, &T.bin, P, const_cast<void *>(grad_out), nullptr);
+    p.grad_xyz = (float *)((unsigned char *)ws + T.off_grad);
+    T.q.grad = grad_xyz;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_tri_expand(T.q, ctx->d_err, p.n_sig, st);
+    if (e == hipSuccess)
+        e = launch_adjoint(p, desc->out_dtype, st);
+    if (e == hipSuccess)
+        e = launch_tri_reduce(T.q, st);
     return e == hipSuccess ? PG_OK : hip_fail(ctx, e);
 }
 

@@ -77,6 +77,24 @@ struct PeakParams {
     int32_t n_mol, C, D, H, W;
 };
 
+// Triclinic cells: expansion of every atom into K lattice images (a * K + k)
+// and the sum of the images' gradients back onto the atoms.
+struct TriParams {
+    const float *xyz;
+    const int32_t *types;
+    const int32_t *offsets;
+    float *exp_xyz;          // n_atoms * K x 3 image positions
+    int32_t *exp_types;      // n_atoms * K (-1: invalid atom)
+    int32_t *exp_offsets;    // n_mol + 1: offsets * K
+    const float *grad_img;   // n_atoms * K x 3 image gradients
+    float *grad;             // n_atoms x 3 (may be nullptr)
+    double M[9];             // cell, row-major: M[3 * alpha + j] = alpha component of vector j
+    double Minv[9];
+    int32_t klo[3], kdim[3]; // lattice range of the home-cell copy, per cell axis
+    int32_t K, n_mol;
+    long long n_atoms;
+};
+
 // Per-atom window table written by the prep kernel (plain form).
 struct AtomWindow {
     int32_t type;            // -1: skipped atom

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_abi_version_and_status_strings():
-    assert pg.abi_version() == 3
+    assert pg.abi_version() == 4
     lib = pg._lib()
     for s in range(0, 10):
         assert lib.pg_status_str(s)
@@ -202,6 +202,50 @@ def test_weighted_channels_validation_and_plans():
                            ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
     d = desc_ok(form="plain")
     assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000, ctypes.byref(info)) == 0
+
+
+SHEAR = [[8.0, 2.5, 1.0], [0.0, 7.5, -1.5], [0.0, 0.0, 8.5]]
+
+
+def test_triclinic_validation_and_plans():
+    """Triclinic cells: the cell check (image cubes apart, non-singular,
+    bounded image count), the unsupported combinations, and the plan of the
+    non-periodic request over the images (the workspace holds the images)."""
+    lib = pg._lib()
+    info = pg.PlanInfo()
+    n = ctypes.c_size_t()
+    sig = [0.3, 0.35, 0.4, 0.45, 0.5]
+    tri = lambda cell, **kw: desc_ok(sigma=sig, dims=(32, 32, 32), spacing=0.25,
+                                    origin=(0, 0, 0), cell=cell, **kw)
+    d = tri(SHEAR)
+    assert d.periodic == pg.PG_CELL_TRICLINIC
+    small = batch_ok(n_mol=2, n_atoms=6, max_atoms=3)
+    assert validate(d, small) == pg.PG_OK
+    assert validate(tri([[8, 0, 0], [0, 8, 0], [0, 0, 0]]), small) == pg.PG_E_PERIODIC   # singular
+    thin = [[8.0, 7.0, 0.0], [0.0, 1.5, 0.0], [0.0, 0.0, 8.0]]   # (-1, 1.5, 0) is a lattice vector
+    assert validate(tri(thin), small) == pg.PG_E_PERIODIC
+    assert validate(tri(SHEAR, cutoff_k=0.0), small) == pg.PG_E_PERIODIC
+    b = batch_ok(n_mol=2, n_atoms=6, max_atoms=3)
+    b.spacings = 0x2000
+    assert validate(d, b) == pg.PG_E_UNSUPPORTED
+    b = batch_ok(n_mol=2, n_atoms=6, max_atoms=3)
+    b.weights = 0x2000
+    assert validate(d, b) == pg.PG_E_UNSUPPORTED
+    # a grid far larger than the cell needs too many images
+    big_grid = desc_ok(sigma=sig, dims=(256, 256, 256), spacing=0.25, origin=(0, 0, 0),
+                       cell=SHEAR)
+    assert validate(big_grid, small) == pg.PG_E_PERIODIC
+    # plans: 3 atoms x 27 images fit the window form; 40 x 27 take the binned path
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(small), 0x10000, ctypes.byref(info)) == 0
+    assert info.form == pg.FORMS["window"] and info.binned == 0
+    assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(small), ctypes.byref(n)) == 0
+    assert n.value >= 6 * 27 * (12 + 4 + 12)
+    mid = batch_ok(n_mol=2, n_atoms=80, max_atoms=40)
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(mid), 0x10000, ctypes.byref(info)) == 0
+    assert info.binned == 1
+    # not with the autotuner's or the reversal step's plans
+    assert lib.pg_reversal_workspace_size(None, ctypes.byref(d), ctypes.byref(small),
+                                          ctypes.byref(n)) == pg.PG_E_UNSUPPORTED
 
 
 def test_reversal_workspace_host_only():
