@@ -156,7 +156,7 @@ def mfma_dense_flops(b, wl) -> int:
     return int(2 * 128 * 128 * tiles * k_pad.sum())
 
 
-def cpu_oracle_baseline(units, run_one, seconds, describe):
+def cpu_oracle_baseline(units, run_one, seconds, describe, max_threads=None):
     """Time the FP64 oracle on a bounded sample: run_one(unit) computes the
     grids of one unit (a chunk of structures, as one oracle call) and returns
     how many; units are taken cycling through the list, first on one thread,
@@ -172,7 +172,7 @@ def cpu_oracle_baseline(units, run_one, seconds, describe):
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
-    P = max(1, min(CPU_THREADS_MAX, avail))
+    P = max(1, min(max_threads or CPU_THREADS_MAX, avail))
     nP = i = 0
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(P) as ex:
@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--workload", default="mol4096", choices=sorted(METRICS))
     ap.add_argument("--value", default="point", choices=("point", "box"),
                     help="voxel value: the Gaussian at the centre, or its mass in the voxel")
+    ap.add_argument("--triclinic", action="store_true",
+                    help="crystal8 in a sheared (triclinic) cell of the same edge length")
     ap.add_argument("--embed", type=int, default=0,
                     help="weighted channels: a dense seeded embedding of the element types "
                          "into this many channels (molecule forward workloads)")
@@ -228,6 +230,15 @@ def main():
     log(f"[bench] generating {wl.name}: {wl.n_mol} structures")
     b = wl.batch()
     sig = wl.sigma()
+    cell = wl.cell
+    if args.triclinic:
+        if wl.kind != "crystal":
+            print("bench.py: --triclinic applies to the crystal workload", file=sys.stderr)
+            sys.exit(2)
+        # the same fractional positions in a sheared cell: column j of the
+        # matrix is lattice vector j
+        cell = wl.cell * np.array([[1.0, 0.15, 0.1], [0.0, 1.0, -0.15], [0.0, 0.0, 1.0]])
+        b.xyz = ((b.xyz.astype(np.float64) / wl.cell) @ cell.T).astype(np.float32)
     xyz = torch.tensor(b.xyz, device=dev)
     types = torch.tensor(b.types, device=dev)
     offs = torch.tensor(b.offsets, device=dev)
@@ -257,16 +268,17 @@ def main():
     extra = {}
     value = args.value
     metric = METRICS[wl.name] + (" [box form]" if value == "box" else "") + \
-        (f" [embedding {wl.n_types} types -> {C} channels]" if E is not None else "")
+        (f" [embedding {wl.n_types} types -> {C} channels]" if E is not None else "") + \
+        (" [triclinic cells]" if args.triclinic else "")
     rec = {"metric": metric, "unit": "grids/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
 
     def forward_case(out_dt, form, autotune, steps, warmup):
-        desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, wl.cell,
+        desc = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k, cell,
                             out_dt, form, value, ntypes)
         out = pg.empty_grid(desc, B, dev)
-        if autotune and not args.no_autotune:
+        if autotune and not args.no_autotune and not args.triclinic:
             log(f"[bench] autotuning {form} {out_dt}")
             ctx.autotune(desc, bv, out, reps=3)
         plan = ctx.plan(desc, bv, out)
@@ -388,7 +400,7 @@ def main():
             if not args.no_baseline:
                 ctx_p = pg.Context(0)
                 descp = pg.make_desc(C, wl.dims, wl.spacing, wl.origin, sig, wl.cutoff_k,
-                                     wl.cell, torch.float32, "plain", value, ntypes)
+                                     cell, torch.float32, "plain", value, ntypes)
                 outp = pg.empty_grid(descp, B, dev)
                 wp, ep = timed_steps(lambda: ctx_p.forward(descp, bv, outp, stream), 3, 1, torch,
                                      stream)
@@ -419,7 +431,8 @@ def main():
         kind = "forward"
 
     if wl.kind == "crystal":
-        desc_w = (f"{wl.name}: {B} periodic {wl.cell:g} A cubic cells of "
+        shape = "triclinic (sheared) cells of edge" if args.triclinic else "cubic cells of"
+        desc_w = (f"{wl.name}: {B} periodic {shape} {wl.cell:g} A, "
                   f"{min(b.counts())}-{max(b.counts())} atoms (uniform positions, {C} types uniform)")
     else:
         desc_w = (f"{wl.name}: {B} molecules of {wl.atoms[0]}-{wl.atoms[1]} atoms "
@@ -464,6 +477,12 @@ def main():
         else:
             def run_one(u):
                 s = u[1]
+                if args.triclinic:
+                    from oracle import triclinic as cpu_triclinic
+                    cpu_triclinic.grid_triclinic_fp64(s.xyz, s.types, s.offsets, sig, wl.dims,
+                                                      wl.spacing, cell, wl.origin,
+                                                      cutoff_k=wl.cutoff_k, value=value)
+                    return s.n_mol
                 cpu_oracle.grid_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
                                      wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell, value=value,
                                      weights=None if E is None else table[s.types])
@@ -475,7 +494,9 @@ def main():
             cpu_units, run_one, args.cpu_seconds,
             lambda n, dt, P: (f"{n} {kind} grids of the {B}-structure batch, {chunk} {per_unit}"
                               f"(s) per oracle call cycling through the batch ({n / B:.2f} "
-                              f"passes), dense FP64 {C}x{D}x{H}x{W}, {P} thread(s), {dt:.1f} s"))
+                              f"passes), dense FP64 {C}x{D}x{H}x{W}, {P} thread(s), {dt:.1f} s"),
+            # the triclinic oracle expands images in Python (the GIL): no pool
+            max_threads=1 if args.triclinic else None)
     rec["cpu_baseline"] = cpu
 
     if args.calibrate_copy:

@@ -54,6 +54,14 @@ __global__ void cr_clear_kernel(uint32_t *a, long long n)
 // structure per block instead of one per atom).
 constexpr int PREP_SPAN = 4;
 
+// The channel an atom is listed under, or -1: skipped atoms, and atoms
+// whose window misses the grid on some axis (they add nothing -- e.g. the
+// lattice images of a triclinic cell that do not reach the grid).
+__device__ __forceinline__ int listed_type(const AtomWindow &w)
+{
+    return (w.type >= 0 && w.n[0] > 0 && w.n[1] > 0 && w.n[2] > 0) ? w.type : -1;
+}
+
 __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, CrystalParams q)
 {
     __shared__ uint32_t cnt[PG_MAX_CHANNELS];
@@ -75,7 +83,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, Cryst
     if (a < p.n_atoms) {
         AtomWindow *w = q.table + a;
         const int m = write_atom_window(p, a, w);
-        const int t = w->type;
+        const int t = listed_type(*w);
         if (t >= 0) {
             atomicAdd(&cnt[t], 1u);
             if (local)
@@ -137,7 +145,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_place_kernel(GridParams p, Crys
     __shared__ uint32_t wc[PREP_BLOCK / 64][PG_MAX_CHANNELS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long a = (long long)blockIdx.x * PREP_BLOCK + tid;
-    const int t = a < p.n_atoms ? q.table[a].type : -1;
+    const int t = a < p.n_atoms ? listed_type(q.table[a]) : -1;
     const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t rank = 0;
     for (int c = 0; c < p.C; ++c) {
