@@ -15,6 +15,11 @@ Functions:
               descent step on the squared grid error (reversal.py)
   triclinic   triclinic periodic cells: lattice images passed to the
               non-periodic map (triclinic.py)
+  sphere      the voxels near a sphere-cutoff edge, which comparisons accept
+              on either side (sphere.py)
+
+cutoff_shape="sphere" keeps, inside each atom's cube, only the voxels with
+|r - mu|^2 <= rc_t^2 (squares summed in double).
 
 What is computed is the point-sampled, un-normalised Gaussian of §III-A
 Eq. 1 at voxel centres (value="point"), or the integral of the normalised
@@ -56,17 +61,19 @@ def _load():
         from .build import build
         build()
     lib = ctypes.CDLL(_LIB_PATH)
-    lib.pgo_grid.argtypes = _COMMON + [ctypes.c_int, _dp, ctypes.c_int, _dp, _i64p, _i64p]
+    lib.pgo_grid.argtypes = _COMMON + [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _i64p,
+                                       _i64p]
     lib.pgo_grid.restype = ctypes.c_int
-    lib.pgo_grad.argtypes = _COMMON + [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp]
+    lib.pgo_grad.argtypes = _COMMON + [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp,
+                                       _dp]
     lib.pgo_grad.restype = ctypes.c_int
-    lib.pgo_voxels.argtypes = _COMMON + [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int64, _i64p,
-                                         _dp]
+    lib.pgo_voxels.argtypes = _COMMON + [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                         ctypes.c_int64, _i64p, _dp]
     lib.pgo_voxels.restype = ctypes.c_int
     lib.pgo_count_evals.argtypes = _COMMON
     lib.pgo_count_evals.restype = ctypes.c_int64
     lib.pgo_version.restype = ctypes.c_int
-    if lib.pgo_version() != 3:
+    if lib.pgo_version() != 4:
         raise ImportError(f"{_LIB_PATH} is stale: rebuild it with oracle/build.py")
     _lib = lib
     return lib
@@ -78,6 +85,7 @@ def _f32(v) -> np.ndarray:
 
 
 VALUES = {"point": 0, "box": 1}
+SHAPES = {"cube": 0, "sphere": 1}
 
 
 def _ptr(a: Optional[np.ndarray], t):
@@ -146,7 +154,7 @@ class _Args:
 
 def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3.0,
               cell=None, origins=None, spacings=None, n_types=None, return_stats=False,
-              value="point", weights=None):
+              value="point", weights=None, cutoff_shape="cube"):
     """Dense FP64 grids, shape (B, C, D, H, W), x fastest.  With weights
     (n_atoms, C), atom a adds weights[a, c] times its Gaussian (width
     sigma[types[a]]) to every channel c."""
@@ -155,8 +163,8 @@ def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3
     out = np.empty(a.shape, dtype=np.float64)
     ev = ctypes.c_int64(0)
     sk = ctypes.c_int64(0)
-    rc = _load().pgo_grid(*a.common(), VALUES[value], *a.weighting(), _ptr(out, _dp),
-                          ctypes.byref(ev), ctypes.byref(sk))
+    rc = _load().pgo_grid(*a.common(), VALUES[value], SHAPES[cutoff_shape], *a.weighting(),
+                          _ptr(out, _dp), ctypes.byref(ev), ctypes.byref(sk))
     if rc != 0:
         raise MemoryError("pgo_grid failed")
     if return_stats:
@@ -166,7 +174,7 @@ def grid_fp64(xyz, types, offsets, sigma, dims, spacing, origin=None, cutoff_k=3
 
 def grad_fp64(xyz, types, offsets, sigma, dims, spacing, U, origin=None, cutoff_k=3.0,
               cell=None, origins=None, spacings=None, n_types=None, value="point",
-              weights=None, return_weight_grad=False):
+              weights=None, return_weight_grad=False, cutoff_shape="cube"):
     """dL/dxyz for L = sum(U * G), shape (n_atoms, 3) float64; with weights
     and return_weight_grad, also dL/dweights (n_atoms, C)."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
@@ -174,8 +182,8 @@ def grad_fp64(xyz, types, offsets, sigma, dims, spacing, U, origin=None, cutoff_
     u = np.ascontiguousarray(np.asarray(U, dtype=np.float64).reshape(a.shape))
     g = np.empty((a.xyz.shape[0], 3), dtype=np.float64)
     gw = np.empty((a.xyz.shape[0], a.C), dtype=np.float64) if weights is not None else None
-    rc = _load().pgo_grad(*a.common(), VALUES[value], *a.weighting(), _ptr(u, _dp),
-                          _ptr(g, _dp), _ptr(gw, _dp))
+    rc = _load().pgo_grad(*a.common(), VALUES[value], SHAPES[cutoff_shape], *a.weighting(),
+                          _ptr(u, _dp), _ptr(g, _dp), _ptr(gw, _dp))
     if rc != 0:
         raise MemoryError("pgo_grad failed")
     return (g, gw) if return_weight_grad else g
@@ -183,13 +191,13 @@ def grad_fp64(xyz, types, offsets, sigma, dims, spacing, U, origin=None, cutoff_
 
 def voxels_fp64(xyz, types, offsets, sigma, dims, spacing, idx, origin=None, cutoff_k=3.0,
                 cell=None, origins=None, spacings=None, n_types=None, value="point",
-                weights=None):
+                weights=None, cutoff_shape="cube"):
     """Grid values at sampled voxels; idx is (S, 5) rows of (b, c, z, y, x)."""
     a = _Args(xyz, types, offsets, sigma, dims, spacing, origin, cutoff_k, cell,
               origins, spacings, n_types, weights)
     q = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 5))
     v = np.empty(q.shape[0], dtype=np.float64)
-    rc = _load().pgo_voxels(*a.common(), VALUES[value], *a.weighting(),
+    rc = _load().pgo_voxels(*a.common(), VALUES[value], SHAPES[cutoff_shape], *a.weighting(),
                             ctypes.c_int64(q.shape[0]), _ptr(q, _i64p), _ptr(v, _dp))
     if rc != 0:
         raise ValueError("sample index out of range")

@@ -48,6 +48,12 @@
  *   of the separable coordinate gradient of §IV-C), cutoff-edge jumps
  *   excluded (derivative almost everywhere).
  *
+ *   Sphere cutoff (sphere = 1, with a cutoff): a voxel inside an atom's
+ *   cube is kept only if also |r - mu|^2 <= rc_t^2, the squared offsets
+ *   (nearest image per axis when periodic) summed in double.  This decision
+ *   is not made exactly: voxels within a relative 1e-6 of the sphere are
+ *   left to the tests to treat as either side.
+ *
  *   Weighted channels (weights != NULL; the learned-embedding grids the
  *   Discussion proposes, and the weighted grids mentioned after Eq. 6): atom
  *   a adds weights[a][c] times its Gaussian to every channel c, the
@@ -235,7 +241,7 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
              const double *origin3, const double *spacing3,
              const double *origins, const double *spacings,
              const float *sigma, float cutoff_k,
-             int periodic, const double *cell3, int value,
+             int periodic, const double *cell3, int value, int sphere,
              const double *weights, int n_sig,
              double *out, int64_t *evals, int64_t *skipped)
 {
@@ -265,6 +271,8 @@ int pgo_grid(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
                 for (int ky = 0; ky < w.n[1]; ++ky)
                     for (int kx = 0; kx < w.n[0]; ++kx) {
                         double dx = w.del[0][kx], dy = w.del[1][ky], dz = w.del[2][kz];
+                        if (sphere && g.cut && dx * dx + dy * dy + dz * dz > g.rc * g.rc)
+                            continue;
                         double v;
                         if (value == 1)
                             v = box1d(dx - 0.5 * g.h[0], dx + 0.5 * g.h[0], sigma[t]) *
@@ -303,7 +311,7 @@ int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
              const double *origin3, const double *spacing3,
              const double *origins, const double *spacings,
              const float *sigma, float cutoff_k,
-             int periodic, const double *cell3, int value,
+             int periodic, const double *cell3, int value, int sphere,
              const double *weights, int n_sig,
              const double *U, double *grad, double *grad_w)
 {
@@ -336,6 +344,8 @@ int pgo_grad(int B, const int64_t *offsets, const double *xyz, const int32_t *ty
                 for (int ky = 0; ky < w.n[1]; ++ky)
                     for (int kx = 0; kx < w.n[0]; ++kx) {
                         double dx = w.del[0][kx], dy = w.del[1][ky], dz = w.del[2][kz];
+                        if (sphere && g.cut && dx * dx + dy * dy + dz * dz > g.rc * g.rc)
+                            continue;
                         const size_t vox = (size_t)w.idx[2][kz] * plane +
                                            (size_t)w.idx[1][ky] * W + w.idx[0][kx];
                         double uv;
@@ -397,7 +407,7 @@ int pgo_voxels(int B, const int64_t *offsets, const double *xyz, const int32_t *
                const double *origin3, const double *spacing3,
                const double *origins, const double *spacings,
                const float *sigma, float cutoff_k,
-               int periodic, const double *cell3, int value,
+               int periodic, const double *cell3, int value, int sphere,
                const double *weights, int n_sig,
                int64_t n_samples, const int64_t *idx, double *val)
 {
@@ -433,6 +443,9 @@ int pgo_voxels(int B, const int64_t *offsets, const double *xyz, const int32_t *
             for (int ax = 0; ax < 3 && inside; ++ax)
                 inside = axis_offset(g.o[ax], g.h[ax], vi[ax], mu[ax], g.periodic,
                                      g.L[ax], g.cut, g.rc, &d[ax]);
+            if (inside && sphere && g.cut &&
+                d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > g.rc * g.rc)
+                inside = 0;
             if (inside) {
                 double v;
                 if (value == 1)
@@ -479,4 +492,4 @@ int64_t pgo_count_evals(int B, const int64_t *offsets, const double *xyz, const 
     return ev;
 }
 
-int pgo_version(void) { return 3; }
+int pgo_version(void) { return 4; }
