@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define PG_ABI_VERSION 4
+#define PG_ABI_VERSION 5
 #define PG_MAX_CHANNELS 64
 
 typedef enum pg_status {
@@ -116,7 +116,18 @@ typedef struct pg_grid_desc {
                                     (1..64); 0 means C.  Without weights: 0 or C */
     float cell_matrix[9];        /* triclinic cell, row-major: cell_matrix[3 * alpha + j] is
                                     the alpha (x, y, z) component of lattice vector j */
+    int32_t cutoff_shape;        /* PG_CUTOFF_CUBE (default) or PG_CUTOFF_SPHERE */
 } pg_grid_desc;
+
+/* Cutoff shape.  PG_CUTOFF_CUBE: |r_alpha - mu_alpha| <= rc_t on every axis,
+   decided exactly (separable: every form supports it).  PG_CUTOFF_SPHERE:
+   inside the cube, also |r - mu|^2 <= rc_t^2 (nearest image per axis when
+   periodic), the squared per-axis offsets summed in float32 -- not exact:
+   a voxel within about 1e-6 rc_t^2 of the sphere may fall on either side.
+   The sphere breaks separability, so it takes the molecule window form or
+   the plain form (AUTO picks plain when the window form does not fit); the
+   binned forms return PG_E_UNSUPPORTED. */
+enum { PG_CUTOFF_CUBE = 0, PG_CUTOFF_SPHERE = 1 };
 
 /* Periodic cells (§III-A: a structure's density sums the lattice
    translations of each atom).

@@ -38,6 +38,7 @@ FORMS = {"auto": 0, "plain": 1, "window": 2, "mfma": 3}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
 VALUES = {"point": 0, "box": 1}
 PG_CELL_NONE, PG_CELL_ORTHO, PG_CELL_TRICLINIC = 0, 1, 2
+SHAPES = {"cube": 0, "sphere": 1}
 PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL = 1, 2, 3, 4, 5
 MAX_CHANNELS = 64
 
@@ -57,7 +58,7 @@ class GridDesc(ctypes.Structure):
                 ("cell", ctypes.c_float * 3), ("out_dtype", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("sigma", ctypes.c_float * MAX_CHANNELS),
                 ("value", ctypes.c_int32), ("n_types", ctypes.c_int32),
-                ("cell_matrix", ctypes.c_float * 9)]
+                ("cell_matrix", ctypes.c_float * 9), ("cutoff_shape", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
@@ -143,14 +144,15 @@ def _f3(v) -> Tuple[float, float, float]:
 def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigma=(),
               cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32,
               form: Union[str, int] = "auto", value: Union[str, int] = "point",
-              n_types: int = 0) -> GridDesc:
+              n_types: int = 0, cutoff_shape: Union[str, int] = "cube") -> GridDesc:
     """Build a pg_grid_desc (host struct).  dims = (D, H, W) = (z, y, x);
     origin / spacing in x, y, z order; cell: None, a scalar or 3 edges
     (orthorhombic), or a 3 x 3 matrix whose column j is lattice vector j
     (triclinic); sigma one width per type
     (= per channel unless weighted); value "point" (the Gaussian at voxel
     centres) or "box" (the normalised Gaussian's mass in each voxel);
-    n_types: with weighted channels, how many widths the types index."""
+    n_types: with weighted channels, how many widths the types index;
+    cutoff_shape "cube" (exact, separable) or "sphere"."""
     d = GridDesc()
     d.C = int(C)
     d.D, d.H, d.W = (int(x) for x in dims)
@@ -175,6 +177,7 @@ def make_desc(C: int, dims: Sequence[int], spacing, origin=(0.0, 0.0, 0.0), sigm
     d.form = FORMS[form] if isinstance(form, str) else int(form)
     d.value = VALUES[value] if isinstance(value, str) else int(value)
     d.n_types = int(n_types)
+    d.cutoff_shape = SHAPES[cutoff_shape] if isinstance(cutoff_shape, str) else int(cutoff_shape)
     sig = [float(s) for s in sigma]
     if len(sig) > MAX_CHANNELS:
         raise ValueError(f"at most {MAX_CHANNELS} channels")
@@ -440,8 +443,8 @@ def grid(xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor, sigma: S
          dims: Sequence[int], spacing=0.5, origin=(0.0, 0.0, 0.0), origins=None, spacings=None,
          cutoff_k: float = 3.0, cell=None, out_dtype=torch.float32, form: str = "auto",
          value: str = "point", weights: Optional[torch.Tensor] = None,
-         n_channels: Optional[int] = None, max_atoms: Optional[int] = None,
-         ctx: Optional[Context] = None) -> torch.Tensor:
+         cutoff_shape: str = "cube", n_channels: Optional[int] = None,
+         max_atoms: Optional[int] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """Density grids (B, C, D, H, W) for a ragged batch (differentiable in
     xyz, and in weights when given).
 
@@ -459,7 +462,7 @@ def grid(xyz: torch.Tensor, types: torch.Tensor, offsets: torch.Tensor, sigma: S
         C = int(n_channels if n_channels is not None else len(sigma))
         n_types = 0
     desc = make_desc(C, dims, spacing, origin, sigma, cutoff_k, cell, out_dtype, form, value,
-                     n_types)
+                     n_types, cutoff_shape)
     pgctx = ctx if ctx is not None else default_context(xyz.device)
     return GridFn.apply(xyz, types, offsets, origins, spacings, weights, desc, max_atoms, pgctx)
 

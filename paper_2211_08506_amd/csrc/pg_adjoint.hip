@@ -41,11 +41,12 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     const long long a = (long long)blockIdx.x * waves + wave;
     const bool active = a < p.n_atoms;
     const int NT = p.W + p.H + p.D;
-    // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | 3 range records
-    int *idx = (int *)(smem + (size_t)wave * (NT * 12 + 3 * sizeof(AxisRanges)));
+    // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | dsq[NT] | 3 range records
+    int *idx = (int *)(smem + (size_t)wave * (NT * 16 + 3 * sizeof(AxisRanges)));
     float *phi = (float *)(idx + NT);
     float *dphi = phi + NT;
-    AxisRanges *rg = (AxisRanges *)(dphi + NT);
+    float *dsq = dphi + NT;      // sphere cutoff: squared centre offsets
+    AxisRanges *rg = (AxisRanges *)(dsq + NT);
     const int base[3] = {0, p.W, p.W + p.H};
     const int N[3] = {p.W, p.H, p.D};   // indexed by the compile-time axis only
 
@@ -93,6 +94,10 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                                                      p.inv2s2[t], p.isq2s[t]);
                     dphi[base[q] + k0 + k] = dfactor1d(p.box != 0, R.bh[r], R.bl[r], h[q], i,
                                                        p.inv2s2[t], p.invs2[t], p.inorm[t]);
+                    if (p.sphere) {
+                        const float d = offset_at(R.bh[r], R.bl[r], h[q], i);
+                        dsq[base[q] + k0 + k] = d * d;
+                    }
                 }
                 k0 += len;
             }
@@ -122,6 +127,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                 const int ky = r % ny;
                 const int kz = r / ny;
                 const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
+                if (p.sphere && !(dsq[kx] <= (p.rc2[t] - dsq[base[2] + kz]) - dsq[base[1] + ky]))
+                    continue;
                 const float u = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
                 const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
                 const float dx = dphi[kx], dy = dphi[base[1] + ky], dz = dphi[base[2] + kz];
@@ -173,7 +180,7 @@ hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s)
     if (p.n_atoms == 0)
         return hipSuccess;
     const int block = 256, waves = block / 64;
-    const size_t lds = (size_t)waves * ((size_t)(p.W + p.H + p.D) * 12 + 3 * sizeof(AxisRanges));
+    const size_t lds = (size_t)waves * ((size_t)(p.W + p.H + p.D) * 16 + 3 * sizeof(AxisRanges));
     const long long grid = (p.n_atoms + waves - 1) / waves;
     if (grad_dtype == PG_OUT_F32) {
         if (lds > 65536)

@@ -134,6 +134,8 @@ int validate(const pg_grid_desc *d, const pg_batch *b)
         return PG_E_PARAM;
     if (d->value != PG_VALUE_POINT && d->value != PG_VALUE_BOX)
         return PG_E_PARAM;
+    if (d->cutoff_shape != PG_CUTOFF_CUBE && d->cutoff_shape != PG_CUTOFF_SPHERE)
+        return PG_E_PARAM;
     for (int q = 0; q < 3; ++q) {
         if (!finite_pos(d->spacing[q]) || !std::isfinite(d->origin[q]))
             return PG_E_PARAM;
@@ -399,6 +401,8 @@ std::string tuning_key(const pg_grid_desc *d, const pg_batch *b, int vec)
                   d->W, d->out_dtype == PG_OUT_BF16 ? "bf16" : "f32", d->periodic, vec, nb, ma,
                   d->value == PG_VALUE_BOX ? (b->weights ? "_box_w" : "_box")
                                            : (b->weights ? "_w" : ""));
+    if (d->cutoff_shape == PG_CUTOFF_SPHERE)
+        std::strncat(buf, "_sph", sizeof buf - std::strlen(buf) - 1);
     return buf;
 }
 
@@ -435,7 +439,7 @@ bool window_fits(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, Pl
     P.row_stride = (W4 + d->H + d->D + 3) & ~3;
     P.mask_words = (P.a_cap + 63) / 64;
     P.lds = window_lds(P.a_cap, P.row_stride, d->C, d->D, P.mask_words,
-                       b->weights ? d->C : 0).total;
+                       b->weights ? d->C : 0, d->cutoff_shape == PG_CUTOFF_SPHERE).total;
     P.ws = 0;
     const int max_lds = ctx ? ctx->max_lds : 65536;
     return P.lds <= (size_t)max_lds;
@@ -467,6 +471,12 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
             }
         }
     }
+    // the sphere is not separable: molecule window form or plain form
+    const bool sphere = d->cutoff_shape == PG_CUTOFF_SPHERE && d->cutoff_k != 0.f;
+    if (sphere && d->form == PG_FORM_AUTO && !fits)
+        form = PG_FORM_PLAIN;
+    if (sphere && (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)))
+        return PG_E_UNSUPPORTED;
     P.form = form;
     // weighted channels: the molecule window form and the plain form only
     if (weighted(b) && (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)))
@@ -502,6 +512,8 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
         if (ctx->opt_nt >= 0)
             P.nt = ctx->opt_nt;
     }
+    if (sphere)
+        P.unroll = 1;   // the sphere variant of the window kernel runs one run per lane
     const int n_cu = ctx ? ctx->n_cu : 256;
     P.grid = window_grid(b, P, n_cu);
     return PG_OK;
@@ -569,6 +581,9 @@ void fill_params(GridParams &p, const pg_ctx *ctx, const pg_grid_desc *d, const 
     }
     p.box = d->value == PG_VALUE_BOX;
     p.weights = weighted(b) ? b->weights : nullptr;
+    p.sphere = d->cutoff_shape == PG_CUTOFF_SPHERE && d->cutoff_k != 0.f;
+    for (int t = 0; t < p.n_sig; ++t)
+        p.rc2[t] = p.rc[t] * p.rc[t];
 }
 
 hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, GridParams &p,

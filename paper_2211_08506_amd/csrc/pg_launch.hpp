@@ -11,11 +11,13 @@ namespace pg {
 
 // Byte offsets of the window kernel's dynamic LDS regions.
 struct WindowLds {
-    size_t rows, ranges, masks, types, wts, total;
+    size_t rows, ranges, masks, types, wts, dsq, total;
 };
 
-// weight_ch: channels of per-atom weights held in LDS (0: unweighted)
-WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int weight_ch);
+// weight_ch: channels of per-atom weights held in LDS (0: unweighted);
+// sphere: squared-offset rows beside the factor rows
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int weight_ch,
+                     bool sphere);
 
 // Persistent molecule window kernel (pg_window.hip); unroll: runs per lane
 // per pass (1, 2 or 4).

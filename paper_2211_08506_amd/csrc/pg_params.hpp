@@ -59,6 +59,10 @@ struct GridParams {
     const float *weights;
     float *grad_w;
     int32_t n_sig;
+    // sphere cutoff: keep a voxel only if the summed squared offsets are at
+    // most rc2 = fl32(rc * rc) of the atom's type
+    int32_t sphere;
+    float rc2[PG_MAX_CHANNELS];
 };
 
 // Peak search of grid reversal: local maxima of every channel of a batch of

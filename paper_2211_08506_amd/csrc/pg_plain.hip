@@ -7,7 +7,9 @@
 //        windows and adds the 3-D Gaussian exp(-|r - mu|^2 / (2 sigma^2))
 //        (§III-A Eq. 1, point-sampled, without the prefactor), or for the box
 //        form the product of the three per-axis voxel masses (with weighted
-//        channels: every atom, times its weight for the channel).  This is the
+//        channels: every atom, times its weight for the channel; with the
+//        sphere cutoff, only voxels whose summed squared offsets are within
+//        rc^2).  This is the
 //        straightforward GPU transcription of the definition; the batched
 //        window kernel is measured against it.
 #include "pg_device.hpp"
@@ -69,10 +71,10 @@ __global__ void __launch_bounds__(256) plain_kernel(GridParams p)
             for (int r = 0; r < tab[a].n[q]; ++r) {
                 if (idx[q] >= tab[a].lo[q][r] && idx[q] <= tab[a].hi[q][r]) {
                     const float bh = tab[a].bh[q][r], bl = tab[a].bl[q][r];
-                    if (box) {
+                    if (box)
                         mass *= box1d(edge_at(bh, bl, h[q], idx[q]), edge_at(bh, bl, h[q], idx[q] + 1),
                                       isq2s);
-                    } else {
+                    if (!box || p.sphere) {
                         const float d = offset_at(bh, bl, h[q], idx[q]);
                         d2 = __builtin_fmaf(d, d, d2);
                     }
@@ -81,6 +83,8 @@ __global__ void __launch_bounds__(256) plain_kernel(GridParams p)
             }
             inside = hit;
         }
+        if (inside && p.sphere && !(d2 <= p.rc2[t]))
+            inside = false;
         if (inside) {
             const float v = box ? mass : expf(-d2 * inv2s2);
             acc += wts ? wgt * v : v;

@@ -37,7 +37,7 @@ struct RangeRec {
 };
 
 __host__ __device__ inline WindowLds window_lds_layout(int a_cap, int row_stride, int C, int D,
-                                                      int mask_words, int weight_ch)
+                                                      int mask_words, int weight_ch, bool sphere)
 {
     WindowLds L;
     size_t off = 0;
@@ -53,13 +53,18 @@ __host__ __device__ inline WindowLds window_lds_layout(int a_cap, int row_stride
     off += (size_t)a_cap * sizeof(int32_t);
     L.wts = off;
     off += (size_t)a_cap * weight_ch * sizeof(float);
+    off = (off + 15) & ~(size_t)15;
+    L.dsq = off;
+    if (sphere)
+        off += (size_t)a_cap * row_stride * sizeof(float);
     L.total = (off + 15) & ~(size_t)15;
     return L;
 }
 
-WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int weight_ch)
+WindowLds window_lds(int a_cap, int row_stride, int C, int D, int mask_words, int weight_ch,
+                     bool sphere)
 {
-    return window_lds_layout(a_cap, row_stride, C, D, mask_words, weight_ch);
+    return window_lds_layout(a_cap, row_stride, C, D, mask_words, weight_ch, sphere);
 }
 
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v)
@@ -87,7 +92,7 @@ __device__ __forceinline__ void load_row(const float *r, float (&v)[VEC])
     }
 }
 
-template <typename T, int VEC, int U, bool RES>
+template <typename T, int VEC, int U, bool RES, bool SPH>
 __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -96,12 +101,13 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     const int W4 = (W + 3) & ~3;
     const int MW = p.mask_words;
     const int WC = p.weights ? C : 0;
-    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW, WC);
+    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW, WC, SPH);
     float *rows = (float *)(smem + lay.rows);
     RangeRec *rr = (RangeRec *)(smem + lay.ranges);
     unsigned long long *masks = (unsigned long long *)(smem + lay.masks);
     int32_t *atype = (int32_t *)(smem + lay.types);
     float *wl = (float *)(smem + lay.wts);
+    float *dsq = (float *)(smem + lay.dsq);   // sphere: squared centre offsets
 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
@@ -183,7 +189,7 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                 ax = 2; i = j - W4 - H; N = D;
             }
             const int t = atype[a];
-            float v = 0.f;
+            float v = 0.f, d2 = __builtin_huge_valf();
             if (t >= 0 && i < N) {
                 const RangeRec &R = rr[3 * a + ax];
                 const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
@@ -191,6 +197,10 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                     if (i >= R.lo[r] && i <= R.hi[r]) {
                         v = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[t],
                                      p.isq2s[t]);
+                        if constexpr (SPH) {
+                            const float d = offset_at(R.bh[r], R.bl[r], hq, i);
+                            d2 = d * d;
+                        }
                         if (ax == 2) {
                             if (WC == 0) {
                                 atomicOr(&masks[(size_t)(t * D + i) * MW + (a >> 6)],
@@ -206,6 +216,8 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                 }
             }
             rows[e] = v;
+            if constexpr (SPH)
+                dsq[e] = d2;
         }
         __syncthreads();
 
@@ -250,11 +262,23 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                         float gz = row[W4 + H + z];
                         if (WC)
                             gz *= wl[a * WC + pc];
+                        float r2z = 0.f;
+                        if constexpr (SPH)
+                            r2z = p.rc2[atype[a]] - dsq[a * RS + W4 + H + z];
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const float gy = row[W4 + yq[u]] * gz;
                             float fx[VEC];
                             load_row<VEC>(row + xq[u], fx);
+                            if constexpr (SPH) {
+                                // keep x only inside the ball: dx^2 <= rc^2 - dz^2 - dy^2
+                                const float r2 = r2z - dsq[a * RS + W4 + yq[u]];
+                                float dx2[VEC];
+                                load_row<VEC>(dsq + a * RS + xq[u], dx2);
+#pragma unroll
+                                for (int k = 0; k < VEC; ++k)
+                                    fx[k] = dx2[k] <= r2 ? fx[k] : 0.f;
+                            }
 #pragma unroll
                             for (int k = 0; k < VEC; ++k)
                                 acc[u][k] = __builtin_fmaf(gy, fx[k], acc[u][k]);
@@ -299,10 +323,10 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     }
 }
 
-template <typename T, int VEC, int U, bool RES>
+template <typename T, int VEC, int U, bool RES, bool SPH = false>
 static const void *window_fn()
 {
-    return (const void *)window_mol_kernel<T, VEC, U, RES>;
+    return (const void *)window_mol_kernel<T, VEC, U, RES, SPH>;
 }
 
 template <typename T, int VEC, bool RES = false>
@@ -316,8 +340,33 @@ static const void *window_fn_u(int unroll)
     return nullptr;
 }
 
-static const void *window_kernel_fn(int out_dtype, int vec, int unroll, bool residual)
+// sphere cutoff: one run per lane only (unroll 1)
+template <bool RES>
+static const void *window_fn_sphere(int out_dtype, int vec)
 {
+    if (out_dtype == PG_OUT_F32) {
+        switch (vec) {
+        case 4: return window_fn<float, 4, 1, RES, true>();
+        case 2: return window_fn<float, 2, 1, RES, true>();
+        case 1: return window_fn<float, 1, 1, RES, true>();
+        }
+    } else if (!RES) {
+        switch (vec) {
+        case 8: return window_fn<__bf16, 8, 1, false, true>();
+        case 4: return window_fn<__bf16, 4, 1, false, true>();
+        case 2: return window_fn<__bf16, 2, 1, false, true>();
+        case 1: return window_fn<__bf16, 1, 1, false, true>();
+        }
+    }
+    return nullptr;
+}
+
+static const void *window_kernel_fn(int out_dtype, int vec, int unroll, bool residual, bool sphere)
+{
+    if (sphere)
+        return unroll == 1 ? (residual ? window_fn_sphere<true>(out_dtype, vec)
+                                       : window_fn_sphere<false>(out_dtype, vec))
+                           : nullptr;
     if (residual) {
         if (out_dtype != PG_OUT_F32)
             return nullptr;
@@ -348,7 +397,7 @@ static const void *window_kernel_fn(int out_dtype, int vec, int unroll, bool res
 hipError_t launch_window(const GridParams &p, int out_dtype, int vec, int unroll, int block,
                          int grid, size_t lds, hipStream_t s)
 {
-    const void *k = window_kernel_fn(out_dtype, vec, unroll, p.target != nullptr);
+    const void *k = window_kernel_fn(out_dtype, vec, unroll, p.target != nullptr, p.sphere != 0);
     if (!k)
         return hipErrorInvalidValue;
     if (p.n_mol == 0)

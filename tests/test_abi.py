@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_abi_version_and_status_strings():
-    assert pg.abi_version() == 4
+    assert pg.abi_version() == 5
     lib = pg._lib()
     for s in range(0, 10):
         assert lib.pg_status_str(s)
@@ -246,6 +246,35 @@ def test_triclinic_validation_and_plans():
     # not with the autotuner's or the reversal step's plans
     assert lib.pg_reversal_workspace_size(None, ctypes.byref(d), ctypes.byref(small),
                                           ctypes.byref(n)) == pg.PG_E_UNSUPPORTED
+
+
+def test_sphere_cutoff_validation_and_plans():
+    """The sphere cutoff: a valid shape code; molecule window or plain form
+    (AUTO falls back to plain for structures past the window kernel); the
+    binned forms refuse it; the window form stages squared offsets in LDS."""
+    lib = pg._lib()
+    info = pg.PlanInfo()
+    d = desc_ok()
+    d.cutoff_shape = 2
+    assert validate(d, batch_ok()) == pg.PG_E_PARAM
+    cube = desc_ok()
+    assert lib.pg_plan(None, ctypes.byref(cube), ctypes.byref(batch_ok()), 0x10000,
+                       ctypes.byref(info)) == 0
+    lds_cube = info.lds_bytes
+    sph = desc_ok()
+    sph.cutoff_shape = pg.SHAPES["sphere"]
+    assert lib.pg_plan(None, ctypes.byref(sph), ctypes.byref(batch_ok()), 0x10000,
+                       ctypes.byref(info)) == 0
+    assert info.form == pg.FORMS["window"] and info.unroll == 1
+    assert info.lds_bytes > lds_cube
+    big = batch_ok(n_atoms=4000, max_atoms=1000)
+    assert lib.pg_plan(None, ctypes.byref(sph), ctypes.byref(big), 0x10000, ctypes.byref(info)) == 0
+    assert info.form == pg.FORMS["plain"] and info.binned == 0
+    for form in ("window", "mfma"):
+        d = desc_ok(form=form)
+        d.cutoff_shape = pg.SHAPES["sphere"]
+        assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000,
+                           ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
 
 
 def test_reversal_workspace_host_only():
