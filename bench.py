@@ -357,7 +357,7 @@ def main():
                                  "algorithmic_bytes_per_launch": alg, "launch_ms": ev},
                     "loss_first_step": loss0, "loss_last_step": loss1})
         kind = "reversal step"
-        Th = target.cpu().numpy()
+        Th = None if args.no_cpu else target.cpu().numpy()   # the CPU leg's targets
     else:
         out_dt = torch.bfloat16 if wl.out_dtype == "bf16" or wl.kind == "crystal" else torch.float32
         desc, out, main_res = forward_case(out_dt, "auto", True, args.steps, args.warmup)
