@@ -141,13 +141,12 @@ enum { PG_CUTOFF_CUBE = 0, PG_CUTOFF_SPHERE = 1 };
    most one image of each atom.  An image's position is fl32(mu_alpha +
    ((n_0 M[alpha][0] + n_1 M[alpha][1]) + n_2 M[alpha][2])) evaluated in
    double and rounded once; its windows are then decided exactly as for a
-   non-periodic atom.  The library expands each atom into the K images of a
-   fixed lattice range that can reach the grid (K <= 64, else
-   PG_E_PERIODIC) and runs the non-periodic map on them, so the workspace
-   grows with K.  Not with per-structure spacings, weighted channels,
-   pg_autotune or pg_reversal_step (PG_E_UNSUPPORTED).  A device error on
-   an image reports the image index atom * K + k; the expansion itself
-   reports invalid atoms by atom index. */
+   non-periodic atom.  The library considers for each atom the K images of
+   a fixed lattice range (K <= 64, else PG_E_PERIODIC), keeps those whose
+   cutoff cube can meet the grid, and runs the non-periodic map on them; the
+   workspace is sized for all K.  Invalid atoms are reported by atom index
+   and get no image.  Not with per-structure spacings, weighted channels,
+   pg_autotune or pg_reversal_step (PG_E_UNSUPPORTED). */
 enum { PG_CELL_NONE = 0, PG_CELL_ORTHO = 1, PG_CELL_TRICLINIC = 2 };
 
 /* A ragged batch of structures (device arrays unless noted). */

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const long long a = (long long)blockIdx.x * waves + wave;
-    const bool active = a < p.n_atoms;
+    const bool active = a < live_atoms(p);
     const int NT = p.W + p.H + p.D;
     // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | dsq[NT] | 3 range records
     int *idx = (int *)(smem + (size_t)wave * (NT * 16 + 3 * sizeof(AxisRanges)));

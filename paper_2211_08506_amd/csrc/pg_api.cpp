@@ -193,7 +193,8 @@ struct Tri {
     TriParams q;
     pg_grid_desc din;
     pg_batch bin;
-    size_t off_types = 0, off_offs = 0, off_grad = 0, inner_off = 0;
+    size_t off_types = 0, off_offs = 0, off_grad = 0, off_istart = 0, inner_off = 0;
+    int32_t K_keep = 1;      // most images one atom can keep
 };
 
 size_t align256(size_t v);
@@ -224,8 +225,11 @@ int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
     Mi[7] = (M[1] * M[6] - M[0] * M[7]) / det;
     Mi[8] = (M[0] * M[4] - M[1] * M[3]) / det;
     double rc_max = 0.0;
-    for (int t = 0; t < n_sig_of(d, b); ++t)
-        rc_max = std::max(rc_max, (double)rc_of(d, t));
+    T.q.n_sig = n_sig_of(d, b);
+    for (int t = 0; t < T.q.n_sig; ++t) {
+        T.q.rc[t] = rc_of(d, t);
+        rc_max = std::max(rc_max, (double)T.q.rc[t]);
+    }
     // distinct images of one atom keep their cutoff cubes apart
     const int R = kTriCheckReach;
     for (int n0 = -R; n0 <= R; ++n0)
@@ -270,19 +274,52 @@ int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
         return PG_E_PERIODIC;
     if ((long long)b->n_atoms * K > 2147483647LL)
         return PG_E_SHAPE;
+    // images an atom can keep: those inside the grid box widened as the
+    // device test widens it (rc_max and a voxel); along cell axis j their
+    // fractional coordinates lie in an interval of length l_j, which holds
+    // at most floor(l_j) + 1 lattice translates of one atom
+    long long K_keep = 1;
+    {
+        double lmin[3] = {1e300, 1e300, 1e300}, lmax[3] = {-1e300, -1e300, -1e300};
+        for (int c = 0; c < 8; ++c) {
+            double x[3];
+            for (int al = 0; al < 3; ++al) {
+                const double w = rc_max + (double)d->spacing[al];
+                const double lo = (double)d->origin[al] - w;
+                const double hi = (double)d->origin[al] + N[al] * (double)d->spacing[al] + w;
+                x[al] = (c >> al) & 1 ? hi : lo;
+            }
+            for (int j = 0; j < 3; ++j) {
+                const double g = Mi[3 * j] * x[0] + Mi[3 * j + 1] * x[1] + Mi[3 * j + 2] * x[2];
+                lmin[j] = std::min(lmin[j], g);
+                lmax[j] = std::max(lmax[j], g);
+            }
+        }
+        for (int j = 0; j < 3; ++j)
+            K_keep *= (long long)std::floor(lmax[j] - lmin[j] + 1e-3) + 1;
+        K_keep = std::min(K_keep, K);
+    }
+    T.K_keep = (int32_t)K_keep;
+    T.q.bound = (long long)b->n_atoms * K_keep;
     T.q.K = (int32_t)K;
     T.q.n_mol = b->n_mol;
     T.q.n_atoms = b->n_atoms;
+    for (int al = 0; al < 3; ++al) {
+        T.q.o[al] = d->origin[al];
+        T.q.h[al] = d->spacing[al];
+        T.q.N[al] = N[al];
+    }
     T.din = *d;
     T.din.periodic = PG_CELL_NONE;
     T.bin = *b;
-    T.bin.n_atoms = b->n_atoms * K;
-    T.bin.max_atoms = (int32_t)std::min<long long>((long long)b->max_atoms * K, 2147483647LL);
-    const size_t nk = (size_t)T.bin.n_atoms;
+    T.bin.n_atoms = b->n_atoms * K_keep;
+    T.bin.max_atoms = (int32_t)std::min<long long>((long long)b->max_atoms * K_keep, 2147483647LL);
+    const size_t nk = (size_t)b->n_atoms * (size_t)K;   // room for every candidate image
     T.off_types = align256(nk * 12);
     T.off_offs = T.off_types + align256(nk * 4);
     T.off_grad = T.off_offs + align256(((size_t)b->n_mol + 1) * 4);
-    T.inner_off = T.off_grad + align256(nk * 12);
+    T.off_istart = T.off_grad + align256(nk * 12);
+    T.inner_off = T.off_istart + align256(((size_t)b->n_atoms + 1) * 4);
     return PG_OK;
 }
 
@@ -303,6 +340,8 @@ void tri_bind(Tri &T, const pg_batch *b, void *ws)
     T.q.exp_types = (int32_t *)(w + T.off_types);
     T.q.exp_offsets = (int32_t *)(w + T.off_offs);
     T.q.grad_img = (const float *)(w + T.off_grad);
+    T.q.istart = (int32_t *)(w + T.off_istart);
+    T.q.origins = b->origins;
     T.bin.xyz = T.q.exp_xyz;
     T.bin.types = T.q.exp_types;
     T.bin.offsets = T.q.exp_offsets;
@@ -883,7 +922,6 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
     tri_bind(T, batch, ws);
     GridParams p;
     fill_params(p, ctx, &T.din, &T.bin, P, out, (unsigned char *)ws + T.inner_off);
-    const int n_sig = p.n_sig;
     std::string key;
     if (ctx->use_graph) {
         key = graph_key(desc, batch, P, out, ws, ws_bytes);
@@ -891,7 +929,7 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
     }
     return run_launches(ctx, ctx->use_graph != 0, key, (hipStream_t)stream,
                         [&](hipStream_t st) -> hipError_t {
-                            hipError_t e = launch_tri_expand(T.q, ctx->d_err, n_sig, st);
+                            hipError_t e = launch_tri_expand(T.q, ctx->d_err, st);
                             if (e != hipSuccess)
                                 return e;
                             GridParams q = p;
@@ -946,7 +984,7 @@ int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     p.grad_xyz = (float *)((unsigned char *)ws + T.off_grad);
     T.q.grad = grad_xyz;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_tri_expand(T.q, ctx->d_err, p.n_sig, st);
+    hipError_t e = launch_tri_expand(T.q, ctx->d_err, st);
     if (e == hipSuccess)
         e = launch_adjoint(p, desc->out_dtype, st);
     if (e == hipSuccess)

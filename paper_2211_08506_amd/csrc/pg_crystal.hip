@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, Cryst
     const int m_last = structure_of(p.offsets, p.n_mol, a1);
     const bool local = m_last - m_first < PREP_SPAN;
     const long long a = a0 + tid;
-    if (a < p.n_atoms) {
+    if (a < live_atoms(p)) {
         AtomWindow *w = q.table + a;
         const int m = write_atom_window(p, a, w);
         const int t = listed_type(*w);
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_place_kernel(GridParams p, Crys
     __shared__ uint32_t wc[PREP_BLOCK / 64][PG_MAX_CHANNELS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long a = (long long)blockIdx.x * PREP_BLOCK + tid;
-    const int t = a < p.n_atoms ? listed_type(q.table[a]) : -1;
+    const int t = a < live_atoms(p) ? listed_type(q.table[a]) : -1;
     const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t rank = 0;
     for (int c = 0; c < p.C; ++c) {

@@ -351,6 +351,15 @@ __device__ __forceinline__ bool atom_valid(float x, float y, float z, int t, int
     return t >= 0 && t < C && isfinite(x) && isfinite(y) && isfinite(z);
 }
 
+// Atoms the batch holds on the device, offsets[n_mol], capped by the host
+// bound n_atoms: atoms past the CSR belong to no structure (and the image
+// batch of a triclinic request fills only part of its bound).
+__device__ __forceinline__ long long live_atoms(const GridParams &p)
+{
+    const long long n = p.n_mol > 0 ? (long long)p.offsets[p.n_mol] : 0;
+    return n < 0 ? 0 : (n < p.n_atoms ? n : p.n_atoms);
+}
+
 // ---------------------------------------------------------------------------
 // Per-atom window records (plain and crystal paths)
 // ---------------------------------------------------------------------------

@@ -51,9 +51,11 @@ hipError_t launch_peaks(const PeakParams &p, hipStream_t s);
 int residual_chunks(long long per_mol);
 hipError_t launch_residual(const GridParams &p, double *partial, hipStream_t s);
 
-// Triclinic cells (pg_triclinic.hip): image expansion (invalid atoms raise
-// PG_E_DEVICE_DATA with their atom index) and the image-gradient sum.
-hipError_t launch_tri_expand(const TriParams &q, DeviceError *err, int n_sig, hipStream_t s);
+// Triclinic cells (pg_triclinic.hip): image expansion -- count, scan and
+// write of the images that can reach the grid (invalid atoms raise
+// PG_E_DEVICE_DATA with their atom index and get no image) -- and the
+// image-gradient sum.
+hipError_t launch_tri_expand(const TriParams &q, DeviceError *err, hipStream_t s);
 hipError_t launch_tri_reduce(const TriParams &q, hipStream_t s);
 
 }  // namespace pg

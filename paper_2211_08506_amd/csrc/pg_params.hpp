@@ -90,13 +90,19 @@ struct TriParams {
     float *exp_xyz;          // n_atoms * K x 3 image positions
     int32_t *exp_types;      // n_atoms * K (-1: invalid atom)
     int32_t *exp_offsets;    // n_mol + 1: offsets * K
-    const float *grad_img;   // n_atoms * K x 3 image gradients
+    const float *grad_img;   // image gradients, in image order
     float *grad;             // n_atoms x 3 (may be nullptr)
+    int32_t *istart;         // n_atoms + 1: images per atom, then their exclusive scan
+    const float *origins;    // per-structure grid origins, or nullptr
     double M[9];             // cell, row-major: M[3 * alpha + j] = alpha component of vector j
     double Minv[9];
+    float o[3], h[3];        // grid origin and spacing (x, y, z)
+    float rc[PG_MAX_CHANNELS];
+    int32_t N[3];            // grid points along x, y, z
     int32_t klo[3], kdim[3]; // lattice range of the home-cell copy, per cell axis
-    int32_t K, n_mol;
+    int32_t K, n_mol, n_sig;
     long long n_atoms;
+    long long bound;         // images the inner request is sized for (n_atoms x most kept)
 };
 
 // Per-atom window table written by the prep kernel (plain form).

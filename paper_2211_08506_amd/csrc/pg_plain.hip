@@ -20,7 +20,7 @@ namespace pg {
 __global__ void __launch_bounds__(256) prep_kernel(GridParams p)
 {
     const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= p.n_atoms)
+    if (a >= live_atoms(p))
         return;
     write_atom_window(p, a, (AtomWindow *)p.ws + a);
 }
