@@ -93,23 +93,25 @@ def expand(xyz, types, offsets, M, dims, spacing, origin, rc_max):
 
 
 def grid_triclinic_fp64(xyz, types, offsets, sigma, dims, spacing, M, origin, cutoff_k=3.0,
-                        value="point"):
+                        value="point", cutoff_shape="cube"):
     """Dense FP64 grids (B, C, D, H, W) of a batch of triclinic cells."""
     sig = np.asarray(sigma, np.float32)
     rc_max = float(np.max(np.float32(cutoff_k) * sig))
     assert check_cell(M, rc_max), "image cutoff cubes overlap"
     xi, ti, oi, _ = expand(xyz, types, offsets, M, dims, spacing, origin, rc_max)
-    return grid_fp64(xi, ti, oi, sigma, dims, spacing, origin, cutoff_k=cutoff_k, value=value)
+    return grid_fp64(xi, ti, oi, sigma, dims, spacing, origin, cutoff_k=cutoff_k, value=value,
+                     cutoff_shape=cutoff_shape)
 
 
 def grad_triclinic_fp64(xyz, types, offsets, sigma, dims, spacing, U, M, origin, cutoff_k=3.0,
-                        value="point"):
+                        value="point", cutoff_shape="cube"):
     """dL/dxyz (n_atoms, 3) for L = sum(U * G) over triclinic cells: each
     image is a translate of its atom, so the image gradients add up."""
     sig = np.asarray(sigma, np.float32)
     rc_max = float(np.max(np.float32(cutoff_k) * sig))
     xi, ti, oi, src = expand(xyz, types, offsets, M, dims, spacing, origin, rc_max)
-    gi = grad_fp64(xi, ti, oi, sigma, dims, spacing, U, origin, cutoff_k=cutoff_k, value=value)
+    gi = grad_fp64(xi, ti, oi, sigma, dims, spacing, U, origin, cutoff_k=cutoff_k, value=value,
+                   cutoff_shape=cutoff_shape)
     g = np.zeros((np.asarray(xyz).reshape(-1, 3).shape[0], 3))
     np.add.at(g, src, gi)
     return g
