@@ -387,12 +387,15 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
     if (P.lds > (size_t)max_lds)
         return PG_E_UNSUPPORTED;
     const long long nmc = (long long)b->n_mol * d->C;
-    if (nmc > 0x7fffffffLL || 3 * b->n_atoms > 0xffffffffLL)
+    // channel-partition entries: one per atom, or with weighted channels one
+    // per (atom, channel with a non-zero weight)
+    const long long n_ent = b->n_atoms * (weighted(b) ? d->C : 1);
+    if (nmc > 0x7fffffffLL || 3 * n_ent > 0xffffffffLL)
         return PG_E_SHAPE;
     P.nblk = crystal_prep_blocks(b->n_atoms);
-    // z images (at most 3 per atom) in 32-image blocks: run r starts at
+    // z images (at most 3 per entry) in 32-image blocks: run r starts at
     // block ceil(3 mstart[r] / 32) + 2 r
-    P.op_blocks = (3 * b->n_atoms + 31) / 32 + 2 * nmc + 1;
+    P.op_blocks = (3 * n_ent + 31) / 32 + 2 * nmc + 1;
     size_t off = align256((size_t)b->n_atoms * sizeof(AtomWindow));
     P.ws_bcount = off;
     off += align256((size_t)d->C * P.nblk * 4);
@@ -401,7 +404,7 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
     P.ws_mstart = off;
     off += align256((size_t)nmc * 4);
     P.ws_list = off;
-    off += align256((size_t)std::max<long long>(b->n_atoms, 1) * sizeof(ListEntry));
+    off += align256((size_t)std::max<long long>(n_ent, 1) * sizeof(ListEntry));
     P.ws_zlist = off;
     off += align256((size_t)P.op_blocks * 32 * sizeof(ZEntry));
     P.ws_ecount = off;
@@ -517,9 +520,6 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
     if (sphere && (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)))
         return PG_E_UNSUPPORTED;
     P.form = form;
-    // weighted channels: the molecule window form and the plain form only
-    if (weighted(b) && (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)))
-        return PG_E_UNSUPPORTED;
     if (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits))
         return crystal_plan(ctx, d, b, form, P);
     if (form == PG_FORM_PLAIN) {

@@ -54,12 +54,32 @@ __global__ void cr_clear_kernel(uint32_t *a, long long n)
 // structure per block instead of one per atom).
 constexpr int PREP_SPAN = 4;
 
-// The channel an atom is listed under, or -1: skipped atoms, and atoms
-// whose window misses the grid on some axis (they add nothing -- e.g. the
-// lattice images of a triclinic cell that do not reach the grid).
+// The type of an atom that enters the channel partition, or -1: skipped
+// atoms, and atoms whose window misses the grid on some axis (they add
+// nothing -- e.g. the lattice images of a triclinic cell that do not reach
+// the grid).
 __device__ __forceinline__ int listed_type(const AtomWindow &w)
 {
     return (w.type >= 0 && w.n[0] > 0 && w.n[1] > 0 && w.n[2] > 0) ? w.type : -1;
+}
+
+// Listed atom a of type t is entered in channel c: c is its type, or with
+// weighted channels its weight for c is non-zero.
+__device__ __forceinline__ bool listed_in(const GridParams &p, long long a, int t, int c)
+{
+    return p.weights ? p.weights[(size_t)a * p.C + c] != 0.f : t == c;
+}
+
+// Per image of channel c: the atom's type (its sigma) and weight.
+__device__ __forceinline__ int image_type(const GridParams &p, const CrystalParams &q, int atom,
+                                          int c)
+{
+    return p.weights ? q.table[atom].type : c;
+}
+
+__device__ __forceinline__ float image_weight(const GridParams &p, int atom, int c)
+{
+    return p.weights ? p.weights[(size_t)atom * p.C + c] : 1.f;
 }
 
 __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, CrystalParams q)
@@ -84,12 +104,16 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, Cryst
         AtomWindow *w = q.table + a;
         const int m = write_atom_window(p, a, w);
         const int t = listed_type(*w);
-        if (t >= 0) {
-            atomicAdd(&cnt[t], 1u);
+        // the channels the atom is listed under: its type, or with weighted
+        // channels every channel with a non-zero weight
+        for (int c = 0; c < p.C && t >= 0; ++c) {
+            if (!listed_in(p, a, t, c))
+                continue;
+            atomicAdd(&cnt[c], 1u);
             if (local)
-                atomicAdd(&cntm[t][m - m_first], 1u);
+                atomicAdd(&cntm[c][m - m_first], 1u);
             else
-                atomicAdd(&q.mcount[(size_t)t * p.n_mol + m], 1u);
+                atomicAdd(&q.mcount[(size_t)c * p.n_mol + m], 1u);
         }
     }
     __syncthreads();
@@ -147,29 +171,34 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_place_kernel(GridParams p, Crys
     const long long a = (long long)blockIdx.x * PREP_BLOCK + tid;
     const int t = a < live_atoms(p) ? listed_type(q.table[a]) : -1;
     const unsigned long long below = (1ull << lane) - 1ull;
-    uint32_t rank = 0;
     for (int c = 0; c < p.C; ++c) {
-        const unsigned long long mask = __ballot(t == c);
-        if (t == c)
-            rank = (uint32_t)__popcll(mask & below);
+        const unsigned long long mask = __ballot(t >= 0 && listed_in(p, a, t, c));
         if (lane == 0)
             wc[wave][c] = (uint32_t)__popcll(mask);
     }
     __syncthreads();
-    if (t >= 0) {
-        uint32_t pos = q.bcount[(size_t)t * q.nblk + blockIdx.x] + rank;
-        for (int w = 0; w < wave; ++w)
-            pos += wc[w][t];
-        const AtomWindow &w = q.table[a];
-        ListEntry e;
-        e.atom = (int32_t)a;
+    if (t < 0)
+        return;
+    const AtomWindow &w = q.table[a];
+    ListEntry e;
+    e.atom = (int32_t)a;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const bool u = r < w.n[2];
-            e.z[r] = u ? pack_range(w.lo[2][r], w.hi[2][r]) : pack_range(0, -1);
-            e.bh[r] = u ? w.bh[2][r] : 0.f;
-            e.bl[r] = u ? w.bl[2][r] : 0.f;
-        }
+    for (int r = 0; r < 3; ++r) {
+        const bool u = r < w.n[2];
+        e.z[r] = u ? pack_range(w.lo[2][r], w.hi[2][r]) : pack_range(0, -1);
+        e.bh[r] = u ? w.bh[2][r] : 0.f;
+        e.bl[r] = u ? w.bl[2][r] : 0.f;
+    }
+    // one entry per channel the atom is listed under, at its stable rank
+    for (int c = 0; c < p.C; ++c) {
+        const bool in = listed_in(p, a, t, c);
+        const unsigned long long mask = __ballot(in);
+        if (!in)
+            continue;
+        uint32_t pos = q.bcount[(size_t)c * q.nblk + blockIdx.x] +
+                       (uint32_t)__popcll(mask & below);
+        for (int v = 0; v < wave; ++v)
+            pos += wc[v][c];
         q.list[pos] = e;
     }
 }
@@ -374,8 +403,11 @@ __global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalPa
     __syncthreads();
     if (k >= (long long)q.ecount[mc])
         return;
-    const AtomWindow &w = q.table[q.zlist[32 * b0 + k].atom];
-    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c];
+    const int atom = q.zlist[32 * b0 + k].atom;
+    const AtomWindow &w = q.table[atom];
+    const int ti = image_type(p, q, atom, c);
+    const float inv2s2 = p.inv2s2[ti], isq2s = p.isq2s[ti];
+    const float wgt = image_weight(p, atom, c);   // folded into phi_y
     const bool box = p.box != 0;
     uint16_t *xo = q.xop + (size_t)gb * W * 32 + kl;
     uint16_t *yo = q.yop + (size_t)gb * H * 32 + kl;
@@ -387,7 +419,7 @@ __global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalPa
     for (int r = 0; r < w.n[1]; ++r) {
         const float bh = w.bh[1][r], bl = w.bl[1][r];
         for (int v = w.lo[1][r] + rg; v <= w.hi[1][r]; v += 8)
-            yo[(size_t)v * 32] = bf16_bits(factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s));
+            yo[(size_t)v * 32] = bf16_bits(factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s) * wgt);
     }
 }
 
@@ -428,14 +460,16 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
         nkb = 0;
     }
     const long long rb = run_block(q, mc);
-    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c], hz = p.h[2];
+    const float hz = p.h[2];
     for (int i = tid; i < nkb * 32; i += blockDim.x) {
         const uint32_t k = (uint32_t)kb0 * 32 + i;
         float g = 0.f;
         if (k < n_img) {
             const ZEntry ze = q.zlist[32 * rb + k];
-            if (z >= range_lo(ze.range) && z <= range_hi(ze.range))
-                g = factor1d(p.box != 0, ze.bh, ze.bl, hz, z, inv2s2, isq2s);
+            if (z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
+                const int ti = image_type(p, q, ze.atom, c);
+                g = factor1d(p.box != 0, ze.bh, ze.bl, hz, z, p.inv2s2[ti], p.isq2s[ti]);
+            }
         }
         gzs[i] = g;
     }
@@ -561,7 +595,6 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
     const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
     const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
     const long long eb = 32ll * run_block(q, mc);
-    const float inv2s2 = p.inv2s2[c], isq2s = p.isq2s[c];
     const bool box = p.box != 0;
     const int ly = 4 * (lane >> 3), lx = 4 * (lane & 7);
     float acc[TMAX][4][4];
@@ -586,7 +619,10 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
             if (k < kn) {
                 const ZEntry ze = q.zlist[eb + k0 + k];
                 if (z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
-                    const float g = factor1d(box, ze.bh, ze.bl, p.h[2], z, inv2s2, isq2s);
+                    const int ti = image_type(p, q, ze.atom, c);
+                    const float inv2s2 = p.inv2s2[ti], isq2s = p.isq2s[ti];
+                    const float g = factor1d(box, ze.bh, ze.bl, p.h[2], z, inv2s2, isq2s) *
+                                    image_weight(p, ze.atom, c);
                     const AtomWindow &w = q.table[ze.atom];
                     uint32_t tx = 0u, ty = 0u;   // tile columns / rows the windows meet
                     for (int r = 0; r < w.n[0]; ++r) {

@@ -166,9 +166,9 @@ def test_workspace_and_plan_host_only():
 
 
 def test_weighted_channels_validation_and_plans():
-    """Weighted channels: types index n_types widths independent of C; the
-    window and plain forms take them, the binned path does not; the window
-    form stages the weights in LDS."""
+    """Weighted channels: types index n_types widths independent of C; every
+    form takes them; the window form stages the weights in LDS, the binned
+    path lists each atom under every channel it weighs into."""
     lib = pg._lib()
     info = pg.PlanInfo()
     sig8 = [0.4 + 0.3 * i / 7 for i in range(8)]
@@ -195,11 +195,17 @@ def test_weighted_channels_validation_and_plans():
     assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(bw), 0x10000, ctypes.byref(info)) == 0
     assert info.form == pg.FORMS["window"] and info.lds_bytes == lds0 + 16 * 5 * 4
     big = batch_ok(n_atoms=4000, max_atoms=1000)
-    big.weights = 0x3000
-    for form in ("auto", "window", "mfma"):
+    n = ctypes.c_size_t()
+    for form in ("window", "mfma"):
         d = desc_ok(form=form, out_dtype="bf16")
         assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000,
-                           ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
+                           ctypes.byref(info)) == 0 and info.binned == 1
+        assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(big), ctypes.byref(n)) == 0
+        ws_one = n.value
+        big.weights = 0x3000       # one channel-partition entry per (atom, channel)
+        assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(big), ctypes.byref(n)) == 0
+        assert n.value > ws_one + 4000 * 4 * 48
+        big.weights = None
     d = desc_ok(form="plain")
     assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000, ctypes.byref(info)) == 0
 

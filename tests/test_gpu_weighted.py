@@ -157,12 +157,45 @@ def test_weighted_full_size_sampled(pg, dev):
     assert rel <= BF16_TOL
 
 
-def test_weighted_large_structures_are_refused(pg, dev):
+@pytest.mark.parametrize("form,dtype,tol", [("window", torch.float32, F32_TOL),
+                                            ("mfma", torch.bfloat16, BF16_TOL)])
+def test_weighted_binned_path(pg, dev, form, dtype, tol):
+    """Periodic cells above the window kernel's capacity, 6 types into 3
+    channels with signed weights (some exactly zero): the binned path lists
+    each atom under every channel it weighs into, with the width of its
+    type; the MFMA form folds the weight into its phi_y operand."""
     rng = np.random.default_rng(27)
-    xyz = rng.uniform(0, 8, size=(400, 3)).astype(np.float32)
-    b = synth.Batch(xyz, rng.integers(0, 3, 400).astype(np.int32), np.array([0, 400], np.int32))
-    x, t, o = to_device(b, dev)
-    with pytest.raises(pg.PGError) as ei:
-        pg.grid(x, t, o, [0.3, 0.35, 0.4], dims=(40, 40, 40), spacing=0.21, cell=8.0,
-                weights=torch.ones((400, 2), device=dev))
-    assert ei.value.status == pg.PG_E_UNSUPPORTED
+    off = np.array([0, 400, 700], np.int32)
+    xyz = rng.uniform(0, 8, size=(700, 3)).astype(np.float32)
+    types = rng.integers(0, 6, 700).astype(np.int32)
+    sig = synth.sigma_table(6, 0.3, 0.45)
+    E = rng.standard_normal((700, 3)).astype(np.float32)
+    E[rng.random(E.shape) < 0.3] = 0.0
+    dims, h = (40, 40, 40), 0.21
+    say(f"case weighted binned path form={form} dtype={dtype}")
+    ref = oracle.grid_fp64(xyz, types, off, sig, dims, h, (0, 0, 0), cell=8.0, weights=E)
+    x = torch.tensor(xyz, device=dev, requires_grad=True)
+    Et = torch.tensor(E, device=dev, requires_grad=True)
+    t, o = torch.tensor(types, device=dev), torch.tensor(off, device=dev)
+    desc = pg.make_desc(3, dims, h, (0, 0, 0), sig, 3.0, 8.0, dtype, form, n_types=6)
+    plan = pg.default_context(dev).plan(desc, pg.BatchView(x.detach(), t, o, weights=Et.detach()))
+    assert plan["binned"] == 1 and plan["form"] == form, plan
+    g = pg.grid(x, t, o, list(sig), dims=dims, spacing=h, cell=8.0, out_dtype=dtype, form=form,
+                weights=Et)
+    torch.cuda.synchronize()
+    got = g.detach().double().cpu().numpy()
+    rel, mx = errors(got, ref)
+    wm = worst_molecule(got, ref)
+    say(f"[weighted binned {form}/{dtype}] rel-L2 {rel:.3e} max-abs {mx:.3e} worst {wm:.3e}")
+    assert rel <= tol and wm <= tol
+    # gradients through the (one wave per atom) adjoint
+    U = synth.upstream(28, (2, 3) + dims)
+    g.backward(torch.tensor(U, device=dev).to(g.dtype))
+    torch.cuda.synchronize()
+    Uused = torch.tensor(U, device=dev).to(g.dtype).double().cpu().numpy()
+    gx_o, gw_o = oracle.grad_fp64(xyz, types, off, sig, dims, h, Uused, (0, 0, 0), cell=8.0,
+                                  weights=E, return_weight_grad=True)
+    rx, _ = errors(x.grad.cpu().numpy(), gx_o)
+    rw, _ = errors(Et.grad.cpu().numpy(), gw_o)
+    say(f"[weighted binned grads] xyz {rx:.3e}, weights {rw:.3e}")
+    assert rx <= ADJ_TOL and rw <= ADJ_TOL
