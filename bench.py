@@ -138,10 +138,11 @@ def window_evals(b, wl) -> int:
     return int(np.sum(cnt[0] * cnt[1] * cnt[2]))
 
 
-def mfma_dense_flops(b, wl) -> int:
+def mfma_dense_flops(b, wl, dense_channels=None) -> int:
     """Dense MFMA flops of the binned plane kernel: per (structure, channel,
     z) bin, 2 x (rows x cols padded to 128-voxel super-tiles) x (bin size
-    padded to the 32-atom step)."""
+    padded to the 32-atom step).  dense_channels: a dense embedding lists
+    every atom under each of that many channels."""
     D, H, W = wl.dims
     mol = np.searchsorted(b.offsets, np.arange(b.n_atoms), side="right") - 1
     bins = np.zeros((b.n_mol, wl.n_types, D), np.int64)
@@ -151,6 +152,8 @@ def mfma_dense_flops(b, wl) -> int:
         z = np.concatenate([np.arange(l, h + 1) for l, h in zip(lo, hi) if h >= l]) \
             if n.sum() else np.zeros(0, np.int64)
         np.add.at(bins, (mol[a], b.types[a], z), 1)
+    if dense_channels:
+        bins = np.repeat(bins.sum(axis=1, keepdims=True), dense_channels, axis=1)
     k_pad = ((bins + 31) // 32) * 32
     tiles = ((H + 127) // 128) * ((W + 127) // 128)
     return int(2 * 128 * 128 * tiles * k_pad.sum())
@@ -247,8 +250,9 @@ def main():
     ntypes = 0
     E = None
     if args.embed:
-        if wl.kind == "crystal" or wl.name in ("adjoint1024", "reversal1024"):
-            print("bench.py: --embed applies to the molecule forward workloads", file=sys.stderr)
+        if wl.name in ("adjoint1024", "reversal1024") or args.triclinic:
+            print("bench.py: --embed applies to the forward workloads (not triclinic cells)",
+                  file=sys.stderr)
             sys.exit(2)
         table = synth.embedding(wl.seed + 100, wl.n_types, args.embed)
         E = table[b.types]
@@ -380,7 +384,7 @@ def main():
             kname = ("binned path, whole step: cr_clear, cr_prep, cr_scan, cr_place, cr_zsort, "
                      + ("cr_operand, " if plan["form"] == "mfma" else "")
                      + f"cr_{plan['form']}_kernel")
-            flops = mfma_dense_flops(b, wl)
+            flops = mfma_dense_flops(b, wl, C if E is not None else None)
             extra["mfma_dense_tflops"] = (flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
                                           if plan["form"] == "mfma" else None)
             extra["mfma_dense_flops_per_step"] = flops

@@ -169,9 +169,11 @@ typedef struct pg_batch {
    and the weighted grids mentioned after Eq. 6); its width is still
    sigma[types[a]], types lying in [0, n_types), so the number of element
    types is independent of the channel count.  One-hot weights give the
-   unweighted grid bit for bit.  Weighted requests take the molecule window
-   form or the plain form; the binned large-structure path returns
-   PG_E_UNSUPPORTED. */
+   unweighted grid bit for bit.  Every form takes weights; the binned
+   large-structure path lists each atom under every channel with a non-zero
+   weight (its workspace grows with C), and the MFMA form rounds the
+   weighted phi_y factor to bf16 once.  Not with triclinic cells
+   (PG_E_UNSUPPORTED). */
 
 typedef struct pg_ctx pg_ctx;
 
