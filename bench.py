@@ -138,11 +138,12 @@ def window_evals(b, wl) -> int:
     return int(np.sum(cnt[0] * cnt[1] * cnt[2]))
 
 
-def mfma_dense_flops(b, wl, dense_channels=None) -> int:
-    """Dense MFMA flops of the binned plane kernel: per (structure, channel,
-    z) bin, 2 x (rows x cols padded to 128-voxel super-tiles) x (bin size
-    padded to the 32-atom step).  dense_channels: a dense embedding lists
-    every atom under each of that many channels."""
+def mfma_dense_flops(b, wl, dense_channels=None):
+    """Flops of the binned plane contraction, as (issued, algorithmic): per
+    (structure, channel, z) bin, the kernel issues 2 x (rows x cols padded
+    to 128-voxel super-tiles) x (bin size padded to the 32-atom step); the
+    algorithmic count is 2 x H x W x (bin size).  dense_channels: a dense
+    embedding lists every atom under each of that many channels."""
     D, H, W = wl.dims
     mol = np.searchsorted(b.offsets, np.arange(b.n_atoms), side="right") - 1
     bins = np.zeros((b.n_mol, wl.n_types, D), np.int64)
@@ -156,7 +157,7 @@ def mfma_dense_flops(b, wl, dense_channels=None) -> int:
         bins = np.repeat(bins.sum(axis=1, keepdims=True), dense_channels, axis=1)
     k_pad = ((bins + 31) // 32) * 32
     tiles = ((H + 127) // 128) * ((W + 127) // 128)
-    return int(2 * 128 * 128 * tiles * k_pad.sum())
+    return int(2 * 128 * 128 * tiles * k_pad.sum()), int(2 * H * W * bins.sum())
 
 
 def cpu_oracle_baseline(units, run_one, seconds, describe, max_threads=None):
@@ -202,7 +203,7 @@ def main():
                     help="crystal8 in a sheared (triclinic) cell of the same edge length")
     ap.add_argument("--embed", type=int, default=0,
                     help="weighted channels: a dense seeded embedding of the element types "
-                         "into this many channels (molecule forward workloads)")
+                         "into this many channels (forward workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain fp32 baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -384,10 +385,11 @@ def main():
             kname = ("binned path, whole step: cr_clear, cr_prep, cr_scan, cr_place, cr_zsort, "
                      + ("cr_operand, " if plan["form"] == "mfma" else "")
                      + f"cr_{plan['form']}_kernel")
-            flops = mfma_dense_flops(b, wl, C if E is not None else None)
+            flops, alg_flops = mfma_dense_flops(b, wl, C if E is not None else None)
             extra["mfma_dense_tflops"] = (flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
                                           if plan["form"] == "mfma" else None)
             extra["mfma_dense_flops_per_step"] = flops
+            extra["mfma_algorithmic_flops_per_step"] = alg_flops
             # the other form / dtype pairs, for the per-shape decision
             for form, dt in (("mfma", torch.bfloat16), ("window", torch.float32),
                              ("window", torch.bfloat16), ("mfma", torch.float32)):
@@ -437,6 +439,17 @@ def main():
             "fill_gbs_same_bytes": fill_gbs,
             "frac_of_fill": achieved / fill_gbs,
         })
+        if wl.kind == "crystal" and plan["form"] == "mfma":
+            # a dense embedding makes the plane contraction the binding
+            # resource: report the bf16 MFMA roofline when it is the larger
+            # fraction (algorithmic flops over the whole step)
+            tflops = alg_flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
+            if tflops / PEAK_BF16_TFLOPS > achieved / PEAK_HBM_GBS:
+                rec["roofline"].update({
+                    "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
+                    "algorithmic_flops_per_launch": alg_flops,
+                    "hbm_frac": achieved / PEAK_HBM_GBS})
         kind = "forward"
 
     if wl.kind == "crystal":

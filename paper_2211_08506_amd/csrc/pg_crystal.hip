@@ -22,9 +22,10 @@
 //            so each plane's images are one contiguous range of that order,
 //            and an operand kernel writes phi_y and phi_x of every image once,
 //            as bf16, in 32-image blocks laid out as the matrix cores read
-//            them.  The plane kernel then streams 16-byte operand fragments,
-//            scales the phi_y fragments by phi_z of the plane, and contracts on
-//            v_mfma_f32_32x32x16_bf16 with FP32 accumulation;
+//            them.  The plane kernel stages each block's rows of its
+//            super-tile in LDS once per workgroup (phi_y scaled by phi_z of
+//            the plane on the way), two blocks ahead of the contraction, and
+//            contracts on v_mfma_f32_32x32x16_bf16 with FP32 accumulation;
 //   window:  the same sum in FP32 on the vector ALUs -- the workgroup compacts,
 //            in list order, the run's atoms whose z window holds the plane;
 //            per 32-atom step their dense factor rows go to LDS and each lane
@@ -41,6 +42,7 @@ namespace pg {
 constexpr int PREP_BLOCK = 256; // atoms per prep / place block (4 waves)
 constexpr int KC = 32;          // atoms per contraction step
 constexpr int ST = 128;         // MFMA super-tile edge (y and x)
+constexpr int OPROW = 40;       // staged operand row: 32 images + 8 bf16 of padding
 
 __global__ void cr_clear_kernel(uint32_t *a, long long n)
 {
@@ -435,6 +437,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParams q)
 {
     __shared__ __attribute__((aligned(16))) float gzs[MFMA_BIN_CAP];   // phi_z per image
+    // two staging buffers of [phi_z phi_y, phi_x][super-tile row][32 images],
+    // rows padded to OPROW elements so that the fragment reads (lanes on
+    // consecutive rows) fall in distinct banks
+    __shared__ __attribute__((aligned(16))) __bf16 ops[2][2][ST * OPROW];
     const int C = p.C, D = p.D, H = p.H, W = p.W;
     const int nsx = (W + ST - 1) / ST, nsy = (H + ST - 1) / ST;
     long long b = xcd_block();
@@ -486,66 +492,87 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
     const int qy = (wave >> 1) * 64, qx = (wave & 1) * 64;
     const int ko = 8 * (lane >> 5);
     const __bf16 *yop = (const __bf16 *)q.yop, *xop = (const __bf16 *)q.xop;
-    // operand rows of this lane; rows past the plane edge load the last row
-    // instead: they only feed output rows / columns that are never stored
-    int yc[2], xc[2];
+    // Staging: the workgroup copies each 32-image operand block's rows of
+    // the super-tile to LDS once -- phi_y scaled by phi_z of the plane
+    // (rounded once to bf16), and phi_x -- so every operand element is
+    // fetched and scaled once per workgroup instead of once per wave that
+    // uses it.  Thread t moves the 16-byte chunk (t % 4) of local rows t / 4
+    // and t / 4 + 64 of both operands; rows past the plane edge copy the last
+    // row instead (they only feed outputs that are never stored).
+    const int srow = tid >> 2, skq = 8 * (tid & 3);
+    int sy_[2], sx_[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        yc[i] = min(y0 + qy + 32 * i + (lane & 31), H - 1);
-        xc[i] = min(x0 + qx + 32 * i + (lane & 31), W - 1);
+    for (int r = 0; r < 2; ++r) {
+        sy_[r] = min(y0 + srow + 64 * r, H - 1);
+        sx_[r] = min(x0 + srow + 64 * r, W - 1);
     }
-    // fragments of one operand block, [k-half][tile]: 16-byte loads with no
-    // use of the registers here, so they stay in flight until contracted
-    auto load_block = [&](int kb, bf16x8 (&ar)[2][2], bf16x8 (&br)[2][2]) {
-        const size_t gb = (size_t)(rb + kb0 + kb);
+    // two register sets: block kb + 2 is fetched while block kb is
+    // contracted and block kb + 1 (fetched one step earlier) is staged
+    bf16x8 ga[2][2], gb[2][2];
+    auto fetch = [&](int kb, bf16x8 (&fa)[2], bf16x8 (&fb)[2]) {
+        const size_t blk = (size_t)(rb + kb0 + kb);
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int kk = 16 * h + ko;
-                ar[h][i] = *(const bf16x8 *)(yop + (gb * H + yc[i]) * 32 + kk);
-                br[h][i] = *(const bf16x8 *)(xop + (gb * W + xc[i]) * 32 + kk);
-            }
+        for (int r = 0; r < 2; ++r) {
+            fa[r] = *(const bf16x8 *)(yop + (blk * H + sy_[r]) * 32 + skq);
+            fb[r] = *(const bf16x8 *)(xop + (blk * W + sx_[r]) * 32 + skq);
+        }
     };
-    // A = phi_y scaled by phi_z of the plane (rounded once to bf16), B = phi_x
-    auto contract = [&](int kb, const bf16x8 (&ar)[2][2], const bf16x8 (&br)[2][2]) {
+    auto stage = [&](int kb, int buf, const bf16x8 (&fa)[2], const bf16x8 (&fb)[2]) {
+        const float4 g0 = *(const float4 *)(gzs + kb * 32 + skq);
+        const float4 g1 = *(const float4 *)(gzs + kb * 32 + skq + 4);
+        const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            bf16x8 av;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                av[e] = (__bf16)((float)fa[r][e] * g[e]);
+            *(bf16x8 *)(ops[buf][0] + (srow + 64 * r) * OPROW + skq) = av;
+            *(bf16x8 *)(ops[buf][1] + (srow + 64 * r) * OPROW + skq) = fb[r];
+        }
+    };
+    auto contract = [&](int buf) {
+        const __bf16 *As = ops[buf][0], *Bs = ops[buf][1];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int kk = 16 * h + ko;
-            const float4 g0 = *(const float4 *)(gzs + kb * 32 + kk);
-            const float4 g1 = *(const float4 *)(gzs + kb * 32 + kk + 4);
-            const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-            bf16x8 av[2];
+            bf16x8 af[2], bf[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    av[i][e] = (__bf16)((float)ar[h][i][e] * g[e]);
+            for (int i = 0; i < 2; ++i) {
+                af[i] = *(const bf16x8 *)(As + (qy + 32 * i + (lane & 31)) * OPROW + kk);
+                bf[i] = *(const bf16x8 *)(Bs + (qx + 32 * i + (lane & 31)) * OPROW + kk);
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], br[h][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
     };
-    // two fragment sets in turn: the loads of one block are in flight while
-    // the other block is contracted (scheduling barriers keep that order)
-    bf16x8 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
-    if (nkb > 0)
-        load_block(0, a0, b0);
+    // one step: fetch kb + 2 (clamped: past the end it refetches the last
+    // block), contract kb, stage kb + 1 into the other buffer (last read
+    // before the previous barrier), barrier
+    auto step = [&](int kb, bf16x8 (&fa_next)[2], bf16x8 (&fb_next)[2],
+                    const bf16x8 (&fa_stage)[2], const bf16x8 (&fb_stage)[2]) {
+        fetch(min(kb + 2, nkb - 1), fa_next, fb_next);
+        contract(kb & 1);
+        if (kb + 1 < nkb)
+            stage(kb + 1, (kb + 1) & 1, fa_stage, fb_stage);
+        __syncthreads();
+    };
+    if (nkb > 0) {
+        fetch(0, ga[0], gb[0]);
+        fetch(min(1, nkb - 1), ga[1], gb[1]);
+        stage(0, 0, ga[0], gb[0]);
+    }
+    __syncthreads();
     int kb = 0;
     for (; kb + 1 < nkb; kb += 2) {
-        load_block(kb + 1, a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
-        contract(kb, a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        load_block(min(kb + 2, nkb - 1), a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        contract(kb + 1, a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
+        step(kb, ga[0], gb[0], ga[1], gb[1]);
+        step(kb + 1, ga[1], gb[1], ga[0], gb[0]);
     }
     if (kb < nkb)
-        contract(kb, a0, b0);
+        step(kb, ga[0], gb[0], ga[1], gb[1]);
 
     // store the quadrant: lane holds column (lane & 31) of rows
     // 8 (e / 4) + 4 (lane / 32) + e % 4 of each tile; a store instruction
