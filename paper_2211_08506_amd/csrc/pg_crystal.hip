@@ -51,6 +51,18 @@ __global__ void cr_clear_kernel(uint32_t *a, long long n)
         a[i] = 0u;
 }
 
+// Two arrays in one launch: [0, na) of a, then [0, nb) of b.
+__global__ void cr_clear2_kernel(uint32_t *a, long long na, uint32_t *b, long long nb)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb;
+         i += (long long)gridDim.x * blockDim.x) {
+        if (i < na)
+            a[i] = 0u;
+        else
+            b[i - na] = 0u;
+    }
+}
+
 // Per-structure counts are aggregated in LDS when the block's atoms span
 // few structures (large structures: one global atomic per channel and
 // structure per block instead of one per atom).
@@ -84,28 +96,56 @@ __device__ __forceinline__ float image_weight(const GridParams &p, int atom, int
     return p.weights ? p.weights[(size_t)atom * p.C + c] : 1.f;
 }
 
-__global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, CrystalParams q)
+// Three threads per atom (wave group q of the block finds axis q of the
+// block's PREP_BLOCK atoms: the exact window search is the long part) build
+// the block's window records in LDS; the block then writes them out as one
+// contiguous 16-byte-store copy, and the first group counts the listed atoms.
+__global__ void __launch_bounds__(3 * PREP_BLOCK) cr_prep_kernel(GridParams p, CrystalParams q)
 {
     __shared__ uint32_t cnt[PG_MAX_CHANNELS];
     __shared__ uint32_t cntm[PG_MAX_CHANNELS][PREP_SPAN];
+    __shared__ int32_t sn[3][PREP_BLOCK];   // ranges per axis
+    __shared__ int32_t sm[PREP_BLOCK];      // structure
+    __shared__ __attribute__((aligned(16))) AtomWindow srec[PREP_BLOCK];
     const int tid = threadIdx.x;
-    for (int c = tid; c < p.C; c += PREP_BLOCK) {
+    for (int c = tid; c < p.C; c += blockDim.x) {
         cnt[c] = 0u;
 #pragma unroll
         for (int j = 0; j < PREP_SPAN; ++j)
             cntm[c][j] = 0u;
     }
-    __syncthreads();
     const long long a0 = (long long)blockIdx.x * PREP_BLOCK;
     const long long a1 = min(p.n_atoms, a0 + PREP_BLOCK) - 1;
     const int m_first = structure_of(p.offsets, p.n_mol, a0);
     const int m_last = structure_of(p.offsets, p.n_mol, a1);
     const bool local = m_last - m_first < PREP_SPAN;
-    const long long a = a0 + tid;
-    if (a < live_atoms(p)) {
-        AtomWindow *w = q.table + a;
-        const int m = write_atom_window(p, a, w);
-        const int t = listed_type(*w);
+    const int ax = tid / PREP_BLOCK, al = tid - ax * PREP_BLOCK;
+    const long long a = a0 + al;
+    const bool live = a < live_atoms(p);
+    if (live) {
+        int n;
+        const int m = write_atom_axis(p, a, ax, srec + al, n);
+        sn[ax][al] = n;
+        if (ax == 0)
+            sm[al] = m;
+    }
+    __syncthreads();
+    {
+        const long long n_live = live_atoms(p) - a0;
+        const int nrec = (int)(n_live < PREP_BLOCK ? (n_live > 0 ? n_live : 0) : PREP_BLOCK);
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        constexpr int R16 = (int)(sizeof(AtomWindow) / 16);
+        static_assert(sizeof(AtomWindow) % 16 == 0, "record copy in 16-byte pieces");
+        const u4 *src = (const u4 *)srec;
+        u4 *dst = (u4 *)(q.table + a0);
+        for (int i = tid; i < nrec * R16; i += blockDim.x)
+            dst[i] = src[i];
+    }
+    if (ax == 0 && live) {
+        const int m = sm[al];
+        // listed: a valid atom whose windows meet the grid on every axis
+        const int t = (srec[al].type >= 0 && sn[0][al] > 0 && sn[1][al] > 0 && sn[2][al] > 0)
+                          ? srec[al].type : -1;
         // the channels the atom is listed under: its type, or with weighted
         // channels every channel with a non-zero weight
         for (int c = 0; c < p.C && t >= 0; ++c) {
@@ -119,10 +159,10 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_prep_kernel(GridParams p, Cryst
         }
     }
     __syncthreads();
-    for (int c = tid; c < p.C; c += PREP_BLOCK)
+    for (int c = tid; c < p.C; c += blockDim.x)
         q.bcount[(size_t)c * q.nblk + blockIdx.x] = cnt[c];
     if (local)
-        for (int i = tid; i < p.C * PREP_SPAN; i += PREP_BLOCK) {
+        for (int i = tid; i < p.C * PREP_SPAN; i += blockDim.x) {
             const int c = i / PREP_SPAN, j = i - c * PREP_SPAN;
             if (cntm[c][j] != 0u)
                 atomicAdd(&q.mcount[(size_t)c * p.n_mol + m_first + j], cntm[c][j]);
@@ -770,17 +810,14 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     if (p.n_mol == 0)
         return hipSuccess;
     const long long nmc = (long long)p.n_mol * p.C;
-    hipLaunchKernelGGL(cr_clear_kernel, dim3((unsigned)std::min<long long>((nmc + 255) / 256, 65535)),
-                       dim3(256), 0, s, q.mcount, nmc);
+    const unsigned clear_grid = (unsigned)std::min<long long>((nmc + q.op_blocks + 255) / 256, 65535);
+    hipLaunchKernelGGL(cr_clear2_kernel, dim3(clear_grid), dim3(256), 0, s, q.mcount, nmc, q.bmap,
+                       (long long)q.op_blocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const unsigned clear_grid_b = (unsigned)std::min<long long>((q.op_blocks + 255) / 256, 65535);
-    hipLaunchKernelGGL(cr_clear_kernel, dim3(clear_grid_b), dim3(256), 0, s, q.bmap, q.op_blocks);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
     if (p.n_atoms > 0) {
-        hipLaunchKernelGGL(cr_prep_kernel, dim3((unsigned)q.nblk), dim3(PREP_BLOCK), 0, s, p, q);
+        hipLaunchKernelGGL(cr_prep_kernel, dim3((unsigned)q.nblk), dim3(3 * PREP_BLOCK), 0, s, p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         hipLaunchKernelGGL(cr_scan_kernel, dim3(2), dim3(1024), 0, s, q, (long long)p.C * q.nblk,

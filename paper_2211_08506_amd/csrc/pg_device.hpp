@@ -378,37 +378,49 @@ __device__ __forceinline__ int structure_of(const int32_t *offsets, int n_mol, l
     return lo;
 }
 
-// Exact window ranges of atom a on the three axes (type -1: skipped atom,
-// which also raises the device error).  Returns the atom's structure.
-__device__ inline int write_atom_window(const GridParams &p, long long a, AtomWindow *w)
+// Exact window ranges of atom a on axis q into its record (axis 0 also
+// writes the type: -1 for a skipped atom, which also raises the device
+// error).  Returns the atom's structure; n_out = the axis's range count.
+__device__ inline int write_atom_axis(const GridParams &p, long long a, int q, AtomWindow *w,
+                                      int &n_out)
 {
     const float mu[3] = {p.xyz[3 * a], p.xyz[3 * a + 1], p.xyz[3 * a + 2]};
     const int t = p.types[a];
     const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.n_sig);
-    if (!ok)
+    if (!ok && q == 0)
         raise_error(p.err, PG_E_DEVICE_DATA, a);
     const int m = structure_of(p.offsets, p.n_mol, a);
-    w->type = ok ? t : -1;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        AxisRanges R;
-        R.n = 0;
-        if (ok) {
-            const float o = p.origins ? p.origins[3 * (size_t)m + q] : p.o[q];
-            const float h = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
-            const int N = q == 0 ? p.W : (q == 1 ? p.H : p.D);
-            axis_ranges(o, h, N, mu[q], p.periodic != 0, p.L[q], p.rc[t], p.cut != 0, R);
-        }
-        w->n[q] = R.n;
-#pragma unroll
-        for (int r = 0; r < MAX_IMAGES; ++r) {
-            const bool u = r < R.n;
-            w->lo[q][r] = u ? R.lo[r] : 0;
-            w->hi[q][r] = u ? R.hi[r] : -1;
-            w->bh[q][r] = u ? R.bh[r] : 0.f;
-            w->bl[q][r] = u ? R.bl[r] : 0.f;
-        }
+    if (q == 0)
+        w->type = ok ? t : -1;
+    AxisRanges R;
+    R.n = 0;
+    if (ok) {
+        const float o = p.origins ? p.origins[3 * (size_t)m + q] : p.o[q];
+        const float h = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
+        const int N = q == 0 ? p.W : (q == 1 ? p.H : p.D);
+        axis_ranges(o, h, N, mu[q], p.periodic != 0, p.L[q], p.rc[t], p.cut != 0, R);
     }
+    w->n[q] = R.n;
+#pragma unroll
+    for (int r = 0; r < MAX_IMAGES; ++r) {
+        const bool u = r < R.n;
+        w->lo[q][r] = u ? R.lo[r] : 0;
+        w->hi[q][r] = u ? R.hi[r] : -1;
+        w->bh[q][r] = u ? R.bh[r] : 0.f;
+        w->bl[q][r] = u ? R.bl[r] : 0.f;
+    }
+    n_out = R.n;
+    return m;
+}
+
+// Exact window ranges of atom a on the three axes.  Returns the atom's
+// structure.
+__device__ inline int write_atom_window(const GridParams &p, long long a, AtomWindow *w)
+{
+    int n, m = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        m = write_atom_axis(p, a, q, w, n);
     return m;
 }
 
