@@ -87,11 +87,14 @@ enum { PG_VALUE_POINT = 0, PG_VALUE_BOX = 1 };
    batch with each structure's atoms staged in LDS; larger structures take
    the binned path (atoms binned per (structure, channel, z plane), one
    workgroup per plane).  MFMA: binned path whose plane kernel evaluates
-   the separable factorisation (§III-A, §IV-C) of each plane as a BF16
-   matrix-core contraction over the plane's atoms (factors rounded to
-   bf16, float32 accumulation); meant for bf16 grids of large, dense
-   structures.  AUTO picks WINDOW when the structure fits, else MFMA for
-   bf16 and WINDOW (binned) for float32 output.  The binned path needs a
+   the separable factorisation (§III-A, §IV-C) of each plane as a
+   matrix-core contraction over the plane's atoms with float32
+   accumulation: for bf16 grids on factors rounded to bf16; for float32
+   grids on factors split into fp16 pairs (hi + lo, three products per
+   step), accurate to the FP32 bar (rel-L2 about 3e-6 against the FP64
+   definition, where the binned WINDOW form reaches about 1e-7); meant for
+   large, dense structures.  AUTO picks WINDOW when the structure fits,
+   else MFMA.  The binned path needs a
    workspace (pg_workspace_size) and does not take per-structure spacings;
    under MFMA, a plane holding more than 2048 z images of one channel
    (pg_plan_info.atom_capacity) is reported as PG_E_CAPACITY through
@@ -171,8 +174,8 @@ typedef struct pg_batch {
    types is independent of the channel count.  One-hot weights give the
    unweighted grid bit for bit.  Every form takes weights; the binned
    large-structure path lists each atom under every channel with a non-zero
-   weight (its workspace grows with C), and the MFMA form rounds the
-   weighted phi_y factor to bf16 once.  Not with triclinic cells
+   weight (its workspace grows with C); the MFMA form for bf16 grids rounds
+   the weighted phi_y factor to bf16 once.  Not with triclinic cells
    (PG_E_UNSUPPORTED). */
 
 typedef struct pg_ctx pg_ctx;

@@ -368,7 +368,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Binned path: workspace layout (window records | per-block channel counts
 // | per-structure channel counts | their scan | channel partition | z-sorted
 // images | per-run image counts | per-plane image ranges | operand block map
-// | bf16 operands (MFMA form)) and the plane kernel's LDS.
+// | operands (MFMA form: bf16, or float for fp32 grids)) and the plane
+// kernel's LDS.
 int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, int form, Plan &P)
 {
     if (b->spacings)
@@ -415,9 +416,12 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
     off += align256((size_t)P.op_blocks * 4);
     P.ws_xop = P.ws_yop = off;
     if (form == PG_FORM_MFMA) {
-        off += align256((size_t)P.op_blocks * d->W * 32 * 2);
+        // bf16 operands for bf16 grids; float operands (split into fp16
+        // pairs in the plane kernel) for fp32 grids
+        const size_t esz = d->out_dtype == PG_OUT_F32 ? 4 : 2;
+        off += align256((size_t)P.op_blocks * d->W * 32 * esz);
         P.ws_yop = off;
-        off += align256((size_t)P.op_blocks * d->H * 32 * 2);
+        off += align256((size_t)P.op_blocks * d->H * 32 * esz);
     }
     P.ws = off;
     const long long nb = nmc * d->D;
@@ -502,10 +506,10 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
         if (fits) {
             form = PG_FORM_WINDOW;
         } else {
-            // large structures: the MFMA contraction rounds its factors to
-            // bf16, so it serves bf16 grids; fp32 grids take the fp32
-            // vector form.  A measured choice (pg_autotune) overrides.
-            form = d->out_dtype == PG_OUT_BF16 ? PG_FORM_MFMA : PG_FORM_WINDOW;
+            // large structures: the MFMA contraction (bf16 factors for bf16
+            // grids, split fp16 factors at the FP32 bar for fp32 grids).  A
+            // measured choice (pg_autotune) overrides.
+            form = PG_FORM_MFMA;
             if (ctx) {
                 auto it = ctx->tuning.find(tuning_key(d, b, P.vec));
                 if (it != ctx->tuning.end() && it->second.form > 0)
@@ -1127,7 +1131,7 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
         return s;
     if (batch->n_mol == 0 || base.form == PG_FORM_PLAIN)
         return PG_OK;   // nothing tunable for this request
-    if (base.crystal && (desc->form != PG_FORM_AUTO || desc->out_dtype != PG_OUT_BF16))
+    if (base.crystal && desc->form != PG_FORM_AUTO)
         return PG_OK;   // a single admissible large-structure form
     if (reps < 1)
         reps = 1;
@@ -1159,7 +1163,7 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
         return e;
     };
     if (base.crystal) {
-        // bf16 grids of large structures: measure both admissible forms
+        // large structures: measure both binned forms
         int best_form = 0;
         double best_us = 1e30;
         int rc = PG_OK;

@@ -417,11 +417,19 @@ __device__ __forceinline__ uint16_t bf16_bits(float v)
     return __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
+// Operand element storage: bf16 bits (the bf16 contraction; the image's
+// weight folded into phi_y) or float (the split-fp16 contraction; the weight
+// is applied with phi_z in the plane kernel).
+__device__ __forceinline__ void op_store(uint16_t *p, float v) { *p = bf16_bits(v); }
+__device__ __forceinline__ void op_store(float *p, float v) { *p = v; }
+
 // One workgroup per operand block: phi_x and phi_y of its 32 images over
-// the whole x and y axes, as bf16, laid out [block][row][32 images] so that
-// a 16-byte load is one MFMA operand fragment.  The block is first cleared
-// with 16-byte stores; then 8 threads per image write the image's window
-// elements only (zeros elsewhere; images past the run's end stay zero).
+// the whole x and y axes, laid out [block][row][32 images] so that a
+// 16-byte load is one MFMA operand fragment (bf16) or one staging piece
+// (float).  The block is first cleared with 16-byte stores; then 8 threads
+// per image write the image's window elements only (zeros elsewhere;
+// images past the run's end stay zero).
+template <typename OT>
 __global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalParams q)
 {
     const long long gb = blockIdx.x;
@@ -434,12 +442,14 @@ __global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalPa
     const int tid = threadIdx.x, kl = tid & 31, rg = tid >> 5;
     const long long k = (gb - b0) * 32 + kl;
     const int W = p.W, H = p.H;
+    constexpr int CH = 32 * (int)sizeof(OT) / 16;   // 16-byte pieces per row
+    OT *xop = (OT *)q.xop, *yop = (OT *)q.yop;
     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-    u4 *xz = (u4 *)(q.xop + (size_t)gb * W * 32);
-    u4 *yz = (u4 *)(q.yop + (size_t)gb * H * 32);
-    for (int i = tid; i < W * 4; i += 256)
+    u4 *xz = (u4 *)(xop + (size_t)gb * W * 32);
+    u4 *yz = (u4 *)(yop + (size_t)gb * H * 32);
+    for (int i = tid; i < W * CH; i += 256)
         xz[i] = u4{0u, 0u, 0u, 0u};
-    for (int i = tid; i < H * 4; i += 256)
+    for (int i = tid; i < H * CH; i += 256)
         yz[i] = u4{0u, 0u, 0u, 0u};
     __threadfence_block();
     __syncthreads();
@@ -449,19 +459,19 @@ __global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalPa
     const AtomWindow &w = q.table[atom];
     const int ti = image_type(p, q, atom, c);
     const float inv2s2 = p.inv2s2[ti], isq2s = p.isq2s[ti];
-    const float wgt = image_weight(p, atom, c);   // folded into phi_y
+    const float wgt = sizeof(OT) == 2 ? image_weight(p, atom, c) : 1.f;
     const bool box = p.box != 0;
-    uint16_t *xo = q.xop + (size_t)gb * W * 32 + kl;
-    uint16_t *yo = q.yop + (size_t)gb * H * 32 + kl;
+    OT *xo = xop + (size_t)gb * W * 32 + kl;
+    OT *yo = yop + (size_t)gb * H * 32 + kl;
     for (int r = 0; r < w.n[0]; ++r) {
         const float bh = w.bh[0][r], bl = w.bl[0][r];
         for (int v = w.lo[0][r] + rg; v <= w.hi[0][r]; v += 8)
-            xo[(size_t)v * 32] = bf16_bits(factor1d(box, bh, bl, p.h[0], v, inv2s2, isq2s));
+            op_store(xo + (size_t)v * 32, factor1d(box, bh, bl, p.h[0], v, inv2s2, isq2s));
     }
     for (int r = 0; r < w.n[1]; ++r) {
         const float bh = w.bh[1][r], bl = w.bl[1][r];
         for (int v = w.lo[1][r] + rg; v <= w.hi[1][r]; v += 8)
-            yo[(size_t)v * 32] = bf16_bits(factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s) * wgt);
+            op_store(yo + (size_t)v * 32, factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s) * wgt);
     }
 }
 
@@ -473,53 +483,75 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // 2 x 2 MFMA tiles of 32 x 32.  The plane's images are the contiguous range
 // [first, end) of its run's z order, taken in whole 32-image operand blocks
 // (images of a block outside the plane get phi_z = 0).
-template <typename T>
+// The plane of this workgroup: its coordinates, its run's operand blocks
+// [kb0, kb0 + nkb) and phi_z of its images in gzs (with weighted channels
+// times the image's weight when fold_weight), ending with a barrier.
+struct PlaneItem {
+    int sx, sy, z, c, m, kb0, nkb;
+    long long rb;
+};
+
+__device__ __forceinline__ PlaneItem mfma_plane_begin(const GridParams &p, const CrystalParams &q,
+                                                      float *gzs, bool fold_weight)
+{
+    const int C = p.C, D = p.D, H = p.H, W = p.W;
+    const int nsx = (W + ST - 1) / ST, nsy = (H + ST - 1) / ST;
+    PlaneItem P;
+    long long b = xcd_block();
+    P.sx = (int)(b % nsx);
+    b /= nsx;
+    P.sy = (int)(b % nsy);
+    b /= nsy;
+    P.z = (int)(b % D);
+    b /= D;
+    P.c = (int)(b % C);
+    P.m = (int)(b / C);
+    const int tid = threadIdx.x;
+    const size_t mc = (size_t)P.c * p.n_mol + P.m;
+    const uint32_t first = q.prange[((size_t)mc * D + P.z) * 2];
+    const uint32_t end = q.prange[((size_t)mc * D + P.z) * 2 + 1];
+    const uint32_t n_img = q.ecount[mc];
+    P.kb0 = (int)(first / 32);
+    P.nkb = first < end ? (int)((end + 31) / 32) - P.kb0 : 0;
+    if (P.nkb * 32 > min(q.bin_cap, MFMA_BIN_CAP)) {
+        if (tid == 0 && P.sx == 0 && P.sy == 0)
+            raise_error(p.err, PG_E_CAPACITY, P.m);
+        P.nkb = 0;
+    }
+    P.rb = run_block(q, mc);
+    const float hz = p.h[2];
+    for (int i = tid; i < P.nkb * 32; i += blockDim.x) {
+        const uint32_t k = (uint32_t)P.kb0 * 32 + i;
+        float g = 0.f;
+        if (k < n_img) {
+            const ZEntry ze = q.zlist[32 * P.rb + k];
+            if (P.z >= range_lo(ze.range) && P.z <= range_hi(ze.range)) {
+                const int ti = image_type(p, q, ze.atom, P.c);
+                g = factor1d(p.box != 0, ze.bh, ze.bl, hz, P.z, p.inv2s2[ti], p.isq2s[ti]);
+                if (fold_weight)
+                    g *= image_weight(p, ze.atom, P.c);
+            }
+        }
+        gzs[i] = g;
+    }
+    __syncthreads();
+    return P;
+}
+
 __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParams q)
 {
+    using T = __bf16;
     __shared__ __attribute__((aligned(16))) float gzs[MFMA_BIN_CAP];   // phi_z per image
     // two staging buffers of [phi_z phi_y, phi_x][super-tile row][32 images],
     // rows padded to OPROW elements so that the fragment reads (lanes on
     // consecutive rows) fall in distinct banks
     __shared__ __attribute__((aligned(16))) __bf16 ops[2][2][ST * OPROW];
     const int C = p.C, D = p.D, H = p.H, W = p.W;
-    const int nsx = (W + ST - 1) / ST, nsy = (H + ST - 1) / ST;
-    long long b = xcd_block();
-    const int sx = (int)(b % nsx);
-    b /= nsx;
-    const int sy = (int)(b % nsy);
-    b /= nsy;
-    const int z = (int)(b % D);
-    b /= D;
-    const int c = (int)(b % C);
-    const int m = (int)(b / C);
-    const int y0 = sy * ST, x0 = sx * ST;
+    const PlaneItem PI = mfma_plane_begin(p, q, gzs, false);
+    const int z = PI.z, c = PI.c, m = PI.m, kb0 = PI.kb0, nkb = PI.nkb;
+    const long long rb = PI.rb;
+    const int y0 = PI.sy * ST, x0 = PI.sx * ST;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const size_t mc = (size_t)c * p.n_mol + m;
-    const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
-    const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
-    const uint32_t n_img = q.ecount[mc];
-    const int kb0 = (int)(first / 32);
-    int nkb = first < end ? (int)((end + 31) / 32) - kb0 : 0;
-    if (nkb * 32 > min(q.bin_cap, MFMA_BIN_CAP)) {
-        if (tid == 0 && sx == 0 && sy == 0)
-            raise_error(p.err, PG_E_CAPACITY, m);
-        nkb = 0;
-    }
-    const long long rb = run_block(q, mc);
-    const float hz = p.h[2];
-    for (int i = tid; i < nkb * 32; i += blockDim.x) {
-        const uint32_t k = (uint32_t)kb0 * 32 + i;
-        float g = 0.f;
-        if (k < n_img) {
-            const ZEntry ze = q.zlist[32 * rb + k];
-            if (z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
-                const int ti = image_type(p, q, ze.atom, c);
-                g = factor1d(p.box != 0, ze.bh, ze.bl, hz, z, p.inv2s2[ti], p.isq2s[ti]);
-            }
-        }
-        gzs[i] = g;
-    }
-    __syncthreads();
 
     f32x16 acc[2][2];
 #pragma unroll
@@ -629,6 +661,180 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
                 if (y < H && x < W) {
                     const float v[1] = {acc[i][j][e]};
                     store_vec<T, 1>(out + (size_t)y * W + x, v, p.nt_store != 0);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Split-fp16 MFMA form (fp32 grids at FP32 accuracy)
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+constexpr int SPROW = 24;             // staged row: 16 images + 8 halves of padding
+constexpr float SPLIT_UP = 4096.f;    // scale of the low parts (2^12)
+
+// v = hi + lo / 2^12 to about 2^-22 |v|: hi = fp16(v), lo = fp16((v - hi) 2^12)
+// (v - hi is exact in FP32; the scaled low part stays in the fp16 normal
+// range for every v the plane kernel splits).
+__device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
+{
+    hi = (_Float16)v;
+    lo = (_Float16)((v - (float)hi) * SPLIT_UP);
+}
+
+// One workgroup (4 waves) per (structure, channel, z, super-tile), as the
+// bf16 form, on FP32 operands (phi_x, and phi_y without the weight).  Per
+// 16-image step the workgroup stages A = s phi_z w phi_y and B = phi_x in
+// LDS, each split as hi + lo / 2^12 into fp16 pairs; s = 2^e is chosen per
+// plane from the largest |phi_z w| so that every A stays within the fp16
+// range.  Each 32 x 32 tile takes three v_mfma_f32_32x32x16_f16 per step:
+// P += Ahi Bhi, Q += Ahi Blo + Alo Bhi; the plane is (P + Q / 2^12) / s.  The
+// dropped Alo Blo and the splits leave about 2^-21 relative error per
+// product, against 2^-8 for the bf16 operands.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) cr_mfma_split_kernel(GridParams p, CrystalParams q)
+{
+    __shared__ __attribute__((aligned(16))) float gzs[MFMA_BIN_CAP];   // phi_z w per image
+    __shared__ float wmax[4];
+    // two staging buffers of [Ahi, Alo, Bhi, Blo][super-tile row][16 images]
+    __shared__ __attribute__((aligned(16))) _Float16 sops[2][4][ST * SPROW];
+    const int H = p.H, W = p.W, C = p.C, D = p.D;
+    const PlaneItem PI = mfma_plane_begin(p, q, gzs, true);
+    const int z = PI.z, c = PI.c, m = PI.m, kb0 = PI.kb0;
+    const long long rb = PI.rb;
+    const int nst = 2 * PI.nkb;   // 16-image steps
+    const int y0 = PI.sy * ST, x0 = PI.sx * ST;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // plane scale: s = 2^(14 - e) for the largest |phi_z w| = f 2^e, f in [0.5, 1)
+    float mx = 0.f;
+    for (int i = tid; i < nst * 16; i += blockDim.x)
+        mx = fmaxf(mx, fabsf(gzs[i]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (lane == 0)
+        wmax[wave] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    int ex = 0;
+    if (mx > 0.f)
+        (void)frexpf(mx, &ex);
+    const float sc = ldexpf(1.f, 14 - ex), unsc = ldexpf(1.f, ex - 14);
+
+    f32x16 accp[2][2], accq[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                accp[i][j][e] = 0.f;
+                accq[i][j][e] = 0.f;
+            }
+    const int qy = (wave >> 1) * 64, qx = (wave & 1) * 64;
+    const int ko = 8 * (lane >> 5);
+    const float *yop = (const float *)q.yop, *xop = (const float *)q.xop;
+    // staging: thread t moves images 4 (t % 4) .. + 3 of the step for local
+    // rows t / 4 and t / 4 + 64 of both operands; rows past the plane edge
+    // copy the last row (they only feed outputs that are never stored)
+    const int srow = tid >> 2, skq = 4 * (tid & 3);
+    int sy_[2], sx_[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        sy_[r] = min(y0 + srow + 64 * r, H - 1);
+        sx_[r] = min(x0 + srow + 64 * r, W - 1);
+    }
+    float4 ga[2][2], gb[2][2];
+    auto fetch = [&](int st, float4 (&fa)[2], float4 (&fb)[2]) {
+        const size_t blk = (size_t)(rb + kb0 + (st >> 1));
+        const int off = 16 * (st & 1) + skq;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            fa[r] = *(const float4 *)(yop + (blk * H + sy_[r]) * 32 + off);
+            fb[r] = *(const float4 *)(xop + (blk * W + sx_[r]) * 32 + off);
+        }
+    };
+    auto stage = [&](int st, int buf, const float4 (&fa)[2], const float4 (&fb)[2]) {
+        const float4 g4 = *(const float4 *)(gzs + st * 16 + skq);
+        const float g[4] = {g4.x * sc, g4.y * sc, g4.z * sc, g4.w * sc};
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const float av[4] = {fa[r].x * g[0], fa[r].y * g[1], fa[r].z * g[2], fa[r].w * g[3]};
+            const float bv[4] = {fb[r].x, fb[r].y, fb[r].z, fb[r].w};
+            f16x4 ah, al, bh, bl;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                _Float16 h, l;
+                split16(av[e], h, l);
+                ah[e] = h;
+                al[e] = l;
+                split16(bv[e], h, l);
+                bh[e] = h;
+                bl[e] = l;
+            }
+            const int o = (srow + 64 * r) * SPROW + skq;
+            *(f16x4 *)(sops[buf][0] + o) = ah;
+            *(f16x4 *)(sops[buf][1] + o) = al;
+            *(f16x4 *)(sops[buf][2] + o) = bh;
+            *(f16x4 *)(sops[buf][3] + o) = bl;
+        }
+    };
+    auto contract = [&](int buf) {
+        f16x8 ahf[2], alf[2], bhf[2], blf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int ra = (qy + 32 * i + (lane & 31)) * SPROW + ko;
+            const int rbx = (qx + 32 * i + (lane & 31)) * SPROW + ko;
+            ahf[i] = *(const f16x8 *)(sops[buf][0] + ra);
+            alf[i] = *(const f16x8 *)(sops[buf][1] + ra);
+            bhf[i] = *(const f16x8 *)(sops[buf][2] + rbx);
+            blf[i] = *(const f16x8 *)(sops[buf][3] + rbx);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                accp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahf[i], bhf[j], accp[i][j], 0, 0, 0);
+                accq[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahf[i], blf[j], accq[i][j], 0, 0, 0);
+                accq[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alf[i], bhf[j], accq[i][j], 0, 0, 0);
+            }
+    };
+    // as the bf16 form: fetch step st + 2 (clamped), contract st, stage
+    // st + 1 into the other buffer, barrier
+    auto step = [&](int st, float4 (&fa_next)[2], float4 (&fb_next)[2],
+                    const float4 (&fa_stage)[2], const float4 (&fb_stage)[2]) {
+        fetch(min(st + 2, nst - 1), fa_next, fb_next);
+        contract(st & 1);
+        if (st + 1 < nst)
+            stage(st + 1, (st + 1) & 1, fa_stage, fb_stage);
+        __syncthreads();
+    };
+    if (nst > 0) {
+        fetch(0, ga[0], gb[0]);
+        fetch(min(1, nst - 1), ga[1], gb[1]);
+        stage(0, 0, ga[0], gb[0]);
+    }
+    __syncthreads();
+    int st = 0;
+    for (; st + 1 < nst; st += 2) {
+        step(st, ga[0], gb[0], ga[1], gb[1]);
+        step(st + 1, ga[1], gb[1], ga[0], gb[0]);
+    }
+    if (st < nst)
+        step(st, ga[0], gb[0], ga[1], gb[1]);
+
+    float *out = (float *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int y = y0 + qy + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                const int x = x0 + qx + 32 * j + (lane & 31);
+                if (y < H && x < W) {
+                    const float v[1] = {(accp[i][j][e] + accq[i][j][e] * (1.f / SPLIT_UP)) * unsc};
+                    store_vec<float, 1>(out + (size_t)y * W + x, v, p.nt_store != 0);
                 }
             }
 }
@@ -846,15 +1052,19 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     if (form == PG_FORM_MFMA) {
-        hipLaunchKernelGGL(cr_operand_kernel, dim3((unsigned)q.op_blocks), dim3(256), 0, s, p, q);
+        if (out_dtype == PG_OUT_F32)
+            hipLaunchKernelGGL(cr_operand_kernel<float>, dim3((unsigned)q.op_blocks), dim3(256), 0, s, p, q);
+        else
+            hipLaunchKernelGGL(cr_operand_kernel<uint16_t>, dim3((unsigned)q.op_blocks), dim3(256), 0, s,
+                               p, q);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
     const void *k;
     long long grid;
     if (form == PG_FORM_MFMA) {
-        k = out_dtype == PG_OUT_F32 ? (const void *)cr_mfma_kernel<float>
-                                    : (const void *)cr_mfma_kernel<__bf16>;
+        k = out_dtype == PG_OUT_F32 ? (const void *)cr_mfma_split_kernel
+                                    : (const void *)cr_mfma_kernel;
         grid = nmc * p.D * ((p.H + ST - 1) / ST) * ((p.W + ST - 1) / ST);
     } else {
         const int r = crystal_window_runs(p.H, p.W);

@@ -149,12 +149,20 @@ def test_workspace_and_plan_host_only():
     for form, dtype in (("window", "f32"), ("mfma", "bf16"), ("auto", "bf16"), ("auto", "f32")):
         d = desc_ok(form=form, out_dtype=dtype)
         assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000, ctypes.byref(info)) == 0
-        want = "mfma" if (form == "mfma" or (form == "auto" and dtype == "bf16")) else "window"
+        want = "mfma" if form in ("mfma", "auto") else "window"
         assert info.form == pg.FORMS[want] and info.binned == 1
         assert info.atom_capacity == (2048 if want == "mfma" else 0)   # 0: no limit
         assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(big), ctypes.byref(n)) == 0
         # per-atom records + 3 counters per (structure, channel, z plane) + bin lists
         assert n.value >= 4000 * 160 + 3 * 4 * 5 * 32 * 4 and n.value % 256 == 0
+    # the MFMA form keeps float operands for float32 grids (split into fp16
+    # pairs on the fly) and bf16 operands for bf16 grids
+    ws = {}
+    for dtype in ("bf16", "f32"):
+        d = desc_ok(form="mfma", out_dtype=dtype)
+        assert lib.pg_workspace_size(None, ctypes.byref(d), ctypes.byref(big), ctypes.byref(n)) == 0
+        ws[dtype] = n.value
+    assert ws["f32"] > ws["bf16"] + (4000 * 3 // 32) * (32 + 32) * 32 * 2
     # per-structure spacings are not supported on the large-structure path
     big.spacings = 0x2000
     assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(big), 0x10000,

@@ -110,7 +110,7 @@ def test_box_binned_path(pg, dev):
     ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, dims, h, (0, 0, 0), cell=8.0,
                            value="box")
     for form, dt, tol in [("window", torch.float32, F32_TOL), ("window", torch.bfloat16, BF16_TOL),
-                          ("mfma", torch.bfloat16, BF16_TOL), ("mfma", torch.float32, BF16_TOL)]:
+                          ("mfma", torch.bfloat16, BF16_TOL), ("mfma", torch.float32, F32_TOL)]:
         say(f"case box binned form={form} dtype={dt}")
         g = run(pg, dev, b, sig, dims, h, (0, 0, 0), dt, form, cell=8.0)
         check(f"cells/{form}/{dt}", g, ref, tol)

@@ -86,7 +86,8 @@ def test_large_cells_binned_forms(pg, dev):
     b = cells(62, [300, 180], SHEAR, 3)
     dims, h, o = (40, 44, 48), 0.21, (0.0, -0.3, 0.2)
     ref = triclinic.grid_triclinic_fp64(b.xyz, b.types, b.offsets, sig, dims, h, SHEAR, o)
-    for form, dt, tol in (("window", torch.float32, F32_TOL), ("mfma", torch.bfloat16, BF16_TOL)):
+    for form, dt, tol in (("window", torch.float32, F32_TOL), ("mfma", torch.bfloat16, BF16_TOL),
+                          ("mfma", torch.float32, F32_TOL)):
         say(f"case triclinic large cells form={form}")
         check(f"large/{form}", run(pg, dev, b, sig, dims, h, o, SHEAR, dt, form), ref, tol)
 

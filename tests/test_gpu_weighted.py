@@ -158,7 +158,8 @@ def test_weighted_full_size_sampled(pg, dev):
 
 
 @pytest.mark.parametrize("form,dtype,tol", [("window", torch.float32, F32_TOL),
-                                            ("mfma", torch.bfloat16, BF16_TOL)])
+                                            ("mfma", torch.bfloat16, BF16_TOL),
+                                            ("mfma", torch.float32, F32_TOL)])
 def test_weighted_binned_path(pg, dev, form, dtype, tol):
     """Periodic cells above the window kernel's capacity, 6 types into 3
     channels with signed weights (some exactly zero): the binned path lists
