@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(3 * PREP_BLOCK) cr_prep_kernel(GridParams p, C
 
 // Exclusive scan of n counts, in place (workgroup 0: the per-block counts)
 // or into mstart (workgroup 1: the per-structure counts).  One workgroup
-// of 1024 threads per array, each thread owning a contiguous segment.
+// of 1024 threads per array.
 __global__ void __launch_bounds__(1024) cr_scan_kernel(CrystalParams q, long long n_blk,
                                                        long long n_mol)
 {
@@ -179,26 +179,7 @@ __global__ void __launch_bounds__(1024) cr_scan_kernel(CrystalParams q, long lon
     const uint32_t *in = blockIdx.x == 0 ? q.bcount : q.mcount;
     uint32_t *out = blockIdx.x == 0 ? q.bcount : q.mstart;
     const long long n = blockIdx.x == 0 ? n_blk : n_mol;
-    const int t = threadIdx.x;
-    const long long seg = (n + 1023) / 1024;
-    const long long b = (long long)t * seg, e = min(n, b + seg);
-    unsigned long long s = 0;
-    for (long long i = b; i < e; ++i)
-        s += in[i];
-    part[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const unsigned long long v = t >= d ? part[t - d] : 0ull;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    unsigned long long run = part[t] - s;
-    for (long long i = b; i < e; ++i) {
-        const uint32_t v = in[i];
-        out[i] = (uint32_t)run;
-        run += v;
-    }
+    (void)workgroup_exclusive_scan(in, out, n, part);
 }
 
 __device__ __forceinline__ uint32_t pack_range(int lo, int hi)

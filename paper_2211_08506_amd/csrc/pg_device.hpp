@@ -338,6 +338,64 @@ __device__ __forceinline__ float load_as_float<__bf16>(const __bf16 *p)
 }
 
 // ---------------------------------------------------------------------------
+// One-workgroup exclusive scan
+// ---------------------------------------------------------------------------
+// out[i] = in[0] + ... + in[i - 1] for the n 32-bit counts in[0..n) (out may
+// be in; both 16-byte aligned), by one workgroup of 1024 threads with a
+// 1024-entry LDS array part; returns the total to every thread.  Each
+// thread owns a contiguous segment whose length is a multiple of 4, read
+// and written in 16-byte pieces, so its loads are independent and stay in
+// flight together instead of one dependent round trip per count.
+__device__ inline unsigned long long workgroup_exclusive_scan(const uint32_t *in, uint32_t *out,
+                                                              long long n,
+                                                              unsigned long long *part)
+{
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const int t = threadIdx.x;
+    const long long seg = (((n + 1023) / 1024) + 3) & ~3ll;
+    const long long b = min(n, (long long)t * seg), e = min(n, b + seg);
+    const long long e4 = b + ((e - b) & ~3ll);
+    unsigned long long s = 0;
+#pragma unroll 4
+    for (long long i = b; i < e4; i += 4) {
+        const u4 v = *(const u4 *)(in + i);
+        s += (unsigned long long)v.x + v.y + v.z + v.w;
+    }
+    for (long long i = e4; i < e; ++i)
+        s += in[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const unsigned long long v = t >= d ? part[t - d] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long total = part[1023];
+    unsigned long long run = part[t] - s;
+#pragma unroll 4
+    for (long long i = b; i < e4; i += 4) {
+        const u4 v = *(const u4 *)(in + i);
+        u4 o;
+        o.x = (uint32_t)run;
+        run += v.x;
+        o.y = (uint32_t)run;
+        run += v.y;
+        o.z = (uint32_t)run;
+        run += v.z;
+        o.w = (uint32_t)run;
+        run += v.w;
+        *(u4 *)(out + i) = o;
+    }
+    for (long long i = e4; i < e; ++i) {
+        const uint32_t v = in[i];
+        out[i] = (uint32_t)run;
+        run += v;
+    }
+    return total;
+}
+
+// ---------------------------------------------------------------------------
 // Sticky device error word
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void raise_error(DeviceError *err, int code, long long index)

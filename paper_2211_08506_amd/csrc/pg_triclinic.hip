@@ -101,33 +101,16 @@ __global__ void __launch_bounds__(256) tri_count_kernel(TriParams q, DeviceError
 // exp_offsets[m] = istart[offsets[m]]
 __global__ void __launch_bounds__(1024) tri_scan_kernel(TriParams q, DeviceError *err)
 {
-    __shared__ long long part[1024];
+    __shared__ unsigned long long part[1024];
     const int t = threadIdx.x;
     const long long n = q.n_atoms;
-    const long long seg = (n + 1023) / 1024;
-    const long long b = (long long)t * seg, e = min(n, b + seg);
-    long long s = 0;
-    for (long long i = b; i < e; ++i)
-        s += q.istart[i];
-    part[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const long long v = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    long long run = part[t] - s;   // exclusive start of this segment
-    for (long long i = b; i < e; ++i) {
-        const int c = q.istart[i];
-        q.istart[i] = (int32_t)run;
-        run += c;
-    }
+    const unsigned long long total =
+        workgroup_exclusive_scan((const uint32_t *)q.istart, (uint32_t *)q.istart, n, part);
     if (t == 1023) {
-        q.istart[n] = (int32_t)part[1023];
+        q.istart[n] = (int32_t)total;
         // more kept images than the host bound (not expected: the bound is
         // the most lattice translates the widened box holds): report it
-        if (part[1023] > q.bound)
+        if (total > (unsigned long long)q.bound)
             raise_error(err, PG_E_CAPACITY, 0);
     }
     __syncthreads();
