@@ -24,6 +24,8 @@
 
 namespace pg {
 
+constexpr int ADJ_UNROLL = 4;   // window elements per lane whose loads are in flight together
+
 __device__ __forceinline__ float wave_sum(float v)
 {
 #pragma unroll
@@ -53,17 +55,17 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     float mu[3] = {0.f, 0.f, 0.f};
     int t = -1, m = 0;
     float o[3] = {0.f, 0.f, 0.f}, h[3] = {1.f, 1.f, 1.f};
-    if (active) {
+    if (active) {   // uniform across the wave
         mu[0] = p.xyz[3 * a];
         mu[1] = p.xyz[3 * a + 1];
         mu[2] = p.xyz[3 * a + 2];
         t = p.types[a];
+        m = structure_of_wave(p.offsets, p.n_mol, a);
         if (!atom_valid(mu[0], mu[1], mu[2], t, p.n_sig)) {
             if (lane == 0)
                 raise_error(p.err, PG_E_DEVICE_DATA, a);
             t = -1;
         } else {
-            m = structure_of(p.offsets, p.n_mol, a);
             for (int q = 0; q < 3; ++q) {
                 o[q] = p.origins ? p.origins[3 * m + q] : p.o[q];
                 h[q] = p.spacings ? p.spacings[3 * m + q] : p.h[q];
@@ -121,22 +123,45 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                 continue;
             const T *U = (const T *)p.out + ((size_t)m * p.C + c) * (size_t)p.D * plane;
             float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
-            for (int e = lane; e < total; e += 64) {
-                const int kx = e % nx;
-                const int r = e / nx;
-                const int ky = r % ny;
-                const int kz = r / ny;
-                const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
-                if (p.sphere && !(dsq[kx] <= (p.rc2[t] - dsq[base[2] + kz]) - dsq[base[1] + ky]))
-                    continue;
-                const float u = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
-                const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
-                const float dx = dphi[kx], dy = dphi[base[1] + ky], dz = dphi[base[2] + kz];
-                sx = __builtin_fmaf(u, dx * (fy * fz), sx);
-                sy = __builtin_fmaf(u, fx * (dy * fz), sy);
-                sz = __builtin_fmaf(u, (fx * fy) * dz, sz);
-                if (want_gw)
-                    sw = __builtin_fmaf(u, (fx * fy) * fz, sw);
+            // ADJ_UNROLL window elements per lane per round: their upstream
+            // loads are issued together, then consumed in element order
+            for (int e0 = 0; e0 < total; e0 += 64 * ADJ_UNROLL) {
+                float u[ADJ_UNROLL];
+                int ke[ADJ_UNROLL][3];
+#pragma unroll
+                for (int j = 0; j < ADJ_UNROLL; ++j) {
+                    const int e = e0 + 64 * j + lane;
+                    const int kx = e % nx;
+                    const int r = e / nx;
+                    const int ky = r % ny;
+                    const int kz = r / ny;
+                    ke[j][0] = kx;
+                    ke[j][1] = ky;
+                    ke[j][2] = kz;
+                    bool in = e < total;
+                    if (in && p.sphere)
+                        in = dsq[kx] <= (p.rc2[t] - dsq[base[2] + kz]) - dsq[base[1] + ky];
+                    u[j] = 0.f;
+                    if (in) {
+                        const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
+                        u[j] = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
+                    } else {
+                        ke[j][0] = -1;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < ADJ_UNROLL; ++j) {
+                    if (ke[j][0] < 0)
+                        continue;
+                    const int kx = ke[j][0], ky = ke[j][1], kz = ke[j][2];
+                    const float fx = phi[kx], fy = phi[base[1] + ky], fz = phi[base[2] + kz];
+                    const float dx = dphi[kx], dy = dphi[base[1] + ky], dz = dphi[base[2] + kz];
+                    sx = __builtin_fmaf(u[j], dx * (fy * fz), sx);
+                    sy = __builtin_fmaf(u[j], fx * (dy * fz), sy);
+                    sz = __builtin_fmaf(u[j], (fx * fy) * dz, sz);
+                    if (want_gw)
+                        sw = __builtin_fmaf(u[j], (fx * fy) * fz, sw);
+                }
             }
             if (want_gw) {
                 sw = wave_sum(sw);

@@ -436,6 +436,26 @@ __device__ __forceinline__ int structure_of(const int32_t *offsets, int n_mol, l
     return lo;
 }
 
+// structure_of for an atom index a that is uniform across the calling wave:
+// each round the 64 lanes probe 63 evenly spaced offsets of the bracket at
+// once, so a batch of n structures takes ceil(log64 n) dependent loads
+// instead of log2 n.  Every lane of the wave must call it.
+__device__ __forceinline__ int structure_of_wave(const int32_t *offsets, int n_mol, long long a)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n_mol;   // invariant: offsets[lo] <= a < offsets[hi]
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int q = lo + lane * step;
+        const bool le = lane > 0 && q < hi && (long long)offsets[q] <= a;
+        // offsets are non-decreasing: the probes at or below a form a prefix
+        const int below = __popcll(__ballot(le));
+        lo += below * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
 // Exact window ranges of atom a on axis q into its record (axis 0 also
 // writes the type: -1 for a skipped atom, which also raises the device
 // error).  Returns the atom's structure; n_out = the axis's range count.
