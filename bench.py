@@ -341,31 +341,48 @@ def main():
         plan = ctx.plan(desc, bvp, residual)
         loss0 = None
 
+        # the step keeps no residual grid where the library allows it (the
+        # molecule window form): the adjoint forms the residual in the windows
+        keep = not (plan["form"] == "window" and not plan["binned"] and E is None)
+        res_arg = residual if keep else None
+
         def step():
-            ctx.reversal_step(desc, bvp, target, residual, loss, None, bvp.xyz, lr, stream)
+            ctx.reversal_step(desc, bvp, target, res_arg, loss, None, bvp.xyz, lr, stream)
 
         step()
         torch.cuda.synchronize()
         loss0 = float(loss.sum().item())
         wall, ev = timed_steps(step, args.steps, args.warmup, torch, stream)
         loss1 = float(loss.sum().item())
-        # algorithmic bytes: the target read and the residual written once,
-        # the residual re-read inside every window by the adjoint, the
-        # inputs, and the coordinates read and written
-        alg = 8 * B * vox + evals * 4 + in_bytes + 24 * b.n_atoms
+        # algorithmic bytes: the target read once (and the residual written
+        # once when kept), the target (or residual) re-read inside every
+        # window by the adjoint, the inputs, and the coordinates read and
+        # written
+        alg = (8 if keep else 4) * B * vox + evals * 4 + in_bytes + 24 * b.n_atoms
         achieved = alg / (ev["mean"] / 1e3) / 1e9
+        if not keep:
+            # the same step with the residual grid written, for comparison
+            def step_res():
+                ctx.reversal_step(desc, bvp, target, residual, loss, None, bvp.xyz, lr, stream)
+            w2, e2 = timed_steps(step_res, max(5, args.steps // 2), 2, torch, stream)
+            extra["with_residual_grid"] = {"ms_per_step": w2, "launch_ms": e2,
+                                           "grids_per_s": B / (w2 / 1e3)}
+            log(f"[bench]   with the residual grid written: {w2:.3f} ms/step wall, "
+                f"{e2['mean']:.3f} ms (events)")
         log(f"[bench] reversal step: plan {plan}")
         log(f"[bench]   {wall:.3f} ms/step wall, {ev['mean']:.3f} ms (events), "
             f"{B / (wall / 1e3) / 1e6:.3f} M grids/s, {achieved:.0f} GB/s algorithmic; "
             f"loss {loss0:.4e} -> {loss1:.4e} over {args.steps + args.warmup + 1} steps")
         kname = (f"whole step: window_mol_kernel<float,{plan['vec']},{plan['unroll']},residual>"
-                 " + adjoint_kernel<float> (update)")
+                 + (" + adjoint_kernel<float> (update)" if keep else
+                    " (no residual grid) + adjoint_kernel<float, recompute> (update)"))
         rec.update({"value": B / (wall / 1e3), "ms_per_step": wall, "dtype": "f32",
                     "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                                  "traffic": None, "kernel": kname,
                                  "algorithmic_bytes_per_launch": alg, "launch_ms": ev},
-                    "loss_first_step": loss0, "loss_last_step": loss1})
+                    "loss_first_step": loss0, "loss_last_step": loss1,
+                    "residual_grid_kept": keep})
         kind = "reversal step"
         Th = None if args.no_cpu else target.cpu().numpy()   # the CPU leg's targets
     else:

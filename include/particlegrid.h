@@ -339,6 +339,12 @@ int pg_reversal_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc,
    forward kernel forms the residual and the loss as it goes (G' is never
    stored; per-lane FP32 partial sums, FP64 across a workgroup); other forms
    store G' in residual and then form both in one pass (FP64 partial sums).
+   residual may be NULL on the molecule window form without weights: no
+   residual grid is written (half the HBM traffic of the step) and the
+   adjoint forms 2 (G' - T) at each voxel of an atom's window, summing G'
+   over the structure's atoms of that channel as the forward does, so loss,
+   grad_xyz and xyz_update are bit-identical to a step with a residual
+   buffer; elsewhere a NULL residual is PG_E_NULL.
    The loss is deterministic for a given launch configuration.  Under
    PG_OPT_GRAPH the whole step is captured once per argument set and
    replayed.  ws: pg_reversal_workspace_size() bytes.

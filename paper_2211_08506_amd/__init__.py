@@ -364,14 +364,18 @@ class Context:
         return int(n.value)
 
     def reversal_step(self, desc: GridDesc, batch: BatchView, target: torch.Tensor,
-                      residual: torch.Tensor, loss: torch.Tensor,
+                      residual: Optional[torch.Tensor], loss: torch.Tensor,
                       grad_xyz: Optional[torch.Tensor] = None,
                       xyz_update: Optional[torch.Tensor] = None, lr: float = 0.0,
                       stream: Optional[torch.cuda.Stream] = None):
         """One grid-reversal step (pg_reversal_step): residual = 2 (G' - T),
         loss per structure, and optionally the gradient and xyz - lr * grad
-        (xyz_update may be batch.xyz for an in-place step)."""
+        (xyz_update may be batch.xyz for an in-place step).  residual may be
+        None on the molecule window form without weights: no residual grid
+        is stored and the adjoint forms it where it reads it."""
         for name, t in (("target", target), ("residual", residual), ("loss", loss)):
+            if t is None and name == "residual":
+                continue
             if t.dtype != torch.float32 or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous float32 tensor")
         nbytes = self.reversal_workspace_size(desc, batch)
@@ -486,7 +490,11 @@ def reverse(target: torch.Tensor, sigma: Sequence[float], *, spacing=0.5,
     xyz, types, offsets = pgctx.find_peaks(desc, target, threshold)
     xyz = xyz.clone()
     batch = BatchView(xyz, types, offsets)
-    residual = torch.empty_like(target)
+    # the molecule window form keeps no residual grid; the binned path
+    # needs one
+    plan = pgctx.plan(desc, batch)
+    residual = None if (plan["form"] == "window" and not plan["binned"]) else \
+        torch.empty_like(target)
     loss = torch.empty(B, dtype=torch.float32, device=target.device)
     for k in range(steps):
         pgctx.reversal_step(desc, batch, target, residual, loss, None, batch.xyz, lr)

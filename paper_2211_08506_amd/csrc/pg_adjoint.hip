@@ -12,6 +12,13 @@
 // (sqrt(2 pi) sigma).  The cutoff edge contributes nothing (the map is
 // differentiable almost everywhere).
 //
+// In a grid-reversal step that keeps no residual grid, the upstream value
+// 2 (G'(v) - T(v)) is formed at each window voxel: G'(v) is summed over the
+// structure's atoms of the same channel exactly as the window kernel sums
+// it (index order, the same factors and fused multiply-adds, the same
+// sphere test), so the gradient is bit-identical to the one read from a
+// stored residual.
+//
 // One wave per atom, any structure size: the wave builds its atom's 1-D
 // factor and offset lists over the window (per-wave LDS), then its lanes
 // sweep the window with x fastest -- lanes of one window row read
@@ -34,7 +41,44 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-template <typename T>
+// Per-wave LDS bytes of the adjoint: the atom's lists over the NT = W + H + D
+// indices and its ranges, plus, when recomputing the residual, for up to
+// a_cap same-channel atoms their index, flags, order and factor rows (and
+// squared offsets for the sphere) over this atom's window lists of at most
+// ntw indices.
+__host__ __device__ inline size_t adjoint_wave_lds(int NT, int a_cap, int ntw, bool sphere)
+{
+    return (size_t)NT * 16 + 3 * sizeof(AxisRanges) +
+           (size_t)a_cap * (3 * sizeof(int) + (size_t)ntw * sizeof(float) * (sphere ? 2 : 1));
+}
+
+// G'(v) of the atom's channel at window element (kx, ky, kz): the window
+// kernel's sum over the same-channel atoms in index order,
+// acc = fma(phi_y phi_z, phi_x, acc), from their factor rows over this
+// atom's window lists (0 outside an atom's window, where the window kernel
+// adds an exact zero), keeping under the sphere cutoff phi_x only where
+// dx^2 <= (rc^2 - dz^2) - dy^2.
+__device__ __forceinline__ float recompute_density(const float *srow, const float *sd2,
+                                                   const int *rel, int nrel, int ntw, int by,
+                                                   int bz, int kx, int ky, int kz, bool sph,
+                                                   float rc2)
+{
+    float acc = 0.f;
+    for (int r = 0; r < nrel; ++r) {
+        const int o = rel[r] * ntw;
+        const float fz = srow[o + bz + kz];
+        const float fy = srow[o + by + ky];
+        const float fx = srow[o + kx];
+        if (fz == 0.f || fy == 0.f || fx == 0.f)
+            continue;
+        if (sph && !(sd2[o + kx] <= (rc2 - sd2[o + bz + kz]) - sd2[o + by + ky]))
+            continue;
+        acc = __builtin_fmaf(fy * fz, fx, acc);
+    }
+    return acc;
+}
+
+template <typename T, bool RECOMP>
 __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -43,12 +87,23 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     const long long a = (long long)blockIdx.x * waves + wave;
     const bool active = a < live_atoms(p);
     const int NT = p.W + p.H + p.D;
-    // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | dsq[NT] | 3 range records
-    int *idx = (int *)(smem + (size_t)wave * (NT * 16 + 3 * sizeof(AxisRanges)));
+    // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | dsq[NT] | 3 range
+    // records | recompute: same[a_cap] | flags[a_cap] | rel[a_cap] |
+    // rows[a_cap][ntw] | (sphere) squared offsets[a_cap][ntw]
+    constexpr bool recomp = RECOMP;
+    const int rcap = recomp ? p.a_cap : 0, ntw = recomp ? p.rec_ntw : 0;
+    unsigned char *slice =
+        smem + (size_t)wave * adjoint_wave_lds(p.W + p.H + p.D, rcap, ntw, p.sphere != 0);
+    int *idx = (int *)slice;
     float *phi = (float *)(idx + NT);
     float *dphi = phi + NT;
     float *dsq = dphi + NT;      // sphere cutoff: squared centre offsets
     AxisRanges *rg = (AxisRanges *)(dsq + NT);
+    int *same = (int *)(rg + 3);
+    int *sflag = same + rcap;
+    int *rel = sflag + rcap;
+    float *srow = (float *)(rel + rcap);
+    float *sd2 = srow + (size_t)rcap * ntw;
     const int base[3] = {0, p.W, p.W + p.H};
     const int N[3] = {p.W, p.H, p.D};   // indexed by the compile-time axis only
 
@@ -107,6 +162,83 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
         }
     }
     __syncthreads();
+    // recompute: the structure's valid atoms of channel t in index order;
+    // their factor rows over this atom's window lists; the atoms whose rows
+    // are non-zero on all three axes, in index order
+    int nsame = 0, nrel = 0;
+    const int wtot = n[0] + n[1] + n[2];
+    const bool rec_ok = recomp && t >= 0 && wtot <= ntw;
+    if (recomp && t >= 0 && wtot > ntw && lane == 0)
+        raise_error(p.err, PG_E_CAPACITY, a);   // not expected: the host bounds every window
+    if (rec_ok) {
+        const long long s0 = p.offsets[m], s1 = p.offsets[m + 1];
+        for (long long k0 = s0; k0 < s1; k0 += 64) {
+            const long long k = k0 + lane;
+            bool hit = false;
+            if (k < s1) {
+                const int tk = p.types[k];
+                hit = tk == t && atom_valid(p.xyz[3 * k], p.xyz[3 * k + 1], p.xyz[3 * k + 2], tk,
+                                            p.n_sig);
+            }
+            const unsigned long long bal = __ballot(hit);
+            const int rank = nsame + __popcll(bal & ((1ull << lane) - 1ull));
+            if (hit && rank < rcap) {
+                same[rank] = (int)k;
+                sflag[rank] = 0;
+            }
+            nsame += __popcll(bal);
+        }
+        nsame = min(nsame, rcap);   // the window plan holds every atom of a structure
+    }
+    __syncthreads();
+    if (rec_ok) {
+        const bool box = p.box != 0, sph = p.sphere != 0;
+        for (int j = lane; j < 3 * nsame; j += 64) {
+            const int s = j / 3, q = j - 3 * (j / 3), k = same[s];
+            const float oq = q == 0 ? o[0] : (q == 1 ? o[1] : o[2]);
+            const float hq = q == 0 ? h[0] : (q == 1 ? h[1] : h[2]);
+            const float Lq = q == 0 ? p.L[0] : (q == 1 ? p.L[1] : p.L[2]);
+            const int Nq = q == 0 ? p.W : (q == 1 ? p.H : p.D);
+            const int nq = q == 0 ? n[0] : (q == 1 ? n[1] : n[2]);
+            const int bq = q == 0 ? 0 : (q == 1 ? n[0] : n[0] + n[1]);
+            AxisRanges ar;
+            axis_ranges(oq, hq, Nq, p.xyz[3 * (size_t)k + q], p.periodic != 0, Lq, p.rc[t],
+                        p.cut != 0, ar);
+            bool any = false;
+            for (int e = 0; e < nq; ++e) {
+                const int i = idx[base[q] + e];
+                float f = 0.f, d2 = __builtin_huge_valf();
+#pragma unroll
+                for (int r = 0; r < MAX_IMAGES; ++r) {
+                    if (r < ar.n && i >= ar.lo[r] && i <= ar.hi[r]) {
+                        f = factor1d(box, ar.bh[r], ar.bl[r], hq, i, p.inv2s2[t], p.isq2s[t]);
+                        if (sph) {
+                            const float d = offset_at(ar.bh[r], ar.bl[r], hq, i);
+                            d2 = d * d;
+                        }
+                    }
+                }
+                srow[(size_t)s * ntw + bq + e] = f;
+                if (sph)
+                    sd2[(size_t)s * ntw + bq + e] = d2;
+                any = any || f != 0.f;
+            }
+            if (any)
+                atomicOr(&sflag[s], 1 << q);
+        }
+    }
+    __syncthreads();
+    if (rec_ok) {
+        for (int s0 = 0; s0 < nsame; s0 += 64) {
+            const int s = s0 + lane;
+            const bool hit = s < nsame && sflag[s] == 7;
+            const unsigned long long bal = __ballot(hit);
+            if (hit)
+                rel[nrel + __popcll(bal & ((1ull << lane) - 1ull))] = s;
+            nrel += __popcll(bal);
+        }
+    }
+    __syncthreads();
     float gx = 0.f, gy = 0.f, gz = 0.f;
     const bool wtd = p.weights != nullptr;
     if (t >= 0) {
@@ -121,7 +253,9 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
             const float wc = wtd ? p.weights[(size_t)a * p.C + c] : 1.f;
             if (wc == 0.f && !want_gw)
                 continue;
-            const T *U = (const T *)p.out + ((size_t)m * p.C + c) * (size_t)p.D * plane;
+            const size_t cbase = ((size_t)m * p.C + c) * (size_t)p.D * plane;
+            const T *U = recomp ? nullptr : (const T *)p.out + cbase;
+            const float *TG = recomp ? p.target + cbase : nullptr;
             float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
             // ADJ_UNROLL window elements per lane per round: their upstream
             // loads are issued together, then consumed in element order
@@ -144,9 +278,22 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                     u[j] = 0.f;
                     if (in) {
                         const int ix = idx[kx], iy = idx[base[1] + ky], iz = idx[base[2] + kz];
-                        u[j] = load_as_float<T>(U + (size_t)iz * plane + (size_t)iy * p.W + ix);
+                        const size_t v = (size_t)iz * plane + (size_t)iy * p.W + ix;
+                        u[j] = recomp ? TG[v] : load_as_float<T>(U + v);
                     } else {
                         ke[j][0] = -1;
+                    }
+                }
+                if (recomp) {
+                    // u = 2 (G'(v) - T(v)), G'(v) summed as the window kernel does
+#pragma unroll
+                    for (int j = 0; j < ADJ_UNROLL; ++j) {
+                        if (ke[j][0] < 0)
+                            continue;
+                        const float gp = recompute_density(srow, sd2, rel, nrel, ntw, nx,
+                                                           nx + ny, ke[j][0], ke[j][1], ke[j][2],
+                                                           p.sphere != 0, p.rc2[t]);
+                        u[j] = 2.f * (gp - u[j]);
                     }
                 }
 #pragma unroll
@@ -204,20 +351,28 @@ hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s)
 {
     if (p.n_atoms == 0)
         return hipSuccess;
-    const int block = 256, waves = block / 64;
-    const size_t lds = (size_t)waves * ((size_t)(p.W + p.H + p.D) * 16 + 3 * sizeof(AxisRanges));
+    const size_t per_wave = adjoint_wave_lds(p.W + p.H + p.D, p.recompute ? p.a_cap : 0,
+                                             p.recompute ? p.rec_ntw : 0, p.sphere != 0);
+    const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / per_wave));
+    const int block = 64 * waves;
+    const size_t lds = (size_t)waves * per_wave;
     const long long grid = (p.n_atoms + waves - 1) / waves;
-    if (grad_dtype == PG_OUT_F32) {
-        if (lds > 65536)
-            hipFuncSetAttribute((const void *)adjoint_kernel<float>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(adjoint_kernel<float>, dim3((unsigned)grid), dim3(block), lds, s, p);
-    } else {
-        if (lds > 65536)
-            hipFuncSetAttribute((const void *)adjoint_kernel<__bf16>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(adjoint_kernel<__bf16>, dim3((unsigned)grid), dim3(block), lds, s, p);
+    const void *k = grad_dtype == PG_OUT_F32
+                        ? (p.recompute ? (const void *)adjoint_kernel<float, true>
+                                       : (const void *)adjoint_kernel<float, false>)
+                        : (const void *)adjoint_kernel<__bf16, false>;
+    if (grad_dtype != PG_OUT_F32 && p.recompute)
+        return hipErrorInvalidValue;   // the residual is recomputed only in float32
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
     }
+    GridParams pc = p;
+    void *args[] = {&pc};
+    const hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(block), args, lds, s);
+    if (e != hipSuccess)
+        return e;
     return hipGetLastError();
 }
 

@@ -772,6 +772,26 @@ int reversal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b,
     return PG_OK;
 }
 
+// Most voxel indices an atom's cube window spans over the three axes: at
+// most floor(2 rc / h) + 1 centres lie within rc of the atom on an axis
+// (+2 for rounding), and never more than the axis holds; with
+// per-structure spacings the axis length.
+int window_index_bound(const GridParams &p)
+{
+    double rc = 0.0;
+    for (int t = 0; t < p.n_sig; ++t)
+        rc = std::max(rc, (double)p.rc[t]);
+    const int N[3] = {p.W, p.H, p.D};
+    int total = 0;
+    for (int q = 0; q < 3; ++q) {
+        int w = N[q];
+        if (!p.spacings && p.cut)
+            w = (int)std::min<double>(N[q], std::floor(2.0 * rc / (double)p.h[q]) + 3.0);
+        total += w;
+    }
+    return total;
+}
+
 void drop_graphs(pg_ctx *ctx)
 {
     for (auto &g : ctx->graphs)
@@ -1072,7 +1092,10 @@ int pg_reversal_step(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
         return s;
     if (!std::isfinite(lr))
         return PG_E_PARAM;
-    if (batch->n_mol > 0 && (!target || !residual || !loss))
+    // no residual grid: only where the window kernel forms the residual
+    // itself (the adjoint then recomputes it at the window voxels)
+    const bool keep_residual = residual != nullptr;
+    if (batch->n_mol > 0 && (!target || !loss || (!keep_residual && (!R.fused || weighted(batch)))))
         return PG_E_NULL;
     if (ws_bytes < R.ws || (R.ws > 0 && !ws))
         return PG_E_WORKSPACE;
@@ -1104,6 +1127,11 @@ int pg_reversal_step(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
             q.grad_xyz = grad_xyz;
             q.xyz_upd = xyz_update;
             q.lr = lr;
+            if (!keep_residual) {
+                q.target = target;
+                q.recompute = 1;
+                q.rec_ntw = window_index_bound(q);
+            }
             e = launch_adjoint(q, PG_OUT_F32, st);
         }
         return e;

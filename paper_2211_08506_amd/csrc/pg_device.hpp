@@ -155,6 +155,27 @@ __device__ __forceinline__ void base_offset(float o, float mu, int n, float L, f
     bl = (e1 + e2) - qe;
 }
 
+// Compact copy of AxisRanges kept in LDS (16-bit window bounds).
+struct RangeRec {
+    int32_t n;
+    int16_t lo[MAX_IMAGES], hi[MAX_IMAGES];
+    float bh[MAX_IMAGES], bl[MAX_IMAGES];
+};
+
+__device__ __forceinline__ RangeRec range_rec(const AxisRanges &ar)
+{
+    RangeRec R;
+    R.n = ar.n;
+#pragma unroll
+    for (int r = 0; r < MAX_IMAGES; ++r) {
+        R.lo[r] = (int16_t)(r < ar.n ? ar.lo[r] : 0);
+        R.hi[r] = (int16_t)(r < ar.n ? ar.hi[r] : -1);
+        R.bh[r] = r < ar.n ? ar.bh[r] : 0.f;
+        R.bl[r] = r < ar.n ? ar.bl[r] : 0.f;
+    }
+    return R;
+}
+
 // All ranges of one atom on one axis.  Far-away coordinates give n = 0.
 // Set-up work: runs once per atom and axis, before any output is written.
 __device__ __forceinline__ void axis_ranges(float o, float h, int N, float mu, bool periodic,

@@ -53,6 +53,10 @@ struct GridParams {
     float *loss;
     float *xyz_upd;
     float lr;
+    // reversal step without a stored residual: the adjoint forms
+    // 2 (G' - target) itself at each window voxel (out is then nullptr)
+    int32_t recompute;
+    int32_t rec_ntw;         // recompute: bound on an atom's window indices over the 3 axes
     // weighted channels: n_atoms x C weights (nullptr: one channel per type),
     // their gradient (backward, may be nullptr), and the number of entries
     // of the per-type tables (rc, inv2s2, ...) the types index

@@ -30,12 +30,6 @@
 
 namespace pg {
 
-struct RangeRec {
-    int32_t n;
-    int16_t lo[MAX_IMAGES], hi[MAX_IMAGES];
-    float bh[MAX_IMAGES], bl[MAX_IMAGES];
-};
-
 __host__ __device__ inline WindowLds window_lds_layout(int a_cap, int row_stride, int C, int D,
                                                       int mask_words, int weight_ch, bool sphere)
 {
@@ -223,7 +217,9 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
 
         // ---- 3. stream the planes: each lane owns U runs per pass, so a
         // wave issues U back-to-back 16-byte stores per pass
-        T *out = (T *)p.out + (size_t)m * mol_elems;
+        // a reversal step may keep no residual grid (out == nullptr)
+        const bool store = !RES || p.out != nullptr;
+        T *out = store ? (T *)p.out + (size_t)m * mol_elems : nullptr;
         const float *tgt = RES ? p.target + (size_t)m * mol_elems : nullptr;
         float sq = 0.f;
         for (int pl = wave; pl < planes; pl += nwaves) {
@@ -233,7 +229,7 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
 #pragma unroll
             for (int w = 0; w < 4; ++w)
                 mk[w] = (w < MW) ? uniform64(masks[(size_t)pl * MW + w]) : 0ull;
-            T *op = out + (size_t)pl * plane_elems;
+            T *op = store ? out + (size_t)pl * plane_elems : nullptr;
             for (int j0 = lane; j0 < chunks; j0 += 64 * U) {
                 int yq[U], xq[U];
                 bool ok[U];
@@ -299,7 +295,8 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                                 acc[u][k] = 2.f * r;
                             }
                         }
-                        store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], nt);
+                        if (store)
+                            store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], nt);
                     }
             }
         }

@@ -189,6 +189,89 @@ def test_step_graph_replay(pg, dev):
     step_case(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, "auto", graph=True)
 
 
+@pytest.mark.parametrize("case", ["point", "box", "periodic", "sphere", "graph"])
+def test_step_without_residual_grid_is_bitwise(pg, dev, case):
+    """residual = NULL on the molecule window form: the adjoint forms
+    2 (G' - T) in each window from the target, summing G' as the forward
+    does, so loss, gradient and update equal a step with a residual buffer
+    bit for bit (and the oracle's step within the bars)."""
+    wl = synth.WORKLOADS["mol256"]
+    b = wl.batch(24)
+    rng = np.random.default_rng(52)
+    value = "box" if case == "box" else "point"
+    cell = 16.0 if case == "periodic" else None
+    shape = "sphere" if case == "sphere" else "cube"
+    origin = (0.0, 0.0, 0.0) if cell else wl.origin
+    xyz0 = np.mod(b.xyz, np.float32(16.0)).astype(np.float32) if cell else b.xyz
+    bb = synth.Batch(xyz0, b.types, b.offsets)
+    T = oracle.grid_fp64(bb.xyz, bb.types, bb.offsets, wl.sigma(), wl.dims, wl.spacing, origin,
+                         cell=cell, value=value, cutoff_shape=shape).astype(np.float32)
+    x0 = (bb.xyz + rng.uniform(-0.15, 0.15, size=bb.xyz.shape)).astype(np.float32)
+    if cell:
+        x0 = np.mod(x0, np.float32(cell)).astype(np.float32)
+    lr = 0.01 if value == "point" else 2.0
+    loss_o, _, grad_o, _ = reversal.reversal_step(x0, bb.types, bb.offsets, wl.sigma(), wl.dims,
+                                                  wl.spacing, T, lr, origin, cell=cell,
+                                                  value=value, cutoff_shape=shape)
+    say(f"case reversal step without residual grid: {case}")
+    ctx = pg.Context(0)
+    desc = pg.make_desc(wl.n_types, wl.dims, wl.spacing, origin, wl.sigma(), 3.0, cell,
+                        torch.float32, "window", value, cutoff_shape=shape)
+    xyz = torch.tensor(x0, device=dev)
+    types, offs = torch.tensor(bb.types, device=dev), torch.tensor(bb.offsets, device=dev)
+    bv = pg.BatchView(xyz, types, offs, offsets_host=bb.offsets)
+    assert ctx.plan(desc, bv)["form"] == "window"
+    Tt = torch.tensor(T, device=dev)
+    if case == "graph":
+        ctx.set_option(pg.PG_OPT_GRAPH, 1)
+    outs = {}
+    for keep in (True, False, True, False):
+        res = torch.full_like(Tt, float("nan")) if keep else None
+        loss = torch.full((bb.n_mol,), float("nan"), device=dev)
+        grad = torch.full_like(xyz, float("nan"))
+        upd = torch.full_like(xyz, float("nan"))
+        ctx.reversal_step(desc, bv, Tt, res, loss, grad, upd, lr)
+        torch.cuda.synchronize()
+        got = (loss.cpu().numpy(), grad.cpu().numpy(), upd.cpu().numpy())
+        if keep in outs:
+            for a, c in zip(outs[keep], got):
+                np.testing.assert_array_equal(a, c)   # replays repeat exactly
+        outs[keep] = got
+    for a, c in zip(outs[True], outs[False]):
+        np.testing.assert_array_equal(a, c)
+    ln, gr, _ = outs[False]
+    rel_l = float(np.max(np.abs(ln.astype(np.float64) - loss_o) / np.maximum(loss_o, 1e-30)))
+    rel_g, _ = errors(gr, grad_o)
+    say(f"[no residual grid {case}] bitwise equal to the stored-residual step; "
+        f"loss max-rel {rel_l:.3e}, grad rel-L2 {rel_g:.3e}")
+    assert rel_l <= F32_TOL and rel_g <= ADJ_TOL
+    assert ctx.device_error()[0] == 0
+
+
+def test_step_without_residual_grid_refused_elsewhere(pg, dev):
+    """A NULL residual needs the molecule window form without weights."""
+    import ctypes
+    lib = pg._lib()
+    ctx = pg.Context(0)
+    sig = synth.sigma_table(3, 0.3, 0.45)
+    rng = np.random.default_rng(53)
+    off = np.array([0, 400, 700], np.int32)
+    xyz = torch.tensor(rng.uniform(0, 8.0, size=(700, 3)).astype(np.float32), device=dev)
+    types = torch.tensor(rng.integers(0, 3, 700).astype(np.int32), device=dev)
+    offs = torch.tensor(off, device=dev)
+    desc = pg.make_desc(3, (40, 40, 40), 0.21, (0, 0, 0), sig, 3.0, 8.0, torch.float32, "window")
+    bv = pg.BatchView(xyz, types, offs, offsets_host=off)
+    assert ctx.plan(desc, bv)["binned"] == 1
+    T = torch.zeros((2, 3, 40, 40, 40), device=dev)
+    loss = torch.empty(2, device=dev)
+    ws = ctx.workspace(ctx.reversal_workspace_size(desc, bv))
+    st = lib.pg_reversal_step(ctx.handle, ctypes.byref(desc), ctypes.byref(bv.c), T.data_ptr(),
+                              None, loss.data_ptr(), None, None, ctypes.c_float(0.0),
+                              ws.data_ptr() if ws is not None and ws.numel() else None,
+                              ctx.reversal_workspace_size(desc, bv), None)
+    assert st == pg.PG_E_NULL
+
+
 def separated_batch(seed, n_mol, n_atoms, box=9.0, min_sep=2.6, n_types=5):
     rng = np.random.default_rng(seed)
     xyz, types, offs = [], [], [0]

@@ -200,3 +200,31 @@ def test_weighted_binned_path(pg, dev, form, dtype, tol):
     rw, _ = errors(Et.grad.cpu().numpy(), gw_o)
     say(f"[weighted binned grads] xyz {rx:.3e}, weights {rw:.3e}")
     assert rx <= ADJ_TOL and rw <= ADJ_TOL
+
+
+@pytest.mark.parametrize("scale", [1e-6, 1e5])
+def test_weighted_split_mfma_weight_range(pg, dev, scale):
+    """The split-fp16 MFMA form for float32 grids scales each plane by a
+    power of two chosen from its largest |phi_z w|: weights of 1e-6 or 1e5
+    (beyond fp16's range once multiplied out), mixed in sign and spread over
+    three decades within a channel, stay at the FP32 bar."""
+    rng = np.random.default_rng(29)
+    off = np.array([0, 400, 700], np.int32)
+    xyz = rng.uniform(0, 8, size=(700, 3)).astype(np.float32)
+    types = rng.integers(0, 4, 700).astype(np.int32)
+    sig = synth.sigma_table(4, 0.3, 0.45)
+    E = (rng.standard_normal((700, 3)) * 10.0 ** rng.uniform(-1.5, 1.5, (700, 3)) * scale)
+    E = E.astype(np.float32)
+    dims, h = (40, 40, 40), 0.21
+    say(f"case split MFMA weight range scale={scale:g}")
+    ref = oracle.grid_fp64(xyz, types, off, sig, dims, h, (0, 0, 0), cell=8.0, weights=E)
+    g = pg.grid(torch.tensor(xyz, device=dev), torch.tensor(types, device=dev),
+                torch.tensor(off, device=dev), list(sig), dims=dims, spacing=h, cell=8.0,
+                out_dtype=torch.float32, form="mfma", weights=torch.tensor(E, device=dev))
+    torch.cuda.synchronize()
+    got = g.double().cpu().numpy()
+    assert np.isfinite(got).all()
+    rel, mx = errors(got, ref)
+    wm = worst_molecule(got, ref)
+    say(f"[split MFMA weights x{scale:g}] rel-L2 {rel:.3e} max-abs {mx:.3e} worst {wm:.3e}")
+    assert rel <= F32_TOL and wm <= F32_TOL
