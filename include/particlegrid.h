@@ -99,7 +99,9 @@ enum { PG_VALUE_POINT = 0, PG_VALUE_BOX = 1 };
    under MFMA, a plane holding more than 2048 z images of one channel
    (pg_plan_info.atom_capacity) is reported as PG_E_CAPACITY through
    pg_get_device_error and left as zeros; the binned WINDOW form has no such
-   limit (atom_capacity 0).  The binned path needs D <= 4096. */
+   limit (atom_capacity 0) but holds at most 32 tiles of 32 x 32 voxels per
+   (y, x) plane (PG_E_UNSUPPORTED beyond).  The binned path needs
+   D <= 4096. */
 enum { PG_FORM_AUTO = 0, PG_FORM_PLAIN = 1, PG_FORM_WINDOW = 2, PG_FORM_MFMA = 3 };
 
 /* Grid description (all fields host values). */

@@ -700,6 +700,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     int ex = 0;
     if (mx > 0.f)
         (void)frexpf(mx, &ex);
+    ex = max(ex, -110);   // s and 1 / s stay normal floats for the tiniest weights
     const float sc = ldexpf(1.f, 14 - ex), unsc = ldexpf(1.f, ex - 14);
 
     f32x16 accp[2][2], accq[2][2];
