@@ -4,42 +4,42 @@
 // Structures with more atoms than the molecule window kernel stages in LDS
 // take this path.  Set-up, all on the GPU and free of order-dependent
 // atomics in anything that reaches the output:
-//   prep:    one thread per atom: exact per-axis window ranges (nearest
-//            periodic images included) into the atom's record, and counts of
-//            the atom per (channel, structure) and per (channel, prep block);
-//   factor:  one wave per atom: the 1-D factors of every voxel index inside
-//            its windows (ranges concatenated), written coalesced;
+//   prep:    three threads per atom (one per axis): exact window ranges
+//            (nearest periodic images included) into the atom's record, and
+//            counts of the atom per (channel, structure) and per (channel,
+//            prep block);
 //   scan:    exclusive scans of both count arrays in channel-major order;
 //   place:   a stable partition of all atoms by channel (ballot ranks within
 //            a block): channel c's atoms in index order, so each (structure,
-//            channel) pair -- a "run" -- is one contiguous stretch of the list.
+//            channel) pair -- a "run" -- is one contiguous stretch of the list;
+//   zsort:   per run, the atoms' z images sorted stably by window start, so
+//            each plane's images are one contiguous range of that order.
 // Then one of two plane forms, one workgroup per (structure, channel, z
 // plane[, 128 x 128 super-tile]):
 //   mfma:    the plane is a product of two factor matrices (separability of
 //            the Gaussian and of the cube cutoff, Sec. III-A / IV-C):
-//            G[y][x] = sum_k phi_z^k(z) phi_y^k(y) phi_x^k(x).  Per run, a
-//            zsort kernel orders the atoms' z images stably by window start,
-//            so each plane's images are one contiguous range of that order,
-//            and an operand kernel writes phi_y and phi_x of every image once,
-//            as bf16, in 32-image blocks laid out as the matrix cores read
-//            them.  The plane kernel stages each block's rows of its
-//            super-tile in LDS once per workgroup (phi_y scaled by phi_z of
-//            the plane on the way), two blocks ahead of the contraction, and
-//            contracts on v_mfma_f32_32x32x16_bf16 with FP32 accumulation;
-//   window:  the same sum in FP32 on the vector ALUs -- the workgroup compacts,
-//            in list order, the run's atoms whose z window holds the plane;
-//            per 32-atom step their dense factor rows go to LDS and each lane
-//            accumulates its 16-voxel row runs over the atoms whose y window
-//            holds the row.
+//            G[y][x] = sum_k phi_z^k(z) phi_y^k(y) phi_x^k(x).  An operand
+//            kernel writes phi_y and phi_x of every image once, in 32-image
+//            blocks laid out as the matrix cores read them; the plane kernel
+//            stages each block's rows of its super-tile in LDS once per
+//            workgroup (phi_y scaled by phi_z of the plane on the way), two
+//            blocks ahead of the contraction.  bf16 grids contract bf16
+//            operands on v_mfma_f32_32x32x16_bf16; fp32 grids split the
+//            operands into fp16 hi/lo pairs and take three
+//            v_mfma_f32_32x32x16_f16 per step (FP32 accuracy); FP32
+//            accumulation in both;
+//   window:  the same sum in FP32 on the vector ALUs -- per 32-image step the
+//            images' dense factor rows go to LDS with a bit mask of the
+//            images meeting each 32 x 32 tile, and each lane accumulates a
+//            4 x 4 block of voxels over its tile's images.
 // Both forms sum each voxel's atoms in an order fixed by the input alone
-// (list order, or z-window start then list order), so results are bitwise
-// reproducible.
+// (z-window start, then list order), so results are bitwise reproducible.
 #include "pg_device.hpp"
 #include "pg_launch.hpp"
 
 namespace pg {
 
-constexpr int PREP_BLOCK = 256; // atoms per prep / place block (4 waves)
+constexpr int PREP_BLOCK = 256; // atoms per prep / place block
 constexpr int KC = 32;          // atoms per contraction step
 constexpr int ST = 128;         // MFMA super-tile edge (y and x)
 constexpr int OPROW = 40;       // staged operand row: 32 images + 8 bf16 of padding
