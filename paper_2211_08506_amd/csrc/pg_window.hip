@@ -248,6 +248,21 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
 #pragma unroll
                     for (int k = 0; k < VEC; ++k)
                         acc[u][k] = 0.f;
+                // residual mode: the target runs are loaded before the
+                // accumulation, so their latency overlaps it
+                float tv[RES ? U : 1][VEC];
+                if constexpr (RES) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (ok[u])
+                            load_row<VEC>(tgt + (size_t)pl * plane_elems + (size_t)(j0 + 64 * u) * VEC,
+                                          tv[u]);
+                        else
+#pragma unroll
+                            for (int k = 0; k < VEC; ++k)
+                                tv[u][k] = 0.f;
+                    }
+                }
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     unsigned long long bits = mk[w];
@@ -285,12 +300,9 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                 for (int u = 0; u < U; ++u)
                     if (ok[u]) {
                         if constexpr (RES) {
-                            float tv[VEC];
-                            load_row<VEC>(tgt + (size_t)pl * plane_elems +
-                                              (size_t)(j0 + 64 * u) * VEC, tv);
 #pragma unroll
                             for (int k = 0; k < VEC; ++k) {
-                                const float r = acc[u][k] - tv[k];
+                                const float r = acc[u][k] - tv[u][k];
                                 sq = __builtin_fmaf(r, r, sq);
                                 acc[u][k] = 2.f * r;
                             }
