@@ -43,13 +43,14 @@ __device__ __forceinline__ float wave_sum(float v)
 
 // Per-wave LDS bytes of the adjoint: the atom's lists over the NT = W + H + D
 // indices and its ranges, plus, when recomputing the residual, for up to
-// a_cap same-channel atoms their index, flags, order and factor rows (and
-// squared offsets for the sphere) over this atom's window lists of at most
-// ntw indices.
+// a_cap same-channel atoms their index, flags, order, range records and
+// factor rows (and squared offsets for the sphere) over this atom's window
+// lists of at most ntw indices.
 __host__ __device__ inline size_t adjoint_wave_lds(int NT, int a_cap, int ntw, bool sphere)
 {
     return (size_t)NT * 16 + 3 * sizeof(AxisRanges) +
-           (size_t)a_cap * (3 * sizeof(int) + (size_t)ntw * sizeof(float) * (sphere ? 2 : 1));
+           (size_t)a_cap * (3 * sizeof(int) + 3 * sizeof(RangeRec) +
+                            (size_t)ntw * sizeof(float) * (sphere ? 2 : 1));
 }
 
 // G'(v) of the atom's channel at window element (kx, ky, kz): the window
@@ -58,14 +59,13 @@ __host__ __device__ inline size_t adjoint_wave_lds(int NT, int a_cap, int ntw, b
 // atom's window lists (0 outside an atom's window, where the window kernel
 // adds an exact zero), keeping under the sphere cutoff phi_x only where
 // dx^2 <= (rc^2 - dz^2) - dy^2.
-__device__ __forceinline__ float recompute_density(const float *srow, const float *sd2,
-                                                   const int *rel, int nrel, int ntw, int by,
-                                                   int bz, int kx, int ky, int kz, bool sph,
-                                                   float rc2)
+__device__ __forceinline__ float recompute_density(const float *srow, const float *sd2, int nrel,
+                                                   int ntw, int by, int bz, int kx, int ky,
+                                                   int kz, bool sph, float rc2)
 {
     float acc = 0.f;
     for (int r = 0; r < nrel; ++r) {
-        const int o = rel[r] * ntw;
+        const int o = r * ntw;
         const float fz = srow[o + bz + kz];
         const float fy = srow[o + by + ky];
         const float fx = srow[o + kx];
@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     const int NT = p.W + p.H + p.D;
     // per-wave slice: idx[NT] (int) | phi[NT] | dphi[NT] | dsq[NT] | 3 range
     // records | recompute: same[a_cap] | flags[a_cap] | rel[a_cap] |
-    // rows[a_cap][ntw] | (sphere) squared offsets[a_cap][ntw]
+    // range records[a_cap][3] | rows[a_cap][ntw] | (sphere) squared
+    // offsets[a_cap][ntw]
     constexpr bool recomp = RECOMP;
     const int rcap = recomp ? p.a_cap : 0, ntw = recomp ? p.rec_ntw : 0;
     unsigned char *slice =
@@ -102,7 +103,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
     int *same = (int *)(rg + 3);
     int *sflag = same + rcap;
     int *rel = sflag + rcap;
-    float *srow = (float *)(rel + rcap);
+    RangeRec *srr = (RangeRec *)(rel + rcap);
+    float *srow = (float *)(srr + 3 * rcap);
     float *sd2 = srow + (size_t)rcap * ntw;
     const int base[3] = {0, p.W, p.W + p.H};
     const int N[3] = {p.W, p.H, p.D};   // indexed by the compile-time axis only
@@ -191,51 +193,66 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
         nsame = min(nsame, rcap);   // the window plan holds every atom of a structure
     }
     __syncthreads();
+    // ranges of every listed atom, and whether they meet this atom's window
+    // ranges on each axis (then the atom adds to some window voxel)
     if (rec_ok) {
-        const bool box = p.box != 0, sph = p.sphere != 0;
         for (int j = lane; j < 3 * nsame; j += 64) {
-            const int s = j / 3, q = j - 3 * (j / 3), k = same[s];
+            const int sa = j / 3, q = j - 3 * (j / 3), k = same[sa];
             const float oq = q == 0 ? o[0] : (q == 1 ? o[1] : o[2]);
             const float hq = q == 0 ? h[0] : (q == 1 ? h[1] : h[2]);
             const float Lq = q == 0 ? p.L[0] : (q == 1 ? p.L[1] : p.L[2]);
             const int Nq = q == 0 ? p.W : (q == 1 ? p.H : p.D);
-            const int nq = q == 0 ? n[0] : (q == 1 ? n[1] : n[2]);
-            const int bq = q == 0 ? 0 : (q == 1 ? n[0] : n[0] + n[1]);
             AxisRanges ar;
             axis_ranges(oq, hq, Nq, p.xyz[3 * (size_t)k + q], p.periodic != 0, Lq, p.rc[t],
                         p.cut != 0, ar);
-            bool any = false;
-            for (int e = 0; e < nq; ++e) {
-                const int i = idx[base[q] + e];
-                float f = 0.f, d2 = __builtin_huge_valf();
+            const RangeRec rr = range_rec(ar);
+            srr[j] = rr;
+            const AxisRanges &mine = rg[q];
+            bool meet = false;
 #pragma unroll
-                for (int r = 0; r < MAX_IMAGES; ++r) {
-                    if (r < ar.n && i >= ar.lo[r] && i <= ar.hi[r]) {
-                        f = factor1d(box, ar.bh[r], ar.bl[r], hq, i, p.inv2s2[t], p.isq2s[t]);
-                        if (sph) {
-                            const float d = offset_at(ar.bh[r], ar.bl[r], hq, i);
-                            d2 = d * d;
-                        }
-                    }
-                }
-                srow[(size_t)s * ntw + bq + e] = f;
-                if (sph)
-                    sd2[(size_t)s * ntw + bq + e] = d2;
-                any = any || f != 0.f;
-            }
-            if (any)
-                atomicOr(&sflag[s], 1 << q);
+            for (int r = 0; r < MAX_IMAGES; ++r)
+                for (int r2 = 0; r2 < mine.n; ++r2)
+                    meet = meet || (r < rr.n && rr.lo[r] <= mine.hi[r2] && mine.lo[r2] <= rr.hi[r]);
+            if (meet)
+                atomicOr(&sflag[sa], 1 << q);
         }
     }
     __syncthreads();
+    // the atoms that meet the window on all three axes, in index order
     if (rec_ok) {
         for (int s0 = 0; s0 < nsame; s0 += 64) {
-            const int s = s0 + lane;
-            const bool hit = s < nsame && sflag[s] == 7;
+            const int sa = s0 + lane;
+            const bool hit = sa < nsame && sflag[sa] == 7;
             const unsigned long long bal = __ballot(hit);
             if (hit)
-                rel[nrel + __popcll(bal & ((1ull << lane) - 1ull))] = s;
+                rel[nrel + __popcll(bal & ((1ull << lane) - 1ull))] = sa;
             nrel += __popcll(bal);
+        }
+    }
+    __syncthreads();
+    // their factor rows over this atom's window lists, one element per lane
+    if (rec_ok) {
+        const bool box = p.box != 0, sph = p.sphere != 0;
+        for (int j = lane; j < nrel * wtot; j += 64) {
+            const int r0 = j / wtot, e0 = j - r0 * wtot;
+            const int q = e0 < n[0] ? 0 : (e0 < n[0] + n[1] ? 1 : 2);
+            const int i = idx[base[q] + e0 - (q == 0 ? 0 : (q == 1 ? n[0] : n[0] + n[1]))];
+            const RangeRec &rr = srr[3 * rel[r0] + q];
+            const float hq = q == 0 ? h[0] : (q == 1 ? h[1] : h[2]);
+            float f = 0.f, d2 = __builtin_huge_valf();
+#pragma unroll
+            for (int r = 0; r < MAX_IMAGES; ++r) {
+                if (r < rr.n && i >= rr.lo[r] && i <= rr.hi[r]) {
+                    f = factor1d(box, rr.bh[r], rr.bl[r], hq, i, p.inv2s2[t], p.isq2s[t]);
+                    if (sph) {
+                        const float d = offset_at(rr.bh[r], rr.bl[r], hq, i);
+                        d2 = d * d;
+                    }
+                }
+            }
+            srow[(size_t)r0 * ntw + e0] = f;
+            if (sph)
+                sd2[(size_t)r0 * ntw + e0] = d2;
         }
     }
     __syncthreads();
@@ -290,7 +307,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                     for (int j = 0; j < ADJ_UNROLL; ++j) {
                         if (ke[j][0] < 0)
                             continue;
-                        const float gp = recompute_density(srow, sd2, rel, nrel, ntw, nx,
+                        const float gp = recompute_density(srow, sd2, nrel, ntw, nx,
                                                            nx + ny, ke[j][0], ke[j][1], ke[j][2],
                                                            p.sphere != 0, p.rc2[t]);
                         u[j] = 2.f * (gp - u[j]);
