@@ -774,8 +774,9 @@ int reversal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b,
 
 // Most voxel indices an atom's cube window spans over the three axes: at
 // most floor(2 rc / h) + 1 centres lie within rc of the atom on an axis
-// (+2 for rounding), and never more than the axis holds; with
-// per-structure spacings the axis length.
+// (+2 for rounding), and never more than the axis holds; the axis length
+// with per-structure spacings, and for periodic cells (a grid wider than
+// the cell can hold several images of one window).
 int window_index_bound(const GridParams &p)
 {
     double rc = 0.0;
@@ -785,7 +786,7 @@ int window_index_bound(const GridParams &p)
     int total = 0;
     for (int q = 0; q < 3; ++q) {
         int w = N[q];
-        if (!p.spacings && p.cut)
+        if (!p.spacings && !p.periodic && p.cut)
             w = (int)std::min<double>(N[q], std::floor(2.0 * rc / (double)p.h[q]) + 3.0);
         total += w;
     }

@@ -189,7 +189,7 @@ def test_step_graph_replay(pg, dev):
     step_case(pg, dev, b, wl.sigma(), wl.dims, wl.spacing, wl.origin, "auto", graph=True)
 
 
-@pytest.mark.parametrize("case", ["point", "box", "periodic", "sphere", "graph"])
+@pytest.mark.parametrize("case", ["point", "box", "periodic", "periodic_wide", "sphere", "graph"])
 def test_step_without_residual_grid_is_bitwise(pg, dev, case):
     """residual = NULL on the molecule window form: the adjoint forms
     2 (G' - T) in each window from the target, summing G' as the forward
@@ -199,10 +199,12 @@ def test_step_without_residual_grid_is_bitwise(pg, dev, case):
     b = wl.batch(24)
     rng = np.random.default_rng(52)
     value = "box" if case == "box" else "point"
-    cell = 16.0 if case == "periodic" else None
+    # periodic_wide: a 16 A grid over a 12 A cell, so one atom's window
+    # can appear twice along an axis
+    cell = {"periodic": 16.0, "periodic_wide": 12.0}.get(case)
     shape = "sphere" if case == "sphere" else "cube"
     origin = (0.0, 0.0, 0.0) if cell else wl.origin
-    xyz0 = np.mod(b.xyz, np.float32(16.0)).astype(np.float32) if cell else b.xyz
+    xyz0 = np.mod(b.xyz, np.float32(cell)).astype(np.float32) if cell else b.xyz
     bb = synth.Batch(xyz0, b.types, b.offsets)
     T = oracle.grid_fp64(bb.xyz, bb.types, bb.offsets, wl.sigma(), wl.dims, wl.spacing, origin,
                          cell=cell, value=value, cutoff_shape=shape).astype(np.float32)
