@@ -129,6 +129,22 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
             }
         }
     }
+    // recompute: the structure's first 64 atoms are requested before the
+    // range search below, so that latency overlaps it
+    long long s0 = 0, s1 = 0;
+    int tk = -1;
+    float kx = 0.f, ky = 0.f, kz = 0.f;
+    if (recomp && t >= 0) {
+        s0 = p.offsets[m];
+        s1 = p.offsets[m + 1];
+        const long long k = s0 + lane;
+        if (k < s1) {
+            tk = p.types[k];
+            kx = p.xyz[3 * k];
+            ky = p.xyz[3 * k + 1];
+            kz = p.xyz[3 * k + 2];
+        }
+    }
     // lanes 0..2: window ranges of the three axes
     if (t >= 0 && lane < 3) {
         const int q = lane;
@@ -137,6 +153,31 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
         const float mq = q == 0 ? mu[0] : (q == 1 ? mu[1] : mu[2]);
         const float Lq = q == 0 ? p.L[0] : (q == 1 ? p.L[1] : p.L[2]);
         axis_ranges(oq, hq, N[q], mq, p.periodic != 0, Lq, p.rc[t], p.cut != 0, rg[q]);
+    }
+    // recompute: the structure's valid atoms of channel t in index order
+    int nsame = 0, nrel = 0;
+    if (recomp && t >= 0) {
+        for (long long k0 = s0; k0 < s1; k0 += 64) {
+            const long long k = k0 + lane;
+            if (k0 != s0) {
+                tk = -1;
+                if (k < s1) {
+                    tk = p.types[k];
+                    kx = p.xyz[3 * k];
+                    ky = p.xyz[3 * k + 1];
+                    kz = p.xyz[3 * k + 2];
+                }
+            }
+            const bool hit = k < s1 && tk == t && atom_valid(kx, ky, kz, tk, p.n_sig);
+            const unsigned long long bal = __ballot(hit);
+            const int rank = nsame + __popcll(bal & ((1ull << lane) - 1ull));
+            if (hit && rank < rcap) {
+                same[rank] = (int)k;
+                sflag[rank] = 0;
+            }
+            nsame += __popcll(bal);
+        }
+        nsame = min(nsame, rcap);   // the window plan holds every atom of a structure
     }
     __syncthreads();
     int n[3] = {0, 0, 0};
@@ -163,38 +204,13 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
             n[q] = k0;
         }
     }
-    __syncthreads();
-    // recompute: the structure's valid atoms of channel t in index order;
-    // their factor rows over this atom's window lists; the atoms whose rows
-    // are non-zero on all three axes, in index order
-    int nsame = 0, nrel = 0;
     const int wtot = n[0] + n[1] + n[2];
     const bool rec_ok = recomp && t >= 0 && wtot <= ntw;
     if (recomp && t >= 0 && wtot > ntw && lane == 0)
         raise_error(p.err, PG_E_CAPACITY, a);   // not expected: the host bounds every window
-    if (rec_ok) {
-        const long long s0 = p.offsets[m], s1 = p.offsets[m + 1];
-        for (long long k0 = s0; k0 < s1; k0 += 64) {
-            const long long k = k0 + lane;
-            bool hit = false;
-            if (k < s1) {
-                const int tk = p.types[k];
-                hit = tk == t && atom_valid(p.xyz[3 * k], p.xyz[3 * k + 1], p.xyz[3 * k + 2], tk,
-                                            p.n_sig);
-            }
-            const unsigned long long bal = __ballot(hit);
-            const int rank = nsame + __popcll(bal & ((1ull << lane) - 1ull));
-            if (hit && rank < rcap) {
-                same[rank] = (int)k;
-                sflag[rank] = 0;
-            }
-            nsame += __popcll(bal);
-        }
-        nsame = min(nsame, rcap);   // the window plan holds every atom of a structure
-    }
-    __syncthreads();
     // ranges of every listed atom, and whether they meet this atom's window
-    // ranges on each axis (then the atom adds to some window voxel)
+    // ranges on each axis (then the atom adds to some window voxel); the
+    // same phase as the atom's own lists (both need only its ranges)
     if (rec_ok) {
         for (int j = lane; j < 3 * nsame; j += 64) {
             const int sa = j / 3, q = j - 3 * (j / 3), k = same[sa];
@@ -229,7 +245,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
             nrel += __popcll(bal);
         }
     }
-    __syncthreads();
+    if constexpr (RECOMP)
+        __syncthreads();
     // their factor rows over this atom's window lists, one element per lane
     if (rec_ok) {
         const bool box = p.box != 0, sph = p.sphere != 0;
@@ -255,7 +272,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
                 sd2[(size_t)r0 * ntw + e0] = d2;
         }
     }
-    __syncthreads();
+    if constexpr (RECOMP)
+        __syncthreads();
     float gx = 0.f, gy = 0.f, gz = 0.f;
     const bool wtd = p.weights != nullptr;
     if (t >= 0) {
