@@ -388,7 +388,9 @@ hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s)
         return hipSuccess;
     const size_t per_wave = adjoint_wave_lds(p.W + p.H + p.D, p.recompute ? p.a_cap : 0,
                                              p.recompute ? p.rec_ntw : 0, p.sphere != 0);
-    const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / per_wave));
+    // one wave per workgroup: the waves share nothing, so a workgroup of
+    // several would only make each wait for the slowest at the barriers
+    const int waves = 1;
     const int block = 64 * waves;
     const size_t lds = (size_t)waves * per_wave;
     const long long grid = (p.n_atoms + waves - 1) / waves;
