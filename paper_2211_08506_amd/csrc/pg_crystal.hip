@@ -519,6 +519,43 @@ __device__ __forceinline__ PlaneItem mfma_plane_begin(const GridParams &p, const
     return P;
 }
 
+// Store a wave's 64 x 64 quadrant -- 2 x 2 MFMA tiles of 32 x 32, element
+// (i, j, e) given by val -- at rows yq.., columns xq.. of an H x W plane.
+// Lane l holds column l % 32 of rows 8 (e / 4) + 4 (l / 32) + e % 4 of each
+// tile, so one store instruction writes 32 contiguous elements per
+// half-wave.  A quadrant that lies inside the plane takes no bounds tests.
+template <typename T, typename F>
+__device__ __forceinline__ void store_quadrant(T *out, int H, int W, int yq, int xq, bool nt, F val)
+{
+    const int lane = threadIdx.x & 63;
+    if (yq + 64 <= H && xq + 64 <= W) {
+        T *o = out + (size_t)(yq + 4 * (lane >> 5)) * W + xq + (lane & 31);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const float v[1] = {val(i, j, e)};
+                    store_vec<T, 1>(o + (size_t)(32 * i + 8 * (e >> 2) + (e & 3)) * W + 32 * j, v, nt);
+                }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int y = yq + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                const int x = xq + 32 * j + (lane & 31);
+                if (y < H && x < W) {
+                    const float v[1] = {val(i, j, e)};
+                    store_vec<T, 1>(out + (size_t)y * W + x, v, nt);
+                }
+            }
+}
+
 __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParams q)
 {
     using T = __bf16;
@@ -627,23 +664,9 @@ __global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParam
     if (kb < nkb)
         step(kb, ga[0], gb[0], ga[1], gb[1]);
 
-    // store the quadrant: lane holds column (lane & 31) of rows
-    // 8 (e / 4) + 4 (lane / 32) + e % 4 of each tile; a store instruction
-    // writes 64 contiguous bytes (bf16) per half-wave
     T *out = (T *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int y = y0 + qy + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int x = x0 + qx + 32 * j + (lane & 31);
-                if (y < H && x < W) {
-                    const float v[1] = {acc[i][j][e]};
-                    store_vec<T, 1>(out + (size_t)y * W + x, v, p.nt_store != 0);
-                }
-            }
+    store_quadrant(out, H, W, y0 + qy, x0 + qx, p.nt_store != 0,
+                   [&](int i, int j, int e) { return acc[i][j][e]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -806,19 +829,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
         step(st, ga[0], gb[0], ga[1], gb[1]);
 
     float *out = (float *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int y = y0 + qy + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int x = x0 + qx + 32 * j + (lane & 31);
-                if (y < H && x < W) {
-                    const float v[1] = {(accp[i][j][e] + accq[i][j][e] * (1.f / SPLIT_UP)) * unsc};
-                    store_vec<float, 1>(out + (size_t)y * W + x, v, p.nt_store != 0);
-                }
-            }
+    store_quadrant(out, H, W, y0 + qy, x0 + qx, p.nt_store != 0, [&](int i, int j, int e) {
+        return (accp[i][j][e] + accq[i][j][e] * (1.f / SPLIT_UP)) * unsc;
+    });
 }
 
 // FP32 vector-ALU form: one workgroup (256 threads) per (structure, channel,
