@@ -180,28 +180,39 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
         nsame = min(nsame, rcap);   // the window plan holds every atom of a structure
     }
     __syncthreads();
+    // the window's index, factor and derivative lists of the three axes,
+    // built in one pass over their concatenation (lane e takes element e)
     int n[3] = {0, 0, 0};
     if (t >= 0) {
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
             const AxisRanges &R = rg[q];
-            int k0 = 0;
-            for (int r = 0; r < R.n; ++r) {
-                const int len = R.hi[r] - R.lo[r] + 1;
-                for (int k = lane; k < len; k += 64) {
-                    const int i = R.lo[r] + k;
-                    idx[base[q] + k0 + k] = i;
-                    phi[base[q] + k0 + k] = factor1d(p.box != 0, R.bh[r], R.bl[r], h[q], i,
-                                                     p.inv2s2[t], p.isq2s[t]);
-                    dphi[base[q] + k0 + k] = dfactor1d(p.box != 0, R.bh[r], R.bl[r], h[q], i,
-                                                       p.inv2s2[t], p.invs2[t], p.inorm[t]);
-                    if (p.sphere) {
-                        const float d = offset_at(R.bh[r], R.bl[r], h[q], i);
-                        dsq[base[q] + k0 + k] = d * d;
-                    }
-                }
-                k0 += len;
+            int len = 0;
+            for (int r = 0; r < R.n; ++r)
+                len += R.hi[r] - R.lo[r] + 1;
+            n[q] = len;
+        }
+        const int n01 = n[0] + n[1], nall = n01 + n[2];
+        for (int e = lane; e < nall; e += 64) {
+            const int q = e < n[0] ? 0 : (e < n01 ? 1 : 2);
+            const int eq = e - (q == 0 ? 0 : (q == 1 ? n[0] : n01));   // position in axis q
+            const AxisRanges &R = rg[q];
+            int r = 0, k = eq;
+            while (r + 1 < R.n && k > R.hi[r] - R.lo[r]) {
+                k -= R.hi[r] - R.lo[r] + 1;
+                ++r;
             }
-            n[q] = k0;
+            const int i = R.lo[r] + k;
+            const float hq = q == 0 ? h[0] : (q == 1 ? h[1] : h[2]);
+            const int slot = base[q] + eq;
+            idx[slot] = i;
+            phi[slot] = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[t], p.isq2s[t]);
+            dphi[slot] = dfactor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[t], p.invs2[t],
+                                   p.inorm[t]);
+            if (p.sphere) {
+                const float d = offset_at(R.bh[r], R.bl[r], hq, i);
+                dsq[slot] = d * d;
+            }
         }
     }
     const int wtot = n[0] + n[1] + n[2];
