@@ -303,6 +303,18 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
             const T *U = recomp ? nullptr : (const T *)p.out + cbase;
             const float *TG = recomp ? p.target + cbase : nullptr;
             float sx = 0.f, sy = 0.f, sz = 0.f, sw = 0.f;
+            // the lane's window element e = lane, lane + 64, ... as digits
+            // (kx, ky, kz) of the mixed radix (nx, ny, nz), stepped by 64 =
+            // (dx, dy, dz) per element with one carry at most per digit
+            int cx = 0, cy = 0, cz = 0, dx = 0, dy = 0, dz = 0;
+            if (total > 0) {
+                cx = lane % nx;
+                cy = (lane / nx) % ny;
+                cz = (lane / nx) / ny;
+                dx = 64 % nx;
+                dy = (64 / nx) % ny;
+                dz = (64 / nx) / ny;
+            }
             // ADJ_UNROLL window elements per lane per round: their upstream
             // loads are issued together, then consumed in element order
             for (int e0 = 0; e0 < total; e0 += 64 * ADJ_UNROLL) {
@@ -311,10 +323,14 @@ __global__ void __launch_bounds__(256) adjoint_kernel(GridParams p)
 #pragma unroll
                 for (int j = 0; j < ADJ_UNROLL; ++j) {
                     const int e = e0 + 64 * j + lane;
-                    const int kx = e % nx;
-                    const int r = e / nx;
-                    const int ky = r % ny;
-                    const int kz = r / ny;
+                    const int kx = cx, ky = cy, kz = cz;
+                    cx += dx;
+                    const int carry_x = cx >= nx ? 1 : 0;
+                    cx -= carry_x * nx;
+                    cy += dy + carry_x;
+                    const int carry_y = cy >= ny ? 1 : 0;
+                    cy -= carry_y * ny;
+                    cz += dz + carry_y;
                     ke[j][0] = kx;
                     ke[j][1] = ky;
                     ke[j][2] = kz;
