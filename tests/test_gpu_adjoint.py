@@ -169,3 +169,32 @@ def test_adjoint_full_size_1024(pg, dev):
     rel = float(np.sqrt(num / den))
     say(f"[adjoint 1024] rel-L2 {rel:.3e} worst-molecule {worst:.3e}")
     assert rel <= ADJ_TOL and worst <= ADJ_TOL
+
+
+@pytest.mark.parametrize("dims", [(5, 7, 90), (6, 20, 9), (12, 10, 1)],
+                         ids=["x_wider_than_a_wave", "y_carries", "single_x_column"])
+def test_adjoint_whole_grid_windows(pg, dev, dims):
+    """No cutoff (k = 0): every window is the whole grid, so a lane's window
+    elements run over many rounds and the lane's (x, y, z) position in the
+    window is stepped by 64 with carries in every digit: x rows longer than
+    a wave (90), carries from x into y and from y into z (9 x 20), and a
+    single x column (nx = 1)."""
+    D, H, W = dims
+    h = 0.3
+    rng = np.random.default_rng(sum(dims))
+    counts = [3, 0, 5]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    ext = np.array([W, H, D]) * h
+    xyz = (rng.uniform(0.1, 0.9, size=(int(off[-1]), 3)) * ext).astype(np.float32)
+    types = rng.integers(0, 3, int(off[-1])).astype(np.int32)
+    b = synth.Batch(xyz, types, off)
+    sig = synth.sigma_table(3, 0.45, 0.8)
+    say(f"case adjoint whole-grid windows, dims {dims}")
+    U = synth.upstream(41, (len(counts), 3) + dims)
+    got, Uused = gpu_grad(pg, dev, b, sig, dims, h, (0, 0, 0), U, cutoff_k=0.0)
+    ref = oracle.grad_fp64(b.xyz, b.types, b.offsets, sig, dims, h, Uused, (0, 0, 0),
+                           cutoff_k=0.0)
+    rel, mx = errors(got, ref)
+    wm = per_molecule_rel(got, ref, b.offsets)
+    say(f"[adjoint/whole grid {dims}] rel-L2 {rel:.3e} max-abs {mx:.3e} worst-molecule {wm:.3e}")
+    assert rel <= ADJ_TOL and wm <= ADJ_TOL
