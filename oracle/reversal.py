@@ -20,12 +20,13 @@ Comparisons are made in the precision of the array passed in, so the same
 float32 grid gives the same peaks on both sides.
 
 Peaks of a structure come out in raster order (channel, z, y, x); the
-position is the voxel centre o + (i + 1/2) h evaluated in double and rounded
-once to float32 (o, h float32), and the type is the channel.
+position is the exact voxel centre o + (i + 1/2) h (o, h float32) rounded
+once to float32, to nearest with ties to even, and the type is the channel.
 """
 from __future__ import annotations
 
 import itertools
+from fractions import Fraction
 
 import numpy as np
 
@@ -51,6 +52,40 @@ def peak_mask(grid: np.ndarray, threshold: float) -> np.ndarray:
     return mask
 
 
+def round_f32(x: Fraction) -> np.float32:
+    """The float32 nearest to the rational x (ties to the even significand)."""
+    c = np.float32(float(x))
+    cands = [np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))]
+    best = None
+    for v in cands:
+        if not np.isfinite(v):
+            continue
+        d = abs(Fraction(float(v)) - x)
+        even = (int(np.asarray(v).view(np.uint32)) & 1) == 0
+        if best is None or d < best[0] or (d == best[0] and even):
+            best = (d, v)
+    return np.float32(best[1])
+
+
+def voxel_centres_f32(o: np.ndarray, idx: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """o + (idx + 1/2) h rounded once to float32, for float32 o, h (per
+    column) and integer idx: in double where both operations are exact (the
+    product always is for idx < 2^28; the sum is checked with TwoSum), else
+    in rationals."""
+    o64 = np.broadcast_to(np.asarray(o, np.float32).astype(np.float64), idx.shape)
+    h64 = np.broadcast_to(np.asarray(h, np.float32).astype(np.float64), idx.shape)
+    p = (idx.astype(np.float64) + 0.5) * h64
+    s = o64 + p
+    bb = s - o64
+    err = (o64 - (s - bb)) + (p - bb)
+    out = s.astype(np.float32)
+    for k in zip(*np.nonzero(err != 0.0)):
+        exact = Fraction(float(o64[k])) + (Fraction(int(idx[k])) + Fraction(1, 2)) * \
+            Fraction(float(h64[k]))
+        out[k] = round_f32(exact)
+    return out
+
+
 def find_peaks(grid, threshold, origin, spacing, origins=None, spacings=None):
     """Peaks of a batch of grids (B, C, D, H, W) -> (xyz float32 (n, 3),
     types int32 (n,), offsets int64 (B + 1,))."""
@@ -65,9 +100,8 @@ def find_peaks(grid, threshold, origin, spacing, origins=None, spacings=None):
         c, z, y, x = np.nonzero(m[b])          # row-major order = raster order
         o = o32 if origins is None else np.asarray(origins, np.float32)[b]
         h = h32 if spacings is None else np.asarray(spacings, np.float32)[b]
-        idx = np.stack([x, y, z], axis=1).astype(np.float64)
-        pos = o.astype(np.float64) + (idx + 0.5) * h.astype(np.float64)
-        xyz.append(pos.astype(np.float32))
+        idx = np.stack([x, y, z], axis=1).astype(np.int64)
+        xyz.append(voxel_centres_f32(o, idx, h))
         types.append(c.astype(np.int32))
         offsets.append(offsets[-1] + len(c))
     return (np.concatenate(xyz).reshape(-1, 3) if xyz else np.zeros((0, 3), np.float32),
