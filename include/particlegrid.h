@@ -191,7 +191,14 @@ const char *pg_status_str(int status);
 /* Create a context bound to HIP device `device`: it owns the sticky device
    error word, the tuning table and the captured-graph cache.  Allocates a
    few bytes of device memory once (not on the hot path).
-   Errors: PG_E_NULL, PG_E_HIP. */
+   device = PG_HOST_ONLY makes a context that touches no device (it needs
+   no GPU): it holds a tuning table and options, pg_plan and
+   pg_workspace_size consult it as they would a gfx950 device's (256 CUs,
+   160 KiB of LDS per workgroup), pg_tuning_load/save work, and every call
+   that would launch or synchronise returns PG_E_UNSUPPORTED.
+   Errors: PG_E_NULL, PG_E_PARAM (negative device other than PG_HOST_ONLY),
+   PG_E_HIP. */
+#define PG_HOST_ONLY (-1)
 int pg_create(pg_ctx **ctx, int device);
 
 /* Destroy a context (waits for nothing; the caller synchronises first). */

@@ -40,7 +40,9 @@ import numpy as np
 from .brute import brute_fp64  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libpgoracle.so")
+# PGORACLE_LIB selects another build of the same source (the sanitizer
+# build of oracle/build.py --sanitize)
+_LIB_PATH = os.environ.get("PGORACLE_LIB") or os.path.join(_HERE, "libpgoracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)

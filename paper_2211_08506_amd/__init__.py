@@ -26,7 +26,9 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libparticlegrid.so")
+# PARTICLEGRID_LIB selects another build of the same sources (the host
+# sanitizer build of build.py --sanitize, for CPU test runs)
+LIB_PATH = os.environ.get("PARTICLEGRID_LIB") or os.path.join(_HERE, "libparticlegrid.so")
 # launch shapes measured by pg_autotune on an MI355X, loaded by every Context
 SHIPPED_TUNING = os.path.join(_HERE, "tuning_gfx950.json")
 
@@ -40,6 +42,7 @@ VALUES = {"point": 0, "box": 1}
 PG_CELL_NONE, PG_CELL_ORTHO, PG_CELL_TRICLINIC = 0, 1, 2
 SHAPES = {"cube": 0, "sphere": 1}
 PG_OPT_GRAPH, PG_OPT_BLOCK, PG_OPT_GRID_PER_CU, PG_OPT_NT_STORE, PG_OPT_UNROLL = 1, 2, 3, 4, 5
+PG_HOST_ONLY = -1          # pg_create device of a context that touches no GPU
 MAX_CHANNELS = 64
 
 

@@ -743,7 +743,7 @@ int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *ou
 
 // Grid reversal step: the forward plan of the residual buffer, whether the
 // molecule window kernel forms the residual itself (fused), and the
-// workspace (the forward's, then FP64 partial loss sums when not fused).
+// workspace (the forward's, then float-float partial loss sums when not fused).
 struct RevPlan {
     Plan P;
     bool fused = false;
@@ -768,7 +768,7 @@ int reversal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b,
     R.ws = R.fused ? R.P.ws
                    : R.partial_off + (size_t)b->n_mol *
                                          residual_chunks((long long)d->C * d->D * d->H * d->W) *
-                                         sizeof(double);
+                                         sizeof(float2);
     return PG_OK;
 }
 
@@ -828,6 +828,18 @@ int pg_create(pg_ctx **out, int device)
     if (!out)
         return PG_E_NULL;
     *out = nullptr;
+    if (device == PG_HOST_ONLY) {
+        // planning and tuning tables only: the shape of a gfx950 device
+        pg_ctx *ctx = new pg_ctx();
+        ctx->device = PG_HOST_ONLY;
+        ctx->n_cu = 256;
+        ctx->max_lds = 163840;
+        ctx->arch = "gfx950 (host-only context)";
+        *out = ctx;
+        return PG_OK;
+    }
+    if (device < 0)
+        return PG_E_PARAM;
     pg_ctx *ctx = new pg_ctx();
     ctx->device = device;
     DeviceGuard g(device);
@@ -864,7 +876,7 @@ int pg_destroy(pg_ctx *ctx)
 {
     if (!ctx)
         return PG_E_NULL;
-    {
+    if (ctx->device != PG_HOST_ONLY) {
         DeviceGuard g(ctx->device);
         drop_graphs(ctx);
         if (ctx->cap_stream)
@@ -926,6 +938,8 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
 {
     if (!ctx)
         return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(ctx->mu);
     Plan P;
     Tri T;
@@ -970,6 +984,8 @@ int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     (void)ws_bytes;
     if (!ctx)
         return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
     int s = validate(desc, batch);
     if (s != PG_OK)
         return s;
@@ -1024,6 +1040,8 @@ int pg_find_peaks(pg_ctx *ctx, const pg_grid_desc *desc, const float *grid, int3
 {
     if (!ctx || !desc || !offsets_out || !n_found)
         return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
     if (n_mol < 0 || capacity < 0 || capacity > INT32_MAX)
         return PG_E_SHAPE;
     if (desc->C < 1 || desc->C > PG_MAX_CHANNELS || desc->D < 1 || desc->H < 1 || desc->W < 1)
@@ -1086,6 +1104,8 @@ int pg_reversal_step(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
 {
     if (!ctx)
         return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(ctx->mu);
     RevPlan R;
     int s = reversal_plan(ctx, desc, batch, residual, target, R);
@@ -1105,7 +1125,7 @@ int pg_reversal_step(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batc
     DeviceGuard g(ctx->device);
     GridParams p;
     fill_params(p, ctx, desc, batch, R.P, residual, ws);
-    double *partial = (double *)((unsigned char *)ws + R.partial_off);
+    float2 *partial = (float2 *)((unsigned char *)ws + R.partial_off);
     auto launch = [&](hipStream_t st) -> hipError_t {
         GridParams q = p;
         if (R.fused) {
@@ -1153,6 +1173,8 @@ int pg_autotune(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, vo
 {
     if (!ctx)
         return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(ctx->mu);
     Plan base;
     int s = make_plan(ctx, desc, batch, out, base);
@@ -1404,6 +1426,8 @@ int pg_get_device_error(pg_ctx *ctx, int32_t *code, int64_t *first_atom)
 {
     if (!ctx || !code || !first_atom)
         return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     DeviceError h;

@@ -38,6 +38,33 @@ __device__ __forceinline__ void two_prod(float a, float b, float &p, float &e)
     e = __builtin_fmaf(a, b, -p);
 }
 
+// Float-float accumulation (a value held as hi + lo, |lo| <= ulp(hi) / 2):
+// (hi, lo) += (bhi, blo), Dekker's addition -- TwoSum of the high parts,
+// the low parts added to its error, renormalised.  For sums of non-negative
+// terms the relative error stays near 2^-44 per addition, far below the
+// float32 rounding of the final hi + lo.
+__device__ __forceinline__ void ff_add(float &hi, float &lo, float bhi, float blo)
+{
+    float s, e;
+    two_sum(hi, bhi, s, e);
+    e += lo + blo;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+
+// Wave-wide float-float sum of one float per lane (butterfly over the 64
+// lanes, a fixed order); every lane receives the total.
+__device__ __forceinline__ void ff_wave_sum(float v, float &hi, float &lo)
+{
+    hi = v;
+    lo = 0.f;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const float oh = __shfl_xor(hi, w, 64), ol = __shfl_xor(lo, w, 64);
+        ff_add(hi, lo, oh, ol);
+    }
+}
+
 // Sign (-1, 0, +1) of the exact real sum of N float terms.  Grow-expansion
 // (Shewchuk 1997): the running sum is kept as a non-overlapping expansion
 // of increasing magnitude, so the sign is that of its largest non-zero

@@ -46,10 +46,11 @@ hipError_t launch_adjoint(const GridParams &p, int grad_dtype, hipStream_t s);
 
 // Grid reversal (pg_reversal.hip): the local-maximum peak search, and the
 // residual / loss pass over a stored forward grid (p.out, float32) with
-// per-chunk FP64 partial sums in `partial` (n_mol x residual_chunks doubles).
+// per-chunk float-float partial sums in `partial` (n_mol x residual_chunks
+// (hi, lo) pairs).
 hipError_t launch_peaks(const PeakParams &p, hipStream_t s);
 int residual_chunks(long long per_mol);
-hipError_t launch_residual(const GridParams &p, double *partial, hipStream_t s);
+hipError_t launch_residual(const GridParams &p, float2 *partial, hipStream_t s);
 
 // Triclinic cells (pg_triclinic.hip): image expansion -- count, scan and
 // write of the images that can reach the grid (invalid atoms raise

@@ -25,6 +25,41 @@ constexpr int PEAK_BLOCK = 256;
 constexpr int RES_BLOCK = 256;
 constexpr int RES_PER_THREAD = 16;
 
+// The floats adjacent to a finite r.
+__device__ __forceinline__ float next_up(float r)
+{
+    if (r == 0.f)
+        return __builtin_bit_cast(float, 1u);   // the smallest positive subnormal
+    const uint32_t u = __builtin_bit_cast(uint32_t, r);
+    return __builtin_bit_cast(float, r > 0.f ? u + 1u : u - 1u);
+}
+
+__device__ __forceinline__ float next_down(float r) { return -next_up(-r); }
+
+// o + (i + 1/2) h rounded once to float32 (round to nearest, ties to even).
+// (i + 1/2) h = ph + pl exactly (TwoProd); r is the float sum of o + ph + pl
+// within an ulp, and the exact sign of (o + ph + pl) - r -/+ half an ulp of
+// r (expansion arithmetic) moves it to the correctly rounded value.
+__device__ __forceinline__ float centre_rounded(float o, int i, float h)
+{
+    float ph, pl;
+    two_prod((float)i + 0.5f, h, ph, pl);
+    float s, e;
+    two_sum(o, ph, s, e);
+    float r = s + (e + pl);
+    const float up = next_up(r), dn = next_down(r);
+    const float hu = 0.5f * (up - r), hd = 0.5f * (r - dn);   // exact halves of the gaps
+    const float tu[5] = {o, ph, pl, -r, -hu};
+    const int su = exact_sign(tu);
+    if (su > 0 || (su == 0 && (__builtin_bit_cast(uint32_t, up) & 1u) == 0u))
+        return up;
+    const float td[5] = {o, ph, pl, -r, hd};
+    const int sd = exact_sign(td);
+    if (sd < 0 || (sd == 0 && (__builtin_bit_cast(uint32_t, dn) & 1u) == 0u))
+        return dn;
+    return r;
+}
+
 __device__ __forceinline__ bool peak_at(const float *g, int z, int y, int x, int D, int H, int W,
                                         float thr)
 {
@@ -161,8 +196,7 @@ __global__ void __launch_bounds__(PEAK_BLOCK) peak_write_kernel(PeakParams p)
             const int idx[3] = {x, y, z};
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-                p.xyz[3 * pos + q] =
-                    (float)((double)o[q] + ((double)idx[q] + 0.5) * (double)h[q]);
+                p.xyz[3 * pos + q] = centre_rounded(o[q], idx[q], h[q]);
             p.types[pos] = c;
         }
         next += total;
@@ -171,12 +205,12 @@ __global__ void __launch_bounds__(PEAK_BLOCK) peak_write_kernel(PeakParams p)
 }
 
 // residual = 2 (G - target) in place over G, per-chunk partial sums of
-// (G - target)^2 in FP64 (chunk = RES_BLOCK * RES_PER_THREAD elements of one
-// structure, summed in a fixed order)
+// (G - target)^2 as float-float pairs (chunk = RES_BLOCK * RES_PER_THREAD
+// elements of one structure; lanes' FP32 sums combined in a fixed order)
 __global__ void __launch_bounds__(RES_BLOCK) residual_kernel(GridParams p, long long per_mol,
-                                                            int nchunk, double *partial)
+                                                            int nchunk, float2 *partial)
 {
-    __shared__ double part[RES_BLOCK / 64];
+    __shared__ float part[2][RES_BLOCK / 64];
     const long long chunk = blockIdx.x;
     const int m = (int)(chunk / nchunk);
     const long long k = chunk - (long long)m * nchunk;
@@ -193,30 +227,32 @@ __global__ void __launch_bounds__(RES_BLOCK) residual_kernel(GridParams p, long 
             g[e] = 2.f * r;
         }
     }
-    double s = sq;
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1)
-        s += __shfl_xor(s, w, 64);
-    if ((threadIdx.x & 63) == 0)
-        part[threadIdx.x >> 6] = s;
+    float sh, sl;
+    ff_wave_sum(sq, sh, sl);
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = sh;
+        part[1][threadIdx.x >> 6] = sl;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0;
+        float ah = 0.f, al = 0.f;
         for (int w = 0; w < RES_BLOCK / 64; ++w)
-            a += part[w];
-        partial[chunk] = a;
+            ff_add(ah, al, part[0][w], part[1][w]);
+        partial[chunk] = make_float2(ah, al);
     }
 }
 
-__global__ void loss_finish_kernel(GridParams p, int nchunk, const double *partial)
+__global__ void loss_finish_kernel(GridParams p, int nchunk, const float2 *partial)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= p.n_mol)
         return;
-    double a = 0.0;
-    for (int k = 0; k < nchunk; ++k)
-        a += partial[(size_t)m * nchunk + k];
-    p.loss[m] = (float)a;
+    float ah = 0.f, al = 0.f;
+    for (int k = 0; k < nchunk; ++k) {
+        const float2 v = partial[(size_t)m * nchunk + k];
+        ff_add(ah, al, v.x, v.y);
+    }
+    p.loss[m] = ah + al;
 }
 
 }  // namespace
@@ -240,7 +276,7 @@ int residual_chunks(long long per_mol)
     return (int)((per_mol + ch - 1) / ch);
 }
 
-hipError_t launch_residual(const GridParams &p, double *partial, hipStream_t s)
+hipError_t launch_residual(const GridParams &p, float2 *partial, hipStream_t s)
 {
     if (p.n_mol == 0)
         return hipSuccess;
@@ -250,7 +286,7 @@ hipError_t launch_residual(const GridParams &p, double *partial, hipStream_t s)
     hipLaunchKernelGGL(residual_kernel, dim3((unsigned)blocks), dim3(RES_BLOCK), 0, s, p, per_mol,
                        nchunk, partial);
     hipLaunchKernelGGL(loss_finish_kernel, dim3((p.n_mol + 255) / 256), dim3(256), 0, s, p, nchunk,
-                       (const double *)partial);
+                       (const float2 *)partial);
     return hipGetLastError();
 }
 

@@ -21,8 +21,9 @@
 // stream of step 3 needs no global loads.  In the residual mode of a grid
 // reversal step (§IV-A, §IV-C) step 3 also reads the target run, writes
 // 2 (G - target) in place of G and sums (G - target)^2 per structure
-// (per-lane FP32 partial sums, FP64 across the workgroup).  Every output element is written
-// exactly once, with no atomics on the output; each voxel's sum runs over
+// (per-lane FP32 partial sums, float-float sums across the workgroup).
+// Every output element is written exactly once, with no atomics on the
+// output; each voxel's sum runs over
 // atoms in index order, so results are bitwise reproducible for every
 // launch shape.
 #include "pg_device.hpp"
@@ -110,8 +111,11 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     const size_t mol_elems = (size_t)planes * plane_elems;
     const int chunks = (int)(plane_elems / VEC);
     const bool nt = p.nt_store != 0;
-    // runs (VEC consecutive x) per row; floor((j + 1/2) / CW) in float is
-    // exact for run indices below 2^20
+    // runs (VEC consecutive x) per row.  A run's row is floor(j / CW); the
+    // float estimate (j + 1/2) / CW is within one row of it for every plane
+    // the validation admits (fewer than 2^15 rows: three roundings of
+    // relative size 2^-24 move a value below 2^15 by less than 2^-8), and
+    // one integer comparison on each side makes it exact.
     const int CW = W / VEC;
     const float inv_cw = 1.0f / (float)CW;
 
@@ -238,7 +242,9 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
                     const int j = j0 + 64 * u;
                     ok[u] = j < chunks;
                     // run j starts at element j*VEC: row j / CW, column (j % CW) * VEC
-                    const int yy = (int)(((float)j + 0.5f) * inv_cw);
+                    int yy = (int)(((float)j + 0.5f) * inv_cw);
+                    yy -= yy * CW > j ? 1 : 0;
+                    yy += (yy + 1) * CW <= j ? 1 : 0;
                     yq[u] = ok[u] ? yy : 0;
                     xq[u] = ok[u] ? (j - yy * CW) * VEC : 0;
                 }
@@ -313,19 +319,21 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
             }
         }
         if constexpr (RES) {
-            __shared__ double red[16];
-            double d = sq;
-#pragma unroll
-            for (int w = 32; w >= 1; w >>= 1)
-                d += __shfl_xor(d, w, 64);
-            if (lane == 0)
-                red[wave] = d;
+            // per-lane FP32 partial sums, combined as float-float sums (a
+            // wave butterfly, then the waves in order): no FP64 on the GPU
+            __shared__ float red[2][16];
+            float dh, dl;
+            ff_wave_sum(sq, dh, dl);
+            if (lane == 0) {
+                red[0][wave] = dh;
+                red[1][wave] = dl;
+            }
             __syncthreads();
             if (tid == 0) {
-                double a = 0.0;
+                float ah = 0.f, alo = 0.f;
                 for (int w = 0; w < nwaves; ++w)
-                    a += red[w];
-                p.loss[m] = (float)a;
+                    ff_add(ah, alo, red[0][w], red[1][w]);
+                p.loss[m] = ah + alo;
             }
         }
         __syncthreads();

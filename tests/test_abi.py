@@ -329,3 +329,117 @@ def test_null_context_calls_fail_cleanly():
                                 None, None, 0.1, None, 0, None) == pg.PG_E_NULL
     assert lib.pg_destroy(None) == pg.PG_E_NULL
     assert lib.pg_create(None, 0) == pg.PG_E_NULL
+
+
+# ---- host-only contexts: planning with a tuning table, no GPU -------------
+
+def host_ctx():
+    lib = pg._lib()
+    h = ctypes.c_void_p()
+    assert lib.pg_create(ctypes.byref(h), pg.PG_HOST_ONLY) == pg.PG_OK
+    assert h.value
+    return lib, h
+
+
+def test_host_only_context_refuses_device_calls():
+    lib, h = host_ctx()
+    try:
+        d = desc_ok()
+        b = batch_ok()
+        assert lib.pg_grid_forward(h, ctypes.byref(d), ctypes.byref(b), 0x1000, None, 0,
+                                   None) == pg.PG_E_UNSUPPORTED
+        assert lib.pg_grid_backward(h, ctypes.byref(d), ctypes.byref(b), 0x1000, 0x1000, None,
+                                    None, 0, None) == pg.PG_E_UNSUPPORTED
+        assert lib.pg_autotune(h, ctypes.byref(d), ctypes.byref(b), 0x1000, None, 0, None,
+                               3) == pg.PG_E_UNSUPPORTED
+        code, first = ctypes.c_int32(), ctypes.c_int64()
+        assert lib.pg_get_device_error(h, ctypes.byref(code),
+                                       ctypes.byref(first)) == pg.PG_E_UNSUPPORTED
+        assert lib.pg_set_option(h, pg.PG_OPT_GRAPH, 1) == pg.PG_OK
+        assert lib.pg_last_hip_error(h) == 0
+        bad = ctypes.c_void_p()
+        assert lib.pg_create(ctypes.byref(bad), -7) == pg.PG_E_PARAM
+    finally:
+        assert lib.pg_destroy(h) == pg.PG_OK
+
+
+def plan_info(lib, h, d, b, out=0x10000):
+    info = pg.PlanInfo()
+    st = lib.pg_plan(h, ctypes.byref(d), ctypes.byref(b), out, ctypes.byref(info))
+    return st, {n: getattr(info, n) for n, _ in pg.PlanInfo._fields_}
+
+
+def test_host_only_plan_wide_plane_takes_window_form():
+    """A 1 x 3296 x 1783 plane with 8-atom structures fits gfx950's 160 KiB
+    of LDS per workgroup, so it takes the molecule window form (whose run
+    rows are exact for every admitted plane), not the binned path."""
+    lib, h = host_ctx()
+    try:
+        d = pg.make_desc(1, (1, 3296, 1783), 0.5, (0, 0, 0), [300.0], 0.0)
+        b = batch_ok(n_mol=2, n_atoms=16, max_atoms=8)
+        st, info = plan_info(lib, h, d, b)
+        assert st == pg.PG_OK
+        assert info["binned"] == 0 and info["form"] == pg.FORMS["window"]
+        assert info["vec"] == 1 and 65536 < info["lds_bytes"] <= 163840
+        # without a context the plan assumes 64 KiB of LDS: the binned path
+        info0 = pg.PlanInfo()
+        assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(b), 0x10000,
+                           ctypes.byref(info0)) == pg.PG_OK
+        assert info0.binned == 1
+    finally:
+        lib.pg_destroy(h)
+
+
+def test_tuning_table_round_trip_and_plan(tmp_path):
+    lib, h = host_ctx()
+    try:
+        d = desc_ok(out_dtype="bf16")
+        b = batch_ok(n_mol=4096, n_atoms=60000, max_atoms=29)
+        st, base = plan_info(lib, h, d, b)
+        assert st == pg.PG_OK and base["form"] == pg.FORMS["window"]
+        key = "C5_D32_H32_W32_bf16_p0_v8_nb12_ma32"
+        path = tmp_path / "t.json"
+        path.write_text('{"version": 1, "arch": "x", "entries": [\n  {"key": "%s", "block": 256, '
+                        '"per_cu": 3, "unroll": 4, "nt": 1, "form": 0, "us": 12.5}\n]}\n' % key)
+        assert lib.pg_tuning_load(h, str(path).encode()) == pg.PG_OK
+        st, tuned = plan_info(lib, h, d, b)
+        assert (tuned["block"], tuned["per_cu"], tuned["unroll"], tuned["nt_store"]) == (256, 3, 4, 1)
+        assert tuned["grid"] == 256 * 3
+        out = tmp_path / "saved.json"
+        assert lib.pg_tuning_save(h, str(out).encode()) == pg.PG_OK
+        assert key in out.read_text()
+        assert lib.pg_tuning_load(h, str(out).encode()) == pg.PG_OK
+        assert plan_info(lib, h, d, b)[1] == tuned
+    finally:
+        lib.pg_destroy(h)
+
+
+@pytest.mark.parametrize("text", [
+    "", "{", '{"version": 2, "entries": []}', '{"version": 1, "entries": [{"key": "k"',
+    '{"version": 1, "entries": [{"key": "k", "block": 256}]}',
+    '{"version": 1, "entries": [{"key": "k", "block": 7, "per_cu": 1, "unroll": 1, "nt": 0, "us": 1}]}',
+    '{"version": 1, "entries": [{"key": "k", "block": 256, "per_cu": 1, "unroll": 3, "nt": 0, "us": 1}]}',
+    '{"version": 1, "entries": [{"key": "k", "block": 256, "per_cu": 1, "unroll": 1, "nt": 0, "us": 1, "form": 9}]}',
+    '{"version": 1, "entries": [{"key": "k", "block": ', '{"version": 1, "entries": [{"key": "',
+    '{"version": 1, "entries": [{"key": "k}", "block": 256, "per_cu": 1, "unroll": 1, "nt": 0}',
+    "\x00\xff" * 64])
+def test_tuning_load_rejects_malformed_and_truncated(tmp_path, text):
+    """Malformed or truncated tables are refused and leave the table empty
+    (the plan falls back to the default shape)."""
+    lib, h = host_ctx()
+    try:
+        d = desc_ok(out_dtype="bf16")
+        b = batch_ok(n_mol=4096, n_atoms=60000, max_atoms=29)
+        default = plan_info(lib, h, d, b)[1]
+        good = tmp_path / "good.json"
+        good.write_text('{"version": 1, "entries": [{"key": "C5_D32_H32_W32_bf16_p0_v8_nb12_ma32", '
+                        '"block": 256, "per_cu": 3, "unroll": 4, "nt": 1, "us": 1}]}')
+        assert lib.pg_tuning_load(h, str(good).encode()) == pg.PG_OK
+        assert plan_info(lib, h, d, b)[1] != default
+        bad = tmp_path / "bad.json"
+        bad.write_bytes(text.encode("latin-1"))
+        assert lib.pg_tuning_load(h, str(bad).encode()) == pg.PG_E_PARAM
+        assert plan_info(lib, h, d, b)[1] == default
+        assert lib.pg_tuning_load(h, str(tmp_path / "missing.json").encode()) == pg.PG_E_PARAM
+    finally:
+        lib.pg_destroy(h)

@@ -246,10 +246,14 @@ def test_autotune_picks_a_form_and_persists(pg, dev, tmp_path):
 
 @pytest.mark.parametrize("form,dtype,tol", [("auto", torch.bfloat16, BF16_TOL),
                                             ("auto", torch.float32, F32_TOL),
-                                            ("mfma", torch.float32, F32_TOL)])
+                                            ("mfma", torch.float32, F32_TOL),
+                                            ("window", torch.float32, F32_TOL),
+                                            ("window", torch.bfloat16, BF16_TOL)])
 def test_full_size_crystal8_sampled(pg, dev, form, dtype, tol):
     """Eight 20 A cells of 2000-20000 atoms, 8 channels, 128^3 at 0.16 A,
-    in the launch configuration the benchmark times (HIP graph)."""
+    in the launch configuration the benchmark times (HIP graph): the MFMA
+    forms and the FP32 vector ("window") form the crystal comparison is
+    made against, at the plane shape it is timed on."""
     wl = synth.WORKLOADS["crystal8"]
     b = wl.batch()
     say(f"case full-size crystal8 form={form} dtype={dtype}")

@@ -385,3 +385,40 @@ def test_full_size_headline_f32(pg, dev):
 
 def test_full_size_48_bf16(pg, dev):
     _full_size_sampled(pg, dev, "mol4096x48", torch.bfloat16, BF16_TOL)
+
+
+def test_wide_plane_window_rows(pg, dev):
+    """A 3296 x 1783 plane (one z layer, one-element runs, 160 KB of LDS per
+    workgroup): the molecule window kernel must place every run in its row
+    (a float estimate alone is one row off for 187 runs of this plane, in
+    the last column).  No cutoff and a wide Gaussian make every voxel
+    non-zero and row-dependent, so a run read from the wrong row is seen."""
+    D, H, W = 1, 3296, 1783
+    h = 0.5
+    rng = np.random.default_rng(77)
+    off = np.array([0, 8, 16], np.int32)
+    ext = np.array([W, H, D], np.float64) * h
+    xyz = (rng.uniform(0.1, 0.9, size=(16, 3)) * ext).astype(np.float32)
+    b = synth.Batch(xyz, np.zeros(16, np.int32), off)
+    sig = np.array([300.0])
+    say("case wide plane 1 x 3296 x 1783, window form")
+    xyz_d, types, offs = to_device(b, dev)
+    ctx = pg.default_context(dev)
+    desc = pg.make_desc(1, (D, H, W), h, (0.0, 0.0, 0.0), sig, 0.0, None, torch.float32, "auto")
+    bv = pg.BatchView(xyz_d, types, offs, offsets_host=b.offsets)
+    out = pg.empty_grid(desc, b.n_mol, dev)
+    plan = ctx.plan(desc, bv, out)
+    say(f"plan {plan}")
+    assert plan["form"] == "window" and plan["binned"] == 0 and plan["vec"] == 1
+    assert plan["lds_bytes"] > 65536
+    ctx.forward(desc, bv, out)
+    torch.cuda.synchronize()
+    assert ctx.device_error()[0] == 0
+    ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, (D, H, W), h, (0.0, 0.0, 0.0),
+                           cutoff_k=0.0)
+    got = out.double().cpu().numpy()
+    rel, mx = errors(got, ref)
+    elem = float(np.max(np.abs(got - ref) / ref))
+    say(f"[wide plane] rel-L2 {rel:.3e} max-abs {mx:.3e} max elementwise rel {elem:.3e}")
+    assert ref.min() > 0
+    assert rel <= F32_TOL and elem <= 1e-5

@@ -53,6 +53,29 @@ def check_peaks(name, got, want):
     np.testing.assert_array_equal(gx, wx)      # bit-exact positions
 
 
+def test_peak_centre_rounded_once(pg, dev):
+    """The exact centre 1 + 2^-24 + 2^-60 (o = 1, h = 16773121 * 2^-59, voxel
+    2048) lies just above a float32 midpoint: rounded once it is 1 + 2^-23
+    (rounding through double would give 1.0).  The GPU forms it from
+    float-float terms with an exact sign test; it must match the oracle."""
+    h = float(np.float32(16773121 * 2.0 ** -59))
+    G = np.zeros((1, 1, 1, 1, 2049), np.float32)
+    G[0, 0, 0, 0, 2048] = 1.0
+    got = gpu_peaks(pg, dev, G, 0.5, (1.0, 0.0, 0.0), (h, 1.0, 1.0))
+    want = reversal.find_peaks(G, 0.5, (1.0, 0.0, 0.0), (h, 1.0, 1.0))
+    assert want[0][0, 0] == np.float32(1.0 + 2.0 ** -23)
+    check_peaks("rounded once", got, want)
+    # and a spread of origins and spacings, every centre of a long axis
+    rng = np.random.default_rng(23)
+    G = np.zeros((3, 1, 1, 1, 4099), np.float32)
+    G[:, 0, 0, 0, ::2] = 1.0
+    origins = rng.uniform(-50, 50, (3, 3)).astype(np.float32)
+    spacings = rng.uniform(1e-4, 2.0, (3, 3)).astype(np.float32)
+    check_peaks("centres of a long axis",
+                gpu_peaks(pg, dev, G, 0.5, (0, 0, 0), 1.0, origins, spacings),
+                reversal.find_peaks(G, 0.5, (0, 0, 0), 1.0, origins, spacings))
+
+
 @pytest.mark.parametrize("value,thr", [("point", 0.05), ("box", 1e-4)])
 def test_peaks_of_molecule_grids(pg, dev, value, thr):
     wl = synth.WORKLOADS["mol256"]
