@@ -232,6 +232,26 @@ int pg_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batc
 int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
                     void *out, void *ws, size_t ws_bytes, void *stream);
 
+/* pg_grid_forward for callers that cannot allocate device memory: code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc.  Same request, output and result as pg_grid_forward (the same
+   kernels; bit-identical output), but no workspace argument: the
+   workspace is the library's fixed device scratch buffer of
+   PG_STATIC_SCRATCH_BYTES, one per device, held from the library's load
+   until the process ends (its address is looked up in pg_create).  The
+   call allocates nothing (no hipMalloc / hipFree, no graph instantiation:
+   the context's graph option is ignored and the kernels are launched
+   directly on `stream`).  Every call on one device shares that device's
+   buffer and finds the previous call's contents there (the kernels clear
+   what must start at zero), so calls that overlap in time on one device --
+   on two streams, or from two contexts -- race and must be serialised by
+   the caller.
+   Errors: as pg_grid_forward; PG_E_WORKSPACE when the request needs more
+   than PG_STATIC_SCRATCH_BYTES of workspace (pg_workspace_size tells). */
+#define PG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int pg_grid_forward_static(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                           void *out, void *stream);
+
 /* Adjoint (§IV-C coordinate gradient): given grad_out = dL/dG (same shape
    and dtype as the forward's out), writes grad_xyz[a][alpha] = sum over
    voxels v in the window of atom a of grad_out[b][t_a][v] * dG_a(v)/dmu_alpha,

@@ -85,7 +85,9 @@ EXPORTS = ("pg_abi_version", "pg_status_str", "pg_create", "pg_destroy", "pg_val
            "pg_workspace_size", "pg_grid_forward", "pg_grid_backward", "pg_autotune",
            "pg_tuning_save", "pg_tuning_load", "pg_set_option", "pg_get_device_error",
            "pg_last_hip_error", "pg_plan", "pg_find_peaks", "pg_reversal_workspace_size",
-           "pg_reversal_step")
+           "pg_reversal_step", "pg_grid_forward_static")
+# fixed device scratch of pg_grid_forward_static (PG_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def _lib():
@@ -109,6 +111,7 @@ def _lib():
         lib.pg_validate.argtypes = [P(GridDesc), P(Batch)]
         lib.pg_workspace_size.argtypes = [vp, P(GridDesc), P(Batch), P(ctypes.c_size_t)]
         lib.pg_grid_forward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, ctypes.c_size_t, vp]
+        lib.pg_grid_forward_static.argtypes = [vp, P(GridDesc), P(Batch), vp, vp]
         lib.pg_grid_backward.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, vp, vp,
                                          ctypes.c_size_t, vp]
         lib.pg_autotune.argtypes = [vp, P(GridDesc), P(Batch), vp, vp, ctypes.c_size_t, vp,
@@ -306,6 +309,16 @@ class Context:
         _check(_lib().pg_grid_forward(self.handle, ctypes.byref(desc), ctypes.byref(batch.c),
                                       _ptr(out), _ptr(ws), nbytes, s.cuda_stream),
                "pg_grid_forward")
+        return out
+
+    def forward_static(self, desc: GridDesc, batch: BatchView, out: torch.Tensor,
+                       stream: Optional[torch.cuda.Stream] = None):
+        """pg_grid_forward_static: the forward on the library's fixed device
+        scratch buffer -- no workspace is allocated here or in the library."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(_lib().pg_grid_forward_static(self.handle, ctypes.byref(desc),
+                                             ctypes.byref(batch.c), _ptr(out), s.cuda_stream),
+               "pg_grid_forward_static")
         return out
 
     def backward(self, desc: GridDesc, batch: BatchView, grad_out: torch.Tensor,

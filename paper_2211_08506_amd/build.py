@@ -25,7 +25,7 @@ LIB = os.path.join(HERE, "libparticlegrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["pg_api.cpp", "pg_window.hip", "pg_plain.hip", "pg_adjoint.hip", "pg_crystal.hip",
-           "pg_reversal.hip", "pg_triclinic.hip"]
+           "pg_reversal.hip", "pg_triclinic.hip", "pg_scratch.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

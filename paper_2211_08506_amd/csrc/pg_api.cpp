@@ -725,7 +725,7 @@ int run_launches(pg_ctx *ctx, bool graph, const std::string &key, hipStream_t s,
 }
 
 int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *out, void *ws,
-                 size_t ws_bytes, hipStream_t s, const Plan &P)
+                 size_t ws_bytes, hipStream_t s, const Plan &P, bool allow_graph)
 {
     if (b->n_mol > 0 && !out)
         return PG_E_NULL;
@@ -733,7 +733,7 @@ int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *ou
         return PG_E_WORKSPACE;
     GridParams p;
     fill_params(p, ctx, d, b, P, out, ws);
-    const bool graph = ctx->use_graph && b->n_mol > 0;
+    const bool graph = allow_graph && ctx->use_graph && b->n_mol > 0;
     return run_launches(ctx, graph, graph ? graph_key(d, b, P, out, ws, ws_bytes) : std::string(),
                         s, [&](hipStream_t st) {
                             GridParams q = p;
@@ -791,6 +791,48 @@ int window_index_bound(const GridParams &p)
         total += w;
     }
     return total;
+}
+
+// Forward request on a given workspace.  allow_graph: the context's graph
+// option may capture and replay the launches (the allocation-free entry
+// point passes false and always launches directly).  Called with ctx->mu
+// held.
+int forward_request(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, void *out,
+                    void *ws, size_t ws_bytes, hipStream_t stream, bool allow_graph)
+{
+    Plan P;
+    Tri T;
+    size_t total = 0;
+    int s = plan_request(ctx, desc, batch, out, P, T, total);
+    if (s != PG_OK)
+        return s;
+    DeviceGuard g(ctx->device);
+    if (!T.on)
+        return forward_impl(ctx, desc, batch, out, ws, ws_bytes, stream, P, allow_graph);
+    // triclinic: expand the atoms into their lattice images in the
+    // workspace, then the non-periodic map over the images
+    if (batch->n_mol > 0 && !out)
+        return PG_E_NULL;
+    if (ws_bytes < total || (total > 0 && !ws))
+        return PG_E_WORKSPACE;
+    if (batch->n_mol == 0)
+        return PG_OK;
+    tri_bind(T, batch, ws);
+    GridParams p;
+    fill_params(p, ctx, &T.din, &T.bin, P, out, (unsigned char *)ws + T.inner_off);
+    const bool graph = allow_graph && ctx->use_graph;
+    std::string key;
+    if (graph) {
+        key = graph_key(desc, batch, P, out, ws, ws_bytes);
+        key.append("triclinic");
+    }
+    return run_launches(ctx, graph, key, stream, [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_tri_expand(T.q, ctx->d_err, st);
+        if (e != hipSuccess)
+            return e;
+        GridParams q = p;
+        return launch_forward(ctx, &T.din, P, q, st);
+    });
 }
 
 void drop_graphs(pg_ctx *ctx)
@@ -862,7 +904,13 @@ int pg_create(pg_ctx **out, int device)
     }
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    // the device's copy of the fixed scratch buffer (pg_grid_forward_static),
+    // looked up once per device with the device current
+    if (e == hipSuccess)
+        e = scratch_init(device);
     if (e != hipSuccess) {
+        if (ctx->cap_stream)
+            hipStreamDestroy(ctx->cap_stream);
         if (ctx->d_err)
             hipFree(ctx->d_err);
         delete ctx;
@@ -941,39 +989,30 @@ int pg_grid_forward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch
     if (ctx->device == PG_HOST_ONLY)
         return PG_E_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(ctx->mu);
+    return forward_request(ctx, desc, batch, out, ws, ws_bytes, (hipStream_t)stream, true);
+}
+
+int pg_grid_forward_static(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
+                           void *out, void *stream)
+{
+    if (!ctx)
+        return PG_E_NULL;
+    if (ctx->device == PG_HOST_ONLY)
+        return PG_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     Plan P;
     Tri T;
     size_t total = 0;
     int s = plan_request(ctx, desc, batch, out, P, T, total);
     if (s != PG_OK)
         return s;
-    DeviceGuard g(ctx->device);
-    if (!T.on)
-        return forward_impl(ctx, desc, batch, out, ws, ws_bytes, (hipStream_t)stream, P);
-    // triclinic: expand the atoms into their lattice images in the
-    // workspace, then the non-periodic map over the images
-    if (batch->n_mol > 0 && !out)
-        return PG_E_NULL;
-    if (ws_bytes < total || (total > 0 && !ws))
+    if (total > PG_STATIC_SCRATCH_BYTES)
         return PG_E_WORKSPACE;
-    if (batch->n_mol == 0)
-        return PG_OK;
-    tri_bind(T, batch, ws);
-    GridParams p;
-    fill_params(p, ctx, &T.din, &T.bin, P, out, (unsigned char *)ws + T.inner_off);
-    std::string key;
-    if (ctx->use_graph) {
-        key = graph_key(desc, batch, P, out, ws, ws_bytes);
-        key.append("triclinic");
-    }
-    return run_launches(ctx, ctx->use_graph != 0, key, (hipStream_t)stream,
-                        [&](hipStream_t st) -> hipError_t {
-                            hipError_t e = launch_tri_expand(T.q, ctx->d_err, st);
-                            if (e != hipSuccess)
-                                return e;
-                            GridParams q = p;
-                            return launch_forward(ctx, &T.din, P, q, st);
-                        });
+    void *ws = total > 0 ? scratch_ptr(ctx->device) : nullptr;
+    if (total > 0 && !ws)   // pg_create looks the buffer up; a context always has it
+        return PG_E_HIP;
+    return forward_request(ctx, desc, batch, out, ws, PG_STATIC_SCRATCH_BYTES,
+                           (hipStream_t)stream, false);
 }
 
 int pg_grid_backward(pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,

@@ -59,4 +59,10 @@ hipError_t launch_residual(const GridParams &p, float2 *partial, hipStream_t s);
 hipError_t launch_tri_expand(const TriParams &q, DeviceError *err, hipStream_t s);
 hipError_t launch_tri_reduce(const TriParams &q, hipStream_t s);
 
+// Fixed device scratch of the allocation-free forward (pg_scratch.hip):
+// scratch_init looks up the current device's copy once (the device must be
+// current); scratch_ptr returns it, or nullptr before scratch_init.
+hipError_t scratch_init(int device);
+void *scratch_ptr(int device);
+
 }  // namespace pg
