@@ -86,22 +86,23 @@ enum { PG_VALUE_POINT = 0, PG_VALUE_BOX = 1 };
    factor rows within the device's LDS) it is one persistent launch per
    batch with each structure's atoms staged in LDS; larger structures take
    the binned path (atoms binned per (structure, channel, z plane), one
-   workgroup per plane).  MFMA: binned path whose plane kernel evaluates
-   the separable factorisation (§III-A, §IV-C) of each plane as a
-   matrix-core contraction over the plane's atoms with float32
-   accumulation: for bf16 grids on factors rounded to bf16; for float32
-   grids on factors split into fp16 pairs (hi + lo, three products per
-   step), accurate to the FP32 bar (rel-L2 about 3e-6 against the FP64
-   definition, where the binned WINDOW form reaches about 1e-7); meant for
-   large, dense structures.  AUTO picks WINDOW when the structure fits,
-   else MFMA.  The binned path needs a
-   workspace (pg_workspace_size) and does not take per-structure spacings;
-   under MFMA, a plane holding more than 2048 z images of one channel
-   (pg_plan_info.atom_capacity) is reported as PG_E_CAPACITY through
-   pg_get_device_error and left as zeros; the binned WINDOW form has no such
-   limit (atom_capacity 0) but holds at most 32 tiles of 32 x 32 voxels per
-   (y, x) plane (PG_E_UNSUPPORTED beyond).  The binned path needs
-   D <= 4096. */
+   workgroup per plane).  MFMA: binned path whose plane kernels evaluate
+   the separable factorisation (§III-A, §IV-C) of each 32 x 32 tile of a
+   plane as a matrix-core contraction over the plane's images that meet
+   that tile (atoms binned per (structure, channel, 32 x 32 tile column)),
+   with float32 accumulation: for bf16 grids on bf16 factors (phi_z phi_y
+   formed in float32 and rounded once); for float32 grids on float32
+   factors (exact float32 products, rel-L2 about 1e-7 against the FP64
+   definition); meant for large, dense structures.  It takes any number of
+   atoms per plane (pg_plan_info.atom_capacity 0) but needs at most 32768
+   (tile column, z) keys per channel (tiles_x tiles_y D, e.g. 128^3) and
+   at most 16 tiles of factor slots per atom and axis; AUTO falls back to
+   the binned WINDOW form, then to PLAIN, where it does not apply.  AUTO
+   picks WINDOW when the structure fits, else MFMA.  The binned path needs
+   a workspace (pg_workspace_size) and does not take per-structure
+   spacings; the binned WINDOW form holds at most 32 tiles of 32 x 32
+   voxels per (y, x) plane (PG_E_UNSUPPORTED beyond).  The binned path
+   needs D <= 4096. */
 enum { PG_FORM_AUTO = 0, PG_FORM_PLAIN = 1, PG_FORM_WINDOW = 2, PG_FORM_MFMA = 3 };
 
 /* Grid description (all fields host values). */
@@ -335,8 +336,8 @@ int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch,
    x) and not less than any later one, so a plateau of equal maxima yields
    its first voxel.  The peaks of structure b are written in raster order
    (channel, z, y, x) from index offsets_out[b] on: xyz_out (capacity x 3
-   float32) receives the voxel centre o + (i + 1/2) h evaluated in double
-   and rounded once to float32 (o, h from origins / spacings, B x 3 device
+   float32) receives the exact voxel centre o + (i + 1/2) h rounded once to
+   float32 (formed from float-float terms; o, h from origins / spacings, B x 3 device
    arrays, when not NULL, else from desc), types_out (capacity int32) the
    channel.  offsets_out (B + 1 int32, device) receives the CSR bounds, each
    clamped to capacity; *n_found (device int64) the total number of peaks,
@@ -366,8 +367,9 @@ int pg_reversal_workspace_size(const pg_ctx *ctx, const pg_grid_desc *desc,
    grad_xyz and xyz_update may be NULL (not written); xyz_update may be
    batch->xyz itself (update in place).  On the molecule window form the
    forward kernel forms the residual and the loss as it goes (G' is never
-   stored; per-lane FP32 partial sums, FP64 across a workgroup); other forms
-   store G' in residual and then form both in one pass (FP64 partial sums).
+   stored; per-lane FP32 partial sums, float-float sums across a
+   workgroup); other forms store G' in residual and then form both in one
+   pass (float-float partial sums).  No step uses FP64 on the GPU.
    residual may be NULL on the molecule window form without weights: no
    residual grid is written (half the HBM traffic of the step) and the
    adjoint forms 2 (G' - T) at each voxel of an atom's window, summing G'

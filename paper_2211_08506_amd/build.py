@@ -29,6 +29,9 @@ SOURCES = ["pg_api.cpp", "pg_window.hip", "pg_plain.hip", "pg_adjoint.hip", "pg_
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # MFMA accumulators in ordinary VGPRs (gfx950 reads and writes them
+          # there): no copies to and from AGPRs around every MFMA
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1",
           "-Wall", "-Wno-unused-result", "-Wno-unused-value", "-I", os.path.join(ROOT, "include")]
 
 

@@ -352,24 +352,39 @@ struct Plan {
     bool crystal = false;     // large-structure path (bins + plane kernel)
     int block = 256, grid = 1, per_cu = 0, vec = 1, nt = 1, unroll = 1;
     int a_cap = 8, row_stride = 4, mask_words = 1;
-    int bin_cap = 0;
     size_t lds = 0;           // dynamic LDS bytes of one workgroup
     size_t ws = 0;            // workspace bytes
     // binned-path workspace layout (byte offsets) and sizes
     size_t ws_bcount = 0, ws_mcount = 0, ws_mstart = 0, ws_list = 0;
-    size_t ws_zlist = 0, ws_ecount = 0, ws_prange = 0, ws_bmap = 0, ws_xop = 0, ws_yop = 0;
+    size_t ws_zlist = 0, ws_ecount = 0, ws_prange = 0;
+    size_t ws_xval = 0, ws_yval = 0, ws_tcl = 0, ws_zstart = 0;
     long long op_blocks = 0;
     int nblk = 0;
+    int sx_max = 0, sy_max = 0, ntx = 0, nty = 0, zwin = 0;
 };
 
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Most voxels of one axis an atom's window can span: floor(2 rc / h) + 1
+// centres lie within rc of a point (+2 for rounding), never more than the
+// axis holds; the whole axis without a cutoff.
+int window_voxels(const pg_grid_desc *d, const pg_batch *b, int axis, int N)
+{
+    if (d->cutoff_k == 0.f)
+        return N;
+    double rc = 0.0;
+    for (int t = 0; t < n_sig_of(d, b); ++t)
+        rc = std::max(rc, (double)rc_of(d, t));
+    return (int)std::min<double>(N, std::floor(2.0 * rc / (double)d->spacing[axis]) + 3.0);
+}
+
 // Binned path: workspace layout (window records | per-block channel counts
 // | per-structure channel counts | their scan | channel partition | z-sorted
-// images | per-run image counts | per-plane image ranges | operand block map
-// | operands (MFMA form: bf16, or float for fp32 grids)) and the plane
-// kernel's LDS.
+// images | per-run image counts | per-plane image ranges | MFMA form: phi_x
+// and phi_y factor slots per atom (bf16, or float for fp32 grids) |
+// tile-column lists | their bounds | per-run longest z window and largest
+// |weight|) and the plane kernel's LDS.
 int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, int form, Plan &P)
 {
     if (b->spacings)
@@ -380,9 +395,6 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
         return PG_E_UNSUPPORTED;
     P.crystal = true;
     P.form = form;
-    // the MFMA form stages phi_z of a plane's z images in LDS; the vector
-    // form streams them (no limit)
-    P.bin_cap = form == PG_FORM_MFMA ? MFMA_BIN_CAP : 0;
     P.lds = crystal_plane_lds(form, d->H, d->W);
     const int max_lds = ctx ? ctx->max_lds : 65536;
     if (P.lds > (size_t)max_lds)
@@ -412,22 +424,38 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
     off += align256((size_t)nmc * 4);
     P.ws_prange = off;
     off += align256((size_t)nmc * d->D * 8);
-    P.ws_bmap = off;
-    off += align256((size_t)P.op_blocks * 4);
-    P.ws_xop = P.ws_yop = off;
-    if (form == PG_FORM_MFMA) {
-        // bf16 operands for bf16 grids; float operands (split into fp16
-        // pairs in the plane kernel) for fp32 grids
-        const size_t esz = d->out_dtype == PG_OUT_F32 ? 4 : 2;
-        off += align256((size_t)P.op_blocks * d->W * 32 * esz);
-        P.ws_yop = off;
-        off += align256((size_t)P.op_blocks * d->H * 32 * esz);
-    }
-    P.ws = off;
     const long long nb = nmc * d->D;
     P.block = 256;
     P.vec = 1;
-    const long long blocks = form == PG_FORM_MFMA ? nb * ((d->H + 127) / 128) * ((d->W + 127) / 128) : nb;
+    long long blocks = nb;
+    if (form == PG_FORM_MFMA) {
+        P.ntx = (d->W + 31) / 32;
+        P.nty = (d->H + 31) / 32;
+        if ((long long)P.ntx * P.nty * d->D > 32768)   // the tile sort's LDS key counters
+            return PG_E_UNSUPPORTED;
+        const bool per = d->periodic == PG_CELL_ORTHO;
+        P.sx_max = crystal_axis_slots(d->W, window_voxels(d, b, 0, d->W), per);
+        P.sy_max = crystal_axis_slots(d->H, window_voxels(d, b, 1, d->H), per);
+        P.zwin = window_voxels(d, b, 2, d->D);
+        // tile-column entries: run r's lists start at entry 32 run_block(r) SS
+        const long long ss = (long long)P.sx_max * P.sy_max;
+        const long long n_tcl = 32 * P.op_blocks * ss;
+        if (P.sx_max > 16 || P.sy_max > 16 || n_tcl > 0xffffffffLL)   // slots packed in 4 bits
+            return PG_E_UNSUPPORTED;
+        // slots: bf16 for bf16 grids, float (split into fp16 pairs in the
+        // plane kernel) for fp32 grids
+        P.ws_xval = off;
+        off += align256((size_t)b->n_atoms * P.sx_max * 32 * crystal_slot_bytes(d->out_dtype, 0));
+        P.ws_yval = off;
+        off += align256((size_t)b->n_atoms * P.sy_max * 32 * crystal_slot_bytes(d->out_dtype, 1));
+        P.ws_tcl = off;
+        off += align256((size_t)n_tcl * sizeof(TileEntry));
+        P.ws_zstart = off;   // (D + 1) words per list: 4 bytes per 1024 output voxels
+        off += align256((size_t)nmc * P.ntx * P.nty * (d->D + 1) * 4);
+        const int zp = crystal_tile_planes(d->out_dtype);
+        blocks = nmc * P.nty * ((P.ntx + 1) / 2) * ((d->D + 2 * zp - 1) / (2 * zp));
+    }
+    P.ws = off;
     if (blocks * P.block > 0xffffffffLL)   // grid size limit of one launch
         return PG_E_UNSUPPORTED;
     P.grid = (int)blocks;
@@ -524,8 +552,23 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
     if (sphere && (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)))
         return PG_E_UNSUPPORTED;
     P.form = form;
-    if (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits))
-        return crystal_plan(ctx, d, b, form, P);
+    if (form == PG_FORM_MFMA || (form == PG_FORM_WINDOW && !fits)) {
+        const int vec = P.vec;
+        s = crystal_plan(ctx, d, b, form, P);
+        if (s != PG_E_UNSUPPORTED || d->form != PG_FORM_AUTO)
+            return s;
+        // AUTO on a request the chosen binned form does not serve (plane too
+        // large for its tile bookkeeping, per-structure spacings, ...): the
+        // other binned form, else the plain form
+        P = Plan();
+        P.vec = vec;
+        s = crystal_plan(ctx, d, b, form == PG_FORM_MFMA ? PG_FORM_WINDOW : PG_FORM_MFMA, P);
+        if (s != PG_E_UNSUPPORTED)
+            return s;
+        P = Plan();
+        P.vec = vec;
+        form = P.form = PG_FORM_PLAIN;
+    }
     if (form == PG_FORM_PLAIN) {
         P.ws = (size_t)b->n_atoms * sizeof(AtomWindow);
         P.ws = (P.ws + 255) & ~(size_t)255;
@@ -657,12 +700,16 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         q.zlist = (ZEntry *)(ws + P.ws_zlist);
         q.ecount = (uint32_t *)(ws + P.ws_ecount);
         q.prange = (uint32_t *)(ws + P.ws_prange);
-        q.bmap = (uint32_t *)(ws + P.ws_bmap);
-        q.xop = (uint16_t *)(ws + P.ws_xop);
-        q.yop = (uint16_t *)(ws + P.ws_yop);
-        q.op_blocks = P.op_blocks;
+        q.xval = ws + P.ws_xval;
+        q.yval = ws + P.ws_yval;
+        q.tcl = (TileEntry *)(ws + P.ws_tcl);
+        q.zstart = (uint32_t *)(ws + P.ws_zstart);
         q.nblk = P.nblk;
-        q.bin_cap = P.bin_cap;
+        q.zwin = P.zwin;
+        q.sx_max = P.sx_max;
+        q.sy_max = P.sy_max;
+        q.ntx = P.ntx;
+        q.nty = P.nty;
         return launch_crystal(p, q, P.form, d->out_dtype, P.lds, s);
     }
     return launch_window(p, d->out_dtype, P.vec, P.unroll, P.block, P.grid, P.lds, s);
@@ -976,7 +1023,7 @@ int pg_plan(const pg_ctx *ctx, const pg_grid_desc *desc, const pg_batch *batch, 
     info->unroll = mol_window ? P.unroll : 0;
     info->per_cu = mol_window ? P.per_cu : 0;
     if (P.crystal)
-        info->atom_capacity = P.bin_cap;
+        info->atom_capacity = 0;   // the binned forms take any number of atoms per plane
     info->binned = P.crystal ? 1 : 0;
     return PG_OK;
 }

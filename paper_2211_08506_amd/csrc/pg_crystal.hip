@@ -34,33 +34,21 @@
 //            4 x 4 block of voxels over its tile's images.
 // Both forms sum each voxel's atoms in an order fixed by the input alone
 // (z-window start, then list order), so results are bitwise reproducible.
+#include <type_traits>
+
 #include "pg_device.hpp"
 #include "pg_launch.hpp"
 
 namespace pg {
 
 constexpr int PREP_BLOCK = 256; // atoms per prep / place block
-constexpr int KC = 32;          // atoms per contraction step
-constexpr int ST = 128;         // MFMA super-tile edge (y and x)
-constexpr int OPROW = 40;       // staged operand row: 32 images + 8 bf16 of padding
+constexpr int KC = 32;          // images per step of the vector form
 
 __global__ void cr_clear_kernel(uint32_t *a, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         a[i] = 0u;
-}
-
-// Two arrays in one launch: [0, na) of a, then [0, nb) of b.
-__global__ void cr_clear2_kernel(uint32_t *a, long long na, uint32_t *b, long long nb)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb;
-         i += (long long)gridDim.x * blockDim.x) {
-        if (i < na)
-            a[i] = 0u;
-        else
-            b[i - na] = 0u;
-    }
 }
 
 // Per-structure counts are aggregated in LDS when the block's atoms span
@@ -96,6 +84,109 @@ __device__ __forceinline__ float image_weight(const GridParams &p, int atom, int
     return p.weights ? p.weights[(size_t)atom * p.C + c] : 1.f;
 }
 
+__device__ __forceinline__ uint16_t bf16_bits(float v)
+{
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// Slot value storage: bf16 bits (the bf16 contraction) or float (the
+// split-fp16 contraction).
+__device__ __forceinline__ void op_store(uint16_t *p, float v) { *p = bf16_bits(v); }
+__device__ __forceinline__ void op_store(float *p, float v) { *p = v; }
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// The window ranges of one atom on axis ax (0 = x, 1 = y), ascending and
+// disjoint (images in increasing lattice order).
+struct AxisWin {
+    int n;
+    int lo[MAX_IMAGES], hi[MAX_IMAGES];
+};
+
+__device__ __forceinline__ AxisWin axis_win(const AtomWindow &w, int ax)
+{
+    AxisWin a;
+    a.n = ax == 0 ? w.n[0] : w.n[1];
+#pragma unroll
+    for (int r = 0; r < MAX_IMAGES; ++r) {
+        a.lo[r] = ax == 0 ? w.lo[0][r] : w.lo[1][r];
+        a.hi[r] = ax == 0 ? w.hi[0][r] : w.hi[1][r];
+    }
+    return a;
+}
+
+// Factor slot s of an axis: the s-th of the 32-voxel tiles its ranges meet
+// (ascending, each tile once), or -1 past the last.
+__device__ __forceinline__ int slot_tile(const AxisWin &a, int s)
+{
+    int last = -1;
+#pragma unroll
+    for (int r = 0; r < MAX_IMAGES; ++r) {
+        if (r < a.n) {
+            const int t0 = max(a.lo[r] >> 5, last + 1), t1 = a.hi[r] >> 5;
+            if (t1 >= t0) {
+                if (s <= t1 - t0)
+                    return t0 + s;
+                s -= t1 - t0 + 1;
+                last = t1;
+            }
+        }
+    }
+    return -1;
+}
+
+// Factor slots of the MFMA form: per listed atom and axis x or y, per
+// 32-voxel tile its windows meet (ascending), the 32 values phi(32 tile + j),
+// zero outside the windows and past the grid edge.  Eight lanes per (atom,
+// axis), four values each per slot, so one wave fills eight atom-axes; the
+// atoms' records are read once.
+template <typename YT, typename XT>
+__global__ void __launch_bounds__(256) cr_slot_kernel(GridParams p, CrystalParams q)
+{
+    const int lane = threadIdx.x & 63, grp = lane >> 3, j8 = lane & 7;
+    const long long id = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8 + grp;
+    const long long a = id >> 1;
+    const int ax = (int)(id & 1);
+    if (a >= live_atoms(p))
+        return;
+    const AtomWindow &w = q.table[a];
+    if (listed_type(w) < 0)
+        return;
+    const AxisWin aw = axis_win(w, ax);
+    float bh[MAX_IMAGES], bl[MAX_IMAGES];
+#pragma unroll
+    for (int r = 0; r < MAX_IMAGES; ++r) {
+        bh[r] = ax == 0 ? w.bh[0][r] : w.bh[1][r];
+        bl[r] = ax == 0 ? w.bl[0][r] : w.bl[1][r];
+    }
+    const int t = w.type;
+    const float inv2s2 = p.inv2s2[t], isq2s = p.isq2s[t], h = p.h[ax];
+    const int S = ax == 0 ? q.sx_max : q.sy_max;
+    XT *outx = (XT *)q.xval + (size_t)a * S * 32;
+    YT *outy = (YT *)q.yval + (size_t)a * S * 32;
+    const bool box = p.box != 0;
+    for (int s = 0; s < S; ++s) {
+        const int tile = slot_tile(aw, s);
+        if (tile < 0)
+            break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = j8 + 8 * i, v = 32 * tile + j;
+            float val = 0.f;
+#pragma unroll
+            for (int r = 0; r < MAX_IMAGES; ++r)
+                if (r < aw.n && v >= aw.lo[r] && v <= aw.hi[r])
+                    val = factor1d(box, bh[r], bl[r], h, v, inv2s2, isq2s);
+            if (ax == 0)
+                op_store(outx + (size_t)s * 32 + j, val);
+            else
+                op_store(outy + (size_t)s * 32 + j, val);
+        }
+    }
+}
+
 // Three threads per atom (wave group q of the block finds axis q of the
 // block's PREP_BLOCK atoms: the exact window search is the long part) build
 // the block's window records in LDS; the block then writes them out as one
@@ -116,23 +207,25 @@ __global__ void __launch_bounds__(3 * PREP_BLOCK) cr_prep_kernel(GridParams p, C
     }
     const long long a0 = (long long)blockIdx.x * PREP_BLOCK;
     const long long a1 = min(p.n_atoms, a0 + PREP_BLOCK) - 1;
-    const int m_first = structure_of(p.offsets, p.n_mol, a0);
-    const int m_last = structure_of(p.offsets, p.n_mol, a1);
+    // every wave finds the block's first and last structures (64-ary search)
+    const int m_first = structure_of_wave(p.offsets, p.n_mol, a0);
+    const int m_last = structure_of_wave(p.offsets, p.n_mol, a1);
     const bool local = m_last - m_first < PREP_SPAN;
     const int ax = tid / PREP_BLOCK, al = tid - ax * PREP_BLOCK;
     const long long a = a0 + al;
     const bool live = a < live_atoms(p);
     if (live) {
         int n;
-        const int m = write_atom_axis(p, a, ax, srec + al, n);
+        const int m = write_atom_axis(p, a, ax, srec + al, n,
+                                      structure_in(p.offsets, m_first, m_last, a));
         sn[ax][al] = n;
         if (ax == 0)
             sm[al] = m;
     }
     __syncthreads();
+    const long long n_live = live_atoms(p) - a0;
+    const int nrec = (int)(n_live < PREP_BLOCK ? (n_live > 0 ? n_live : 0) : PREP_BLOCK);
     {
-        const long long n_live = live_atoms(p) - a0;
-        const int nrec = (int)(n_live < PREP_BLOCK ? (n_live > 0 ? n_live : 0) : PREP_BLOCK);
         typedef uint32_t u4 __attribute__((ext_vector_type(4)));
         constexpr int R16 = (int)(sizeof(AtomWindow) / 16);
         static_assert(sizeof(AtomWindow) % 16 == 0, "record copy in 16-byte pieces");
@@ -230,10 +323,10 @@ __global__ void __launch_bounds__(PREP_BLOCK) cr_place_kernel(GridParams p, Crys
 // the 8 XCDs in turn; remap so that each XCD runs a contiguous stretch of
 // planes (consecutive z of one structure and channel share their atoms'
 // factor rows in that XCD's L2).  A bijection on [0, gridDim.x).
-__device__ __forceinline__ long long xcd_block()
+__device__ __forceinline__ unsigned xcd_block()
 {
     const unsigned G = gridDim.x, full = G & ~7u, b = blockIdx.x;
-    return b < full ? (long long)(b & 7u) * (full >> 3) + (b >> 3) : (long long)b;
+    return b < full ? (b & 7u) * (full >> 3) + (b >> 3) : b;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,451 +481,488 @@ __global__ void __launch_bounds__(1024) cr_zsort_kernel(GridParams p, CrystalPar
     }
     if (tid == 0)
         q.ecount[mc] = n_img;
-    const long long b0 = run_block(q, mc), nb = (n_img + 31) / 32;
-    for (long long i = tid; i < nb; i += nt)
-        q.bmap[b0 + i] = (uint32_t)mc + 1u;
 }
 
-__device__ __forceinline__ uint16_t bf16_bits(float v)
-{
-    return __builtin_bit_cast(uint16_t, (__bf16)v);
-}
 
-// Operand element storage: bf16 bits (the bf16 contraction; the image's
-// weight folded into phi_y) or float (the split-fp16 contraction; the weight
-// is applied with phi_z in the plane kernel).
-__device__ __forceinline__ void op_store(uint16_t *p, float v) { *p = bf16_bits(v); }
-__device__ __forceinline__ void op_store(float *p, float v) { *p = v; }
-
-// One workgroup per operand block: phi_x and phi_y of its 32 images over
-// the whole x and y axes, laid out [block][row][32 images] so that a
-// 16-byte load is one MFMA operand fragment (bf16) or one staging piece
-// (float).  The block is first cleared with 16-byte stores; then 8 threads
-// per image write the image's window elements only (zeros elsewhere;
-// images past the run's end stay zero).
-template <typename OT>
-__global__ void __launch_bounds__(256) cr_operand_kernel(GridParams p, CrystalParams q)
-{
-    const long long gb = blockIdx.x;
-    const uint32_t tag = q.bmap[gb];
-    if (tag == 0u)
-        return;
-    const size_t mc = tag - 1u;
-    const int c = (int)(mc / (size_t)p.n_mol);
-    const long long b0 = run_block(q, mc);
-    const int tid = threadIdx.x, kl = tid & 31, rg = tid >> 5;
-    const long long k = (gb - b0) * 32 + kl;
-    const int W = p.W, H = p.H;
-    constexpr int CH = 32 * (int)sizeof(OT) / 16;   // 16-byte pieces per row
-    OT *xop = (OT *)q.xop, *yop = (OT *)q.yop;
-    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-    u4 *xz = (u4 *)(xop + (size_t)gb * W * 32);
-    u4 *yz = (u4 *)(yop + (size_t)gb * H * 32);
-    for (int i = tid; i < W * CH; i += 256)
-        xz[i] = u4{0u, 0u, 0u, 0u};
-    for (int i = tid; i < H * CH; i += 256)
-        yz[i] = u4{0u, 0u, 0u, 0u};
-    __threadfence_block();
-    __syncthreads();
-    if (k >= (long long)q.ecount[mc])
-        return;
-    const int atom = q.zlist[32 * b0 + k].atom;
-    const AtomWindow &w = q.table[atom];
-    const int ti = image_type(p, q, atom, c);
-    const float inv2s2 = p.inv2s2[ti], isq2s = p.isq2s[ti];
-    const float wgt = sizeof(OT) == 2 ? image_weight(p, atom, c) : 1.f;
-    const bool box = p.box != 0;
-    OT *xo = xop + (size_t)gb * W * 32 + kl;
-    OT *yo = yop + (size_t)gb * H * 32 + kl;
-    for (int r = 0; r < w.n[0]; ++r) {
-        const float bh = w.bh[0][r], bl = w.bl[0][r];
-        for (int v = w.lo[0][r] + rg; v <= w.hi[0][r]; v += 8)
-            op_store(xo + (size_t)v * 32, factor1d(box, bh, bl, p.h[0], v, inv2s2, isq2s));
+// Items of one channel-partition entry for the tile-column lists: each z
+// range r of the atom (a z image) with each (y tile, x tile) pair its
+// windows meet, enumerated r-major, then y, then x.
+struct ItemWalk {
+    AxisWin wy, wx;
+    uint32_t z[MAX_IMAGES];
+    int r, sy, sx, ty, tx;
+    bool live;
+    __device__ __forceinline__ void settle()
+    {
+        // skip empty z ranges; live <=> (r, sy, sx) names an item
+        int nr = MAX_IMAGES;
+#pragma unroll
+        for (int k = MAX_IMAGES - 1; k >= 0; --k)
+            if (k >= r && range_hi(z[k]) >= range_lo(z[k]))
+                nr = k;
+        r = nr;
+        live = r < MAX_IMAGES && ty >= 0 && tx >= 0;
     }
-    for (int r = 0; r < w.n[1]; ++r) {
-        const float bh = w.bh[1][r], bl = w.bl[1][r];
-        for (int v = w.lo[1][r] + rg; v <= w.hi[1][r]; v += 8)
-            op_store(yo + (size_t)v * 32, factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s) * wgt);
+    __device__ __forceinline__ void start(const ListEntry &e, const AtomWindow &w)
+    {
+        wx = axis_win(w, 0);
+        wy = axis_win(w, 1);
+#pragma unroll
+        for (int k = 0; k < MAX_IMAGES; ++k)
+            z[k] = e.z[k];
+        r = sy = sx = 0;
+        ty = slot_tile(wy, 0);
+        tx = slot_tile(wx, 0);
+        settle();
     }
-}
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-// One workgroup (4 waves) per (structure, channel, z, super-tile); wave w
-// owns the 64 x 64 quadrant (w / 2, w % 2) of the 128 x 128 super-tile as
-// 2 x 2 MFMA tiles of 32 x 32.  The plane's images are the contiguous range
-// [first, end) of its run's z order, taken in whole 32-image operand blocks
-// (images of a block outside the plane get phi_z = 0).
-// The plane of this workgroup: its coordinates, its run's operand blocks
-// [kb0, kb0 + nkb) and phi_z of its images in gzs (with weighted channels
-// times the image's weight when fold_weight), ending with a barrier.
-struct PlaneItem {
-    int sx, sy, z, c, m, kb0, nkb;
-    long long rb;
+    __device__ __forceinline__ void next()
+    {
+        tx = slot_tile(wx, ++sx);
+        if (tx < 0) {
+            sx = 0;
+            tx = slot_tile(wx, 0);
+            ty = slot_tile(wy, ++sy);
+            if (ty < 0) {
+                sy = 0;
+                ty = slot_tile(wy, 0);
+                ++r;
+            }
+        }
+        settle();
+    }
+    __device__ __forceinline__ uint32_t zs() const
+    {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int k = 0; k < MAX_IMAGES; ++k)
+            if (k == r)
+                v = z[k];
+        return v;
+    }
 };
 
-__device__ __forceinline__ PlaneItem mfma_plane_begin(const GridParams &p, const CrystalParams &q,
-                                                      float *gzs, bool fold_weight)
+// One workgroup per run (its stretch of the channel partition): every z
+// image of the run goes into the list of each 32 x 32 (y, x) tile column
+// its windows meet, the lists sorted by the image's z start -- a counting
+// sort on the key (tile column, z start), D keys per column: per-wave key
+// counts, a scan over (key, wave), then each wave places its part, equal
+// keys within 64 entries ranked by a match over the key bits.  The scan
+// gives each list's z boundaries directly: zstart[tc][z] = the first entry
+// of key (tc, z), zstart[tc][D] = the list's end.  Dynamic LDS: waves x ntc
+// x D words.
+__global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalParams q)
 {
-    const int C = p.C, D = p.D, H = p.H, W = p.W;
-    const int nsx = (W + ST - 1) / ST, nsy = (H + ST - 1) / ST;
-    PlaneItem P;
-    long long b = xcd_block();
-    P.sx = (int)(b % nsx);
-    b /= nsx;
-    P.sy = (int)(b % nsy);
-    b /= nsy;
-    P.z = (int)(b % D);
-    b /= D;
-    P.c = (int)(b % C);
-    P.m = (int)(b / C);
-    const int tid = threadIdx.x;
-    const size_t mc = (size_t)P.c * p.n_mol + P.m;
-    const uint32_t first = q.prange[((size_t)mc * D + P.z) * 2];
-    const uint32_t end = q.prange[((size_t)mc * D + P.z) * 2 + 1];
-    const uint32_t n_img = q.ecount[mc];
-    P.kb0 = (int)(first / 32);
-    P.nkb = first < end ? (int)((end + 31) / 32) - P.kb0 : 0;
-    if (P.nkb * 32 > min(q.bin_cap, MFMA_BIN_CAP)) {
-        if (tid == 0 && P.sx == 0 && P.sy == 0)
-            raise_error(p.err, PG_E_CAPACITY, P.m);
-        P.nkb = 0;
-    }
-    P.rb = run_block(q, mc);
-    const float hz = p.h[2];
-    for (int i = tid; i < P.nkb * 32; i += blockDim.x) {
-        const uint32_t k = (uint32_t)P.kb0 * 32 + i;
-        float g = 0.f;
-        if (k < n_img) {
-            const ZEntry ze = q.zlist[32 * P.rb + k];
-            if (P.z >= range_lo(ze.range) && P.z <= range_hi(ze.range)) {
-                const int ti = image_type(p, q, ze.atom, P.c);
-                g = factor1d(p.box != 0, ze.bh, ze.bl, hz, P.z, p.inv2s2[ti], p.isq2s[ti]);
-                if (fold_weight)
-                    g *= image_weight(p, ze.atom, P.c);
-            }
+    extern __shared__ uint32_t tls[];
+    __shared__ uint32_t tsum[1024];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = blockDim.x >> 6, nt = blockDim.x;
+    const size_t mc = blockIdx.x;
+    const int D = p.D, ntc = q.ntx * q.nty, K = ntc * D;
+    uint32_t *cnt = tls;   // [wave][K]: counts, then cursors
+    const uint32_t start = q.mstart[mc], n = q.mcount[mc];
+    const uint32_t base = (uint32_t)(32ll * run_block(q, mc) * (long long)(q.sx_max * q.sy_max));
+    for (int i = tid; i < nw * K; i += nt)
+        cnt[i] = 0u;
+    __syncthreads();
+    const uint32_t part = (n + nw - 1) / nw;
+    const uint32_t pb = min(n, part * wave), pe = min(n, pb + part);
+    uint32_t *cw = cnt + (size_t)wave * K;
+    const int ntx = q.ntx;
+    for (uint32_t i = pb + lane; i < pe; i += 64) {
+        const ListEntry le = q.list[start + i];
+        ItemWalk iw;
+        iw.start(le, q.table[le.atom]);
+        while (iw.live) {
+            atomicAdd(&cw[(iw.ty * ntx + iw.tx) * D + range_lo(iw.zs())], 1u);
+            iw.next();
         }
-        gzs[i] = g;
     }
     __syncthreads();
-    return P;
+    // key totals and their exclusive scan: a contiguous segment of keys per
+    // thread, the segment sums scanned across the workgroup
+    const int seg = (K + nt - 1) / nt, kb = min(K, tid * seg), ke = min(K, kb + seg);
+    uint32_t ssum = 0;
+    for (int k = kb; k < ke; ++k)
+        for (int w = 0; w < nw; ++w)
+            ssum += cnt[(size_t)w * K + k];
+    tsum[tid] = ssum;
+    __syncthreads();
+    for (int d = 1; d < nt; d <<= 1) {
+        const uint32_t v = tid >= d ? tsum[tid - d] : 0u;
+        __syncthreads();
+        tsum[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = base + tsum[tid] - ssum;
+    for (int k = kb; k < ke; ++k) {
+        const int tc = k / D, z = k - tc * D;
+        uint32_t *zs = q.zstart + (mc * ntc + tc) * (size_t)(D + 1);
+        zs[z] = run;
+        for (int w = 0; w < nw; ++w) {   // counts -> per-wave cursors
+            const uint32_t v = cnt[(size_t)w * K + k];
+            cnt[(size_t)w * K + k] = run;
+            run += v;
+        }
+        if (z == D - 1)
+            zs[D] = run;
+    }
+    __syncthreads();
+    int kbits = 0;
+    while ((1 << kbits) < K)
+        ++kbits;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (uint32_t i0 = pb; i0 < pe; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        ItemWalk iw;
+        iw.live = false;
+        ListEntry le;
+        le.atom = 0;
+        if (i < pe) {
+            le = q.list[start + i];
+            iw.start(le, q.table[le.atom]);
+        }
+        // one item per lane per round; equal keys ranked by lane
+        while (__ballot(iw.live) != 0ull) {
+            const uint32_t key = iw.live ? (uint32_t)((iw.ty * ntx + iw.tx) * D + range_lo(iw.zs())) : 0u;
+            unsigned long long m = __ballot(iw.live);
+            for (int b = 0; b < kbits; ++b) {
+                const unsigned long long mb = __ballot(iw.live && ((key >> b) & 1u));
+                m &= ((key >> b) & 1u) ? mb : ~mb;
+            }
+            if (iw.live) {
+                const uint32_t rank = (uint32_t)__popcll(m & below);
+                const uint32_t cur = cw[key];
+                TileEntry te;
+                te.atom = le.atom;
+                const uint32_t zr = iw.zs();
+                te.zs = (uint32_t)range_lo(zr) | ((uint32_t)range_hi(zr) << 12) |
+                        ((uint32_t)iw.sy << 24) | ((uint32_t)iw.sx << 28);
+                te.bh = 0.f;
+                te.bl = 0.f;
+#pragma unroll
+                for (int k = 0; k < MAX_IMAGES; ++k)
+                    if (k == iw.r) {
+                        te.bh = le.bh[k];
+                        te.bl = le.bl[k];
+                    }
+                q.tcl[cur + rank] = te;
+                if (rank == 0)
+                    cw[key] = cur + (uint32_t)__popcll(m);
+                iw.next();
+            }
+        }
+    }
 }
 
-// Store a wave's 64 x 64 quadrant -- 2 x 2 MFMA tiles of 32 x 32, element
-// (i, j, e) given by val -- at rows yq.., columns xq.. of an H x W plane.
-// Lane l holds column l % 32 of rows 8 (e / 4) + 4 (l / 32) + e % 4 of each
-// tile, so one store instruction writes 32 contiguous elements per
-// half-wave.  A quadrant that lies inside the plane takes no bounds tests.
-template <typename T, typename F>
-__device__ __forceinline__ void store_quadrant(T *out, int H, int W, int yq, int xq, bool nt, F val)
+// ---------------------------------------------------------------------------
+// MFMA plane tiles
+// ---------------------------------------------------------------------------
+// Workgroup (4 waves) = (run, tile row ty, tile pair tp, plane group zq);
+// wave w owns the 32 x 32 tile (ty, 2 tp + w % 2) of the ZP planes from
+// z0 = ZP (2 zq + w / 2) on (two neighbouring tiles make full 128-byte rows
+// of a bf16 plane; neighbouring planes share their images, so one wave
+// contracts the images of its ZP planes together).  The wave's entries are
+// those of its tile column's list whose z start lies in
+// [z0 - zwin + 1, z0 + ZP - 1] (zwin bounds every z window; an entry whose
+// window misses a plane gets phi_z = 0 there), taken 64 at a time, one per
+// lane; their factor-slot rows are loaded before the first MFMA step.
+// Every entry is taken in list order, so each voxel's sum has a fixed order.
+constexpr int KS = 16;    // entries per bf16 MFMA step
+constexpr int KCH = 64;   // entries per chunk: one list entry per lane
+
+__device__ __forceinline__ int entry_zlo(uint32_t zs) { return (int)(zs & 0xfffu); }
+__device__ __forceinline__ int entry_zhi(uint32_t zs) { return (int)((zs >> 12) & 0xfffu); }
+
+struct TileItem {
+    size_t mc;
+    int c, m, z0, ty, tx;
+};
+
+template <int ZP>
+__device__ __forceinline__ TileItem tile_item(const GridParams &p, const CrystalParams &q)
 {
-    const int lane = threadIdx.x & 63;
-    if (yq + 64 <= H && xq + 64 <= W) {
-        T *o = out + (size_t)(yq + 4 * (lane >> 5)) * W + xq + (lane & 31);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const float v[1] = {val(i, j, e)};
-                    store_vec<T, 1>(o + (size_t)(32 * i + 8 * (e >> 2) + (e & 3)) * W + 32 * j, v, nt);
-                }
+    const unsigned ntp = (unsigned)(q.ntx + 1) / 2, nzq = (unsigned)(p.D + 2 * ZP - 1) / (2 * ZP);
+    unsigned b = xcd_block();
+    TileItem it;
+    const int zq = (int)(b % nzq);
+    b /= nzq;
+    const int tp = (int)(b % ntp);
+    b /= ntp;
+    it.ty = (int)(b % (unsigned)q.nty);
+    b /= (unsigned)q.nty;
+    it.mc = (size_t)b;
+    it.c = (int)(b / (unsigned)p.n_mol);
+    it.m = (int)(b % (unsigned)p.n_mol);
+    const int w = (int)(threadIdx.x >> 6);
+    it.tx = 2 * tp + (w & 1);
+    it.z0 = ZP * (2 * zq + (w >> 1));
+    return it;
+}
+
+// The wave's range [first, end) of its tile column's list.
+template <int ZP>
+__device__ __forceinline__ void tile_range(const GridParams &p, const CrystalParams &q,
+                                           const TileItem &it, uint32_t &first, uint32_t &end)
+{
+    first = end = 0u;
+    if (it.tx >= q.ntx || it.z0 >= p.D)
         return;
+    const uint32_t *zs =
+        q.zstart + (it.mc * (size_t)(q.ntx * q.nty) + it.ty * q.ntx + it.tx) * (size_t)(p.D + 1);
+    first = zs[max(0, it.z0 - q.zwin + 1)];
+    end = zs[min(it.z0 + ZP, p.D)];
+}
+
+// One list entry per lane: phi_z of its image at each of the wave's planes
+// (times the channel weight; 0 where its z window misses the plane, or past
+// the range) and the indices of its y and x factor slots.  inv2s2_c,
+// isq2s_c: the channel's constants, used when channels are not weighted
+// (the image's type is then the channel).
+template <int ZP>
+struct LaneImage {
+    float gz[ZP];
+    uint32_t yslot, xslot;
+};
+
+template <int ZP>
+__device__ __forceinline__ LaneImage<ZP> lane_image(const GridParams &p, const CrystalParams &q,
+                                                    uint32_t e, uint32_t end, int z0, int c,
+                                                    float inv2s2_c, float isq2s_c)
+{
+    LaneImage<ZP> li;
+#pragma unroll
+    for (int k = 0; k < ZP; ++k)
+        li.gz[k] = 0.f;
+    li.yslot = li.xslot = 0u;
+    if (e < end) {
+        const TileEntry te = q.tcl[e];
+        const int zlo = entry_zlo(te.zs), zhi = min(entry_zhi(te.zs), p.D - 1);
+        float inv2s2 = inv2s2_c, isq2s = isq2s_c, wgt = 1.f;
+        if (p.weights) {
+            const int ti = q.table[te.atom].type;
+            inv2s2 = p.inv2s2[ti];
+            isq2s = p.isq2s[ti];
+            wgt = p.weights[(size_t)te.atom * p.C + c];
+        }
+#pragma unroll
+        for (int k = 0; k < ZP; ++k) {
+            const int z = z0 + k;
+            if (z >= zlo && z <= zhi)
+                li.gz[k] = factor1d(p.box != 0, te.bh, te.bl, p.h[2], z, inv2s2, isq2s) * wgt;
+        }
+        li.yslot = (uint32_t)te.atom * (uint32_t)q.sy_max + ((te.zs >> 24) & 15u);
+        li.xslot = (uint32_t)te.atom * (uint32_t)q.sx_max + (te.zs >> 28);
     }
+    return li;
+}
+
+// A wave's 32 x 32 tile (accumulators: lane l holds column l % 32 of rows
+// 8 (e / 4) + 4 (l / 32) + e % 4) goes through the wave's LDS buffer as T,
+// then out in 16-byte pieces, whole 32-element row segments.  Rows and
+// columns past the plane edge are not written; unaligned rows fall back to
+// element stores.
+template <typename T>
+__device__ __forceinline__ void store_tile(T *out, int H, int W, int y0, int x0, bool nt,
+                                           const f32x16 &acc, T *ls)
+{
+    constexpr int LROW = 32 + 16 / (int)sizeof(T);   // padded LDS row (elements)
+    constexpr int EPL = 16 / (int)sizeof(T);         // elements per 16-byte piece
+    constexpr int LPR = 32 / EPL;                    // lanes per row
+    constexpr int RPI = 64 / LPR;                    // rows per store instruction
+    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the buffer's last reads are done
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int e = 0; e < 16; ++e)
+        ls[(8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)) * LROW + (lane & 31)] = (T)acc[e];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const bool vec = ((size_t)W * sizeof(T)) % 16 == 0 && ((uintptr_t)out & 15) == 0;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+    for (int k = 0; k < 32 / RPI; ++k) {
+        const int r = RPI * k + lane / LPR, cs = EPL * (lane % LPR);
+        const int y = y0 + r, x = x0 + cs;
+        if (y >= H || x >= W)
+            continue;
+        const T *src = ls + r * LROW + cs;
+        T *dst = out + (size_t)y * W + x;
+        if (vec && x + EPL <= W) {
+            typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+            const u4 v = *(const u4 *)src;
+            if (nt)
+                __builtin_nontemporal_store(v, (u4 *)dst);
+            else
+                *(u4 *)dst = v;
+        } else {
+            for (int u = 0; u < EPL && x + u < W; ++u)
+                dst[u] = src[u];
+        }
+    }
+}
+
+// bf16 grids: per 16-entry step, lane l stages the image pair 2 (l / 8),
+// 2 (l / 8) + 1 of the step on rows (columns) 4 (l % 8) .. + 3: per plane the
+// four rows of phi_z phi_y (FP32 products, each pair of images rounded to
+// bf16 by one conversion) and, once per step, of phi_x go into the wave's
+// LDS buffer as [row][16 entries] (4 bytes per row and pair); the wave then
+// reads its fragments and each plane takes one v_mfma_f32_32x32x16_bf16.
+// The y slots are float, the x slots bf16.
+constexpr int AST = 24;   // staged row: 16 entries + 8 bf16 of padding (48 B)
+
+template <int ZP>
+__global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, CrystalParams q)
+{
+    constexpr int WBUF = 2 * 32 * AST;   // bf16 per wave: staging 2 x 32 x AST >= store 32 x 40
+    __shared__ __attribute__((aligned(16))) __bf16 lds[4][WBUF];
+    const TileItem it = tile_item<ZP>(p, q);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t first, end;
+    tile_range<ZP>(p, q, it, first, end);
+    if (it.tx >= q.ntx || it.z0 >= p.D)
+        return;
+    const float inv2s2_c = p.inv2s2[it.c], isq2s_c = p.isq2s[it.c];
+    uint32_t *As = (uint32_t *)lds[wave], *Bs = (uint32_t *)(lds[wave] + 32 * AST);
+    const int ip = lane >> 3, g = lane & 7;   // image pair, row group
+    const int fo = (lane & 31) * AST + 8 * (lane >> 5);
+    const float *yv = (const float *)q.yval;
+    const __bf16 *xv = (const __bf16 *)q.xval;
+    f32x16 acc[ZP];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int y = yq + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int x = xq + 32 * j + (lane & 31);
-                if (y < H && x < W) {
-                    const float v[1] = {val(i, j, e)};
-                    store_vec<T, 1>(out + (size_t)y * W + x, v, nt);
+    for (int k = 0; k < ZP; ++k)
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            acc[k][e] = 0.f;
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+    for (uint32_t c0 = first; c0 < end; c0 += KCH) {
+        const LaneImage<ZP> li = lane_image<ZP>(p, q, c0 + lane, end, it.z0, it.c, inv2s2_c, isq2s_c);
+        const int nst = (int)((min((uint32_t)KCH, end - c0) + KS - 1) / KS);
+        float4 ya[KCH / KS][2];
+        b4 xb[KCH / KS][2];
+        float gg[KCH / KS][2][ZP];
+#pragma unroll
+        for (int st = 0; st < KCH / KS; ++st)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int src = KS * st + 2 * ip + u;
+#pragma unroll
+                for (int k = 0; k < ZP; ++k)
+                    gg[st][u][k] = __shfl(li.gz[k], src, 64);
+                const uint32_t ys = (uint32_t)__shfl((int)li.yslot, src, 64);
+                const uint32_t xs = (uint32_t)__shfl((int)li.xslot, src, 64);
+                ya[st][u] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    xb[st][u][r] = (__bf16)0.f;
+                if (st < nst && c0 + (uint32_t)src < end) {
+                    ya[st][u] = *(const float4 *)(yv + (size_t)ys * 32 + 4 * g);
+                    xb[st][u] = *(const b4 *)(xv + (size_t)xs * 32 + 4 * g);
                 }
             }
+#pragma unroll
+        for (int st = 0; st < KCH / KS; ++st) {
+            if (st >= nst)
+                break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const b2 pb = {xb[st][0][r], xb[st][1][r]};
+                Bs[((4 * g + r) * AST + 2 * ip) / 2] = __builtin_bit_cast(uint32_t, pb);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            const bf16x8 bf = *(const bf16x8 *)((const __bf16 *)Bs + fo);
+            const float y0[4] = {ya[st][0].x, ya[st][0].y, ya[st][0].z, ya[st][0].w};
+            const float y1[4] = {ya[st][1].x, ya[st][1].y, ya[st][1].z, ya[st][1].w};
+#pragma unroll
+            for (int k = 0; k < ZP; ++k) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const f2 pr = {y0[r] * gg[st][0][k], y1[r] * gg[st][1][k]};
+                    As[((4 * g + r) * AST + 2 * ip) / 2] =
+                        __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, b2));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                const bf16x8 af = *(const bf16x8 *)((const __bf16 *)As + fo);
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, acc[k], 0, 0, 0);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ZP; ++k) {
+        const int z = it.z0 + k;
+        if (z >= p.D)
+            break;
+        __bf16 *out = (__bf16 *)p.out + (((size_t)it.m * p.C + it.c) * p.D + z) * (size_t)p.H * p.W;
+        store_tile<__bf16>(out, p.H, p.W, 32 * it.ty, 32 * it.tx, p.nt_store != 0, acc[k], lds[wave]);
+    }
 }
 
-__global__ void __launch_bounds__(256) cr_mfma_kernel(GridParams p, CrystalParams q)
+// fp32 grids: v_mfma_f32_32x32x2_f32 takes one value of A and one of B per
+// lane -- lane l: entry l / 32 of a pair of entries, row (A) or column (B)
+// l % 32 -- which is one float of that entry's y or x slot: the slots are
+// read straight into the operands (no transposition), A scaled by phi_z of
+// each plane in FP32.  Exact FP32 products, FP32 accumulation; per pair of
+// entries one MFMA per plane.
+template <int ZP>
+__global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalParams q)
 {
-    using T = __bf16;
-    __shared__ __attribute__((aligned(16))) float gzs[MFMA_BIN_CAP];   // phi_z per image
-    // two staging buffers of [phi_z phi_y, phi_x][super-tile row][32 images],
-    // rows padded to OPROW elements so that the fragment reads (lanes on
-    // consecutive rows) fall in distinct banks
-    __shared__ __attribute__((aligned(16))) __bf16 ops[2][2][ST * OPROW];
-    const int C = p.C, D = p.D, H = p.H, W = p.W;
-    const PlaneItem PI = mfma_plane_begin(p, q, gzs, false);
-    const int z = PI.z, c = PI.c, m = PI.m, kb0 = PI.kb0, nkb = PI.nkb;
-    const long long rb = PI.rb;
-    const int y0 = PI.sy * ST, x0 = PI.sx * ST;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    f32x16 acc[2][2];
+    constexpr int PB = 8;   // entry pairs whose operands are loaded together
+    __shared__ __attribute__((aligned(16))) float lds[4][32 * (32 + 4)];
+    const TileItem it = tile_item<ZP>(p, q);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t first, end;
+    tile_range<ZP>(p, q, it, first, end);
+    if (it.tx >= q.ntx || it.z0 >= p.D)
+        return;
+    const float inv2s2_c = p.inv2s2[it.c], isq2s_c = p.isq2s[it.c];
+    const int j = lane & 31, hi = lane >> 5;
+    const float *yv = (const float *)q.yval, *xv = (const float *)q.xval;
+    f32x16 acc[ZP];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int k = 0; k < ZP; ++k)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int e = 0; e < 16; ++e)
+            acc[k][e] = 0.f;
+    for (uint32_t c0 = first; c0 < end; c0 += KCH) {
+        const LaneImage<ZP> li = lane_image<ZP>(p, q, c0 + lane, end, it.z0, it.c, inv2s2_c, isq2s_c);
+        const int npair = (int)((min((uint32_t)KCH, end - c0) + 1) / 2);
+        for (int p0 = 0; p0 < npair; p0 += PB) {
+            float av[PB], bv[PB], gg[PB][ZP];
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                acc[i][j][e] = 0.f;
-    const int qy = (wave >> 1) * 64, qx = (wave & 1) * 64;
-    const int ko = 8 * (lane >> 5);
-    const __bf16 *yop = (const __bf16 *)q.yop, *xop = (const __bf16 *)q.xop;
-    // Staging: the workgroup copies each 32-image operand block's rows of
-    // the super-tile to LDS once -- phi_y scaled by phi_z of the plane
-    // (rounded once to bf16), and phi_x -- so every operand element is
-    // fetched and scaled once per workgroup instead of once per wave that
-    // uses it.  Thread t moves the 16-byte chunk (t % 4) of local rows t / 4
-    // and t / 4 + 64 of both operands; rows past the plane edge copy the last
-    // row instead (they only feed outputs that are never stored).
-    const int srow = tid >> 2, skq = 8 * (tid & 3);
-    int sy_[2], sx_[2];
+            for (int u = 0; u < PB; ++u) {
+                const int src = 2 * (p0 + u) + hi;   // < 64 as p0 + u < 32
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        sy_[r] = min(y0 + srow + 64 * r, H - 1);
-        sx_[r] = min(x0 + srow + 64 * r, W - 1);
-    }
-    // two register sets: block kb + 2 is fetched while block kb is
-    // contracted and block kb + 1 (fetched one step earlier) is staged
-    bf16x8 ga[2][2], gb[2][2];
-    auto fetch = [&](int kb, bf16x8 (&fa)[2], bf16x8 (&fb)[2]) {
-        const size_t blk = (size_t)(rb + kb0 + kb);
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            fa[r] = *(const bf16x8 *)(yop + (blk * H + sy_[r]) * 32 + skq);
-            fb[r] = *(const bf16x8 *)(xop + (blk * W + sx_[r]) * 32 + skq);
-        }
-    };
-    auto stage = [&](int kb, int buf, const bf16x8 (&fa)[2], const bf16x8 (&fb)[2]) {
-        const float4 g0 = *(const float4 *)(gzs + kb * 32 + skq);
-        const float4 g1 = *(const float4 *)(gzs + kb * 32 + skq + 4);
-        const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            bf16x8 av;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                av[e] = (__bf16)((float)fa[r][e] * g[e]);
-            *(bf16x8 *)(ops[buf][0] + (srow + 64 * r) * OPROW + skq) = av;
-            *(bf16x8 *)(ops[buf][1] + (srow + 64 * r) * OPROW + skq) = fb[r];
-        }
-    };
-    auto contract = [&](int buf) {
-        const __bf16 *As = ops[buf][0], *Bs = ops[buf][1];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int kk = 16 * h + ko;
-            bf16x8 af[2], bf[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                af[i] = *(const bf16x8 *)(As + (qy + 32 * i + (lane & 31)) * OPROW + kk);
-                bf[i] = *(const bf16x8 *)(Bs + (qx + 32 * i + (lane & 31)) * OPROW + kk);
+                for (int k = 0; k < ZP; ++k)
+                    gg[u][k] = __shfl(li.gz[k], src, 64);
+                const uint32_t ys = (uint32_t)__shfl((int)li.yslot, src, 64);
+                const uint32_t xs = (uint32_t)__shfl((int)li.xslot, src, 64);
+                av[u] = bv[u] = 0.f;
+                if (p0 + u < npair && c0 + (uint32_t)src < end) {
+                    av[u] = yv[(size_t)ys * 32 + j];
+                    bv[u] = xv[(size_t)xs * 32 + j];
+                }
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int u = 0; u < PB; ++u) {
+                if (p0 + u >= npair)
+                    break;
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                for (int k = 0; k < ZP; ++k)
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u] * gg[u][k], bv[u], acc[k], 0, 0, 0);
+            }
         }
-    };
-    // one step: fetch kb + 2 (clamped: past the end it refetches the last
-    // block), contract kb, stage kb + 1 into the other buffer (last read
-    // before the previous barrier), barrier
-    auto step = [&](int kb, bf16x8 (&fa_next)[2], bf16x8 (&fb_next)[2],
-                    const bf16x8 (&fa_stage)[2], const bf16x8 (&fb_stage)[2]) {
-        fetch(min(kb + 2, nkb - 1), fa_next, fb_next);
-        contract(kb & 1);
-        if (kb + 1 < nkb)
-            stage(kb + 1, (kb + 1) & 1, fa_stage, fb_stage);
-        __syncthreads();
-    };
-    if (nkb > 0) {
-        fetch(0, ga[0], gb[0]);
-        fetch(min(1, nkb - 1), ga[1], gb[1]);
-        stage(0, 0, ga[0], gb[0]);
     }
-    __syncthreads();
-    int kb = 0;
-    for (; kb + 1 < nkb; kb += 2) {
-        step(kb, ga[0], gb[0], ga[1], gb[1]);
-        step(kb + 1, ga[1], gb[1], ga[0], gb[0]);
+#pragma unroll
+    for (int k = 0; k < ZP; ++k) {
+        const int z = it.z0 + k;
+        if (z >= p.D)
+            break;
+        float *out = (float *)p.out + (((size_t)it.m * p.C + it.c) * p.D + z) * (size_t)p.H * p.W;
+        store_tile<float>(out, p.H, p.W, 32 * it.ty, 32 * it.tx, p.nt_store != 0, acc[k], lds[wave]);
     }
-    if (kb < nkb)
-        step(kb, ga[0], gb[0], ga[1], gb[1]);
-
-    T *out = (T *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
-    store_quadrant(out, H, W, y0 + qy, x0 + qx, p.nt_store != 0,
-                   [&](int i, int j, int e) { return acc[i][j][e]; });
 }
 
-// ---------------------------------------------------------------------------
-// Split-fp16 MFMA form (fp32 grids at FP32 accuracy)
-// ---------------------------------------------------------------------------
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-constexpr int SPROW = 24;             // staged row: 16 images + 8 halves of padding
-constexpr float SPLIT_UP = 4096.f;    // scale of the low parts (2^12)
-
-// v = hi + lo / 2^12 to about 2^-22 |v|: hi = fp16(v), lo = fp16((v - hi) 2^12)
-// (v - hi is exact in FP32; the scaled low part stays in the fp16 normal
-// range for every v the plane kernel splits).
-__device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
-{
-    hi = (_Float16)v;
-    lo = (_Float16)((v - (float)hi) * SPLIT_UP);
-}
-
-// One workgroup (4 waves) per (structure, channel, z, super-tile), as the
-// bf16 form, on FP32 operands (phi_x, and phi_y without the weight).  Per
-// 16-image step the workgroup stages A = s phi_z w phi_y and B = phi_x in
-// LDS, each split as hi + lo / 2^12 into fp16 pairs; s = 2^e is chosen per
-// plane from the largest |phi_z w| so that every A stays within the fp16
-// range.  Each 32 x 32 tile takes three v_mfma_f32_32x32x16_f16 per step:
-// P += Ahi Bhi, Q += Ahi Blo + Alo Bhi; the plane is (P + Q / 2^12) / s.  The
-// dropped Alo Blo and the splits leave about 2^-21 relative error per
-// product, against 2^-8 for the bf16 operands.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) cr_mfma_split_kernel(GridParams p, CrystalParams q)
-{
-    __shared__ __attribute__((aligned(16))) float gzs[MFMA_BIN_CAP];   // phi_z w per image
-    __shared__ float wmax[4];
-    // two staging buffers of [Ahi, Alo, Bhi, Blo][super-tile row][16 images]
-    __shared__ __attribute__((aligned(16))) _Float16 sops[2][4][ST * SPROW];
-    const int H = p.H, W = p.W, C = p.C, D = p.D;
-    const PlaneItem PI = mfma_plane_begin(p, q, gzs, true);
-    const int z = PI.z, c = PI.c, m = PI.m, kb0 = PI.kb0;
-    const long long rb = PI.rb;
-    const int nst = 2 * PI.nkb;   // 16-image steps
-    const int y0 = PI.sy * ST, x0 = PI.sx * ST;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    // plane scale: s = 2^(14 - e) for the largest |phi_z w| = f 2^e, f in [0.5, 1)
-    float mx = 0.f;
-    for (int i = tid; i < nst * 16; i += blockDim.x)
-        mx = fmaxf(mx, fabsf(gzs[i]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        mx = fmaxf(mx, __shfl_xor(mx, off));
-    if (lane == 0)
-        wmax[wave] = mx;
-    __syncthreads();
-    mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-    int ex = 0;
-    if (mx > 0.f)
-        (void)frexpf(mx, &ex);
-    ex = max(ex, -110);   // s and 1 / s stay normal floats for the tiniest weights
-    const float sc = ldexpf(1.f, 14 - ex), unsc = ldexpf(1.f, ex - 14);
-
-    f32x16 accp[2][2], accq[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                accp[i][j][e] = 0.f;
-                accq[i][j][e] = 0.f;
-            }
-    const int qy = (wave >> 1) * 64, qx = (wave & 1) * 64;
-    const int ko = 8 * (lane >> 5);
-    const float *yop = (const float *)q.yop, *xop = (const float *)q.xop;
-    // staging: thread t moves images 4 (t % 4) .. + 3 of the step for local
-    // rows t / 4 and t / 4 + 64 of both operands; rows past the plane edge
-    // copy the last row (they only feed outputs that are never stored)
-    const int srow = tid >> 2, skq = 4 * (tid & 3);
-    int sy_[2], sx_[2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        sy_[r] = min(y0 + srow + 64 * r, H - 1);
-        sx_[r] = min(x0 + srow + 64 * r, W - 1);
-    }
-    float4 ga[2][2], gb[2][2];
-    auto fetch = [&](int st, float4 (&fa)[2], float4 (&fb)[2]) {
-        const size_t blk = (size_t)(rb + kb0 + (st >> 1));
-        const int off = 16 * (st & 1) + skq;
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            fa[r] = *(const float4 *)(yop + (blk * H + sy_[r]) * 32 + off);
-            fb[r] = *(const float4 *)(xop + (blk * W + sx_[r]) * 32 + off);
-        }
-    };
-    auto stage = [&](int st, int buf, const float4 (&fa)[2], const float4 (&fb)[2]) {
-        const float4 g4 = *(const float4 *)(gzs + st * 16 + skq);
-        const float g[4] = {g4.x * sc, g4.y * sc, g4.z * sc, g4.w * sc};
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const float av[4] = {fa[r].x * g[0], fa[r].y * g[1], fa[r].z * g[2], fa[r].w * g[3]};
-            const float bv[4] = {fb[r].x, fb[r].y, fb[r].z, fb[r].w};
-            f16x4 ah, al, bh, bl;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                _Float16 h, l;
-                split16(av[e], h, l);
-                ah[e] = h;
-                al[e] = l;
-                split16(bv[e], h, l);
-                bh[e] = h;
-                bl[e] = l;
-            }
-            const int o = (srow + 64 * r) * SPROW + skq;
-            *(f16x4 *)(sops[buf][0] + o) = ah;
-            *(f16x4 *)(sops[buf][1] + o) = al;
-            *(f16x4 *)(sops[buf][2] + o) = bh;
-            *(f16x4 *)(sops[buf][3] + o) = bl;
-        }
-    };
-    auto contract = [&](int buf) {
-        f16x8 ahf[2], alf[2], bhf[2], blf[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int ra = (qy + 32 * i + (lane & 31)) * SPROW + ko;
-            const int rbx = (qx + 32 * i + (lane & 31)) * SPROW + ko;
-            ahf[i] = *(const f16x8 *)(sops[buf][0] + ra);
-            alf[i] = *(const f16x8 *)(sops[buf][1] + ra);
-            bhf[i] = *(const f16x8 *)(sops[buf][2] + rbx);
-            blf[i] = *(const f16x8 *)(sops[buf][3] + rbx);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                accp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahf[i], bhf[j], accp[i][j], 0, 0, 0);
-                accq[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahf[i], blf[j], accq[i][j], 0, 0, 0);
-                accq[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alf[i], bhf[j], accq[i][j], 0, 0, 0);
-            }
-    };
-    // as the bf16 form: fetch step st + 2 (clamped), contract st, stage
-    // st + 1 into the other buffer, barrier
-    auto step = [&](int st, float4 (&fa_next)[2], float4 (&fb_next)[2],
-                    const float4 (&fa_stage)[2], const float4 (&fb_stage)[2]) {
-        fetch(min(st + 2, nst - 1), fa_next, fb_next);
-        contract(st & 1);
-        if (st + 1 < nst)
-            stage(st + 1, (st + 1) & 1, fa_stage, fb_stage);
-        __syncthreads();
-    };
-    if (nst > 0) {
-        fetch(0, ga[0], gb[0]);
-        fetch(min(1, nst - 1), ga[1], gb[1]);
-        stage(0, 0, ga[0], gb[0]);
-    }
-    __syncthreads();
-    int st = 0;
-    for (; st + 1 < nst; st += 2) {
-        step(st, ga[0], gb[0], ga[1], gb[1]);
-        step(st + 1, ga[1], gb[1], ga[0], gb[0]);
-    }
-    if (st < nst)
-        step(st, ga[0], gb[0], ga[1], gb[1]);
-
-    float *out = (float *)p.out + (((size_t)m * C + c) * D + z) * (size_t)H * W;
-    store_quadrant(out, H, W, y0 + qy, x0 + qx, p.nt_store != 0, [&](int i, int j, int e) {
-        return (accp[i][j][e] + accq[i][j][e] * (1.f / SPLIT_UP)) * unsc;
-    });
-}
+constexpr int ZP_BF16 = 4;   // planes per wave of the bf16 tile kernel
+constexpr int ZP_F32 = 4;    // planes per wave of the fp32 tile kernel
 
 // FP32 vector-ALU form: one workgroup (256 threads) per (structure, channel,
 // z); the plane's images are the range [first, end) of the run's z order.
@@ -853,11 +983,11 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
     float *gx = (float *)smem;                    // [KC][W32] phi_x
     float *gy = gx + KC * W32;                    // [KC][H32] phi_z(z) phi_y
     uint32_t *tmask = (uint32_t *)(gy + KC * H32);   // [ntiles] images meeting each tile
-    long long b = xcd_block();
-    const int z = (int)(b % D);
-    b /= D;
-    const int c = (int)(b % C);
-    const int m = (int)(b / C);
+    unsigned b = xcd_block();
+    const int z = (int)(b % (unsigned)D);
+    b /= (unsigned)D;
+    const int c = (int)(b % (unsigned)C);
+    const int m = (int)(b / (unsigned)C);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const size_t mc = (size_t)c * p.n_mol + m;
     const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
@@ -969,10 +1099,17 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
 
 size_t crystal_plane_lds(int form, int H, int W)
 {
-    if (form == PG_FORM_MFMA)   // all static: phi_z per image
+    if (form == PG_FORM_MFMA)   // all static: the waves' staging and store buffers
         return 0;
     const int W32 = (W + 31) & ~31, H32 = (H + 31) & ~31;
     return (size_t)KC * (W32 + H32) * sizeof(float) + (size_t)(W32 / 32) * (H32 / 32) * 4;
+}
+
+int crystal_axis_slots(int N, int wmax, bool periodic)
+{
+    const int tiles = (N + 31) / 32;
+    const int per_range = std::min(tiles, (std::max(wmax, 1) - 1 + 31) / 32 + 1);
+    return std::min(tiles, (periodic ? MAX_IMAGES : 1) * per_range);
 }
 
 // waves of the z-sort workgroup: up to 16, within 64 KB of LDS counters
@@ -1000,6 +1137,28 @@ int crystal_window_runs(int H, int W)
     return 0;
 }
 
+// waves of the tile-sort workgroup: up to 16, within 128 KB of LDS key
+// counters (K = tile columns x D keys, at most 32768)
+int crystal_tsort_waves(int K)
+{
+    return std::max(1, std::min(16, 32768 / std::max(K, 1)));
+}
+
+size_t crystal_tsort_lds(int K)
+{
+    return (size_t)crystal_tsort_waves(K) * K * sizeof(uint32_t);
+}
+
+int crystal_slot_bytes(int out_dtype, int axis)
+{
+    return (out_dtype == PG_OUT_F32 || axis == 1) ? 4 : 2;
+}
+
+int crystal_tile_planes(int out_dtype)
+{
+    return out_dtype == PG_OUT_F32 ? ZP_F32 : ZP_BF16;
+}
+
 int crystal_prep_blocks(long long n_atoms)
 {
     return (int)((n_atoms + PREP_BLOCK - 1) / PREP_BLOCK);
@@ -1011,9 +1170,8 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     if (p.n_mol == 0)
         return hipSuccess;
     const long long nmc = (long long)p.n_mol * p.C;
-    const unsigned clear_grid = (unsigned)std::min<long long>((nmc + q.op_blocks + 255) / 256, 65535);
-    hipLaunchKernelGGL(cr_clear2_kernel, dim3(clear_grid), dim3(256), 0, s, q.mcount, nmc, q.bmap,
-                       (long long)q.op_blocks);
+    hipLaunchKernelGGL(cr_clear_kernel, dim3((unsigned)std::min<long long>((nmc + 255) / 256, 65535)),
+                       dim3(256), 0, s, q.mcount, nmc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -1035,33 +1193,51 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    const size_t zl = crystal_zsort_lds(p.D);
-    if (zl > 65536) {
-        e = hipFuncSetAttribute((const void *)cr_zsort_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl);
-        if (e != hipSuccess)
-            return e;
-    }
-    hipLaunchKernelGGL(cr_zsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_zsort_waves(p.D)), zl,
-                       s, p, q);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
-    if (form == PG_FORM_MFMA) {
-        if (out_dtype == PG_OUT_F32)
-            hipLaunchKernelGGL(cr_operand_kernel<float>, dim3((unsigned)q.op_blocks), dim3(256), 0, s, p, q);
-        else
-            hipLaunchKernelGGL(cr_operand_kernel<uint16_t>, dim3((unsigned)q.op_blocks), dim3(256), 0, s,
-                               p, q);
-        if ((e = hipGetLastError()) != hipSuccess)
-            return e;
-    }
     const void *k;
     long long grid;
     if (form == PG_FORM_MFMA) {
-        k = out_dtype == PG_OUT_F32 ? (const void *)cr_mfma_split_kernel
-                                    : (const void *)cr_mfma_kernel;
-        grid = nmc * p.D * ((p.H + ST - 1) / ST) * ((p.W + ST - 1) / ST);
+        // factor slots of every atom, then the tile-column lists of every run
+        const long long slot_blocks = (2 * p.n_atoms + 31) / 32;
+        if (slot_blocks > 0) {
+            // y slots are float in both forms (phi_z phi_y is formed in FP32);
+            // x slots bf16 for bf16 grids, float for fp32 grids
+            if (out_dtype == PG_OUT_F32)
+                hipLaunchKernelGGL((cr_slot_kernel<float, float>), dim3((unsigned)slot_blocks), dim3(256), 0,
+                                   s, p, q);
+            else
+                hipLaunchKernelGGL((cr_slot_kernel<float, uint16_t>), dim3((unsigned)slot_blocks), dim3(256),
+                                   0, s, p, q);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+        }
+        const int K = q.ntx * q.nty * p.D;
+        const size_t tl = crystal_tsort_lds(K);
+        if (tl > 65536) {
+            e = hipFuncSetAttribute((const void *)cr_tsort_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl);
+            if (e != hipSuccess)
+                return e;
+        }
+        hipLaunchKernelGGL(cr_tsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_tsort_waves(K)), tl, s,
+                           p, q);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        const int zp = out_dtype == PG_OUT_F32 ? ZP_F32 : ZP_BF16;
+        k = out_dtype == PG_OUT_F32 ? (const void *)cr_tile_f32_kernel<ZP_F32>
+                                    : (const void *)cr_tile_bf16_kernel<ZP_BF16>;
+        grid = nmc * q.nty * ((q.ntx + 1) / 2) * ((p.D + 2 * zp - 1) / (2 * zp));
     } else {
+        const size_t zl = crystal_zsort_lds(p.D);
+        if (zl > 65536) {
+            e = hipFuncSetAttribute((const void *)cr_zsort_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl);
+            if (e != hipSuccess)
+                return e;
+        }
+        hipLaunchKernelGGL(cr_zsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_zsort_waves(p.D)), zl,
+                           s, p, q);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
         const int r = crystal_window_runs(p.H, p.W);
         if (out_dtype == PG_OUT_F32)
             k = r == 1 ? (const void *)cr_window_kernel<float, 1>

@@ -484,6 +484,22 @@ __device__ __forceinline__ int structure_of(const int32_t *offsets, int n_mol, l
     return lo;
 }
 
+// structure_of within a known bracket: the last m in [lo, hi] with
+// offsets[m] <= a, given offsets[lo] <= a (the atoms of one prep block span
+// a few structures).
+__device__ __forceinline__ int structure_in(const int32_t *offsets, int lo, int hi, long long a)
+{
+    int h = hi + 1;   // invariant: offsets[lo] <= a < offsets[h] (h past the bracket: unknown)
+    while (h - lo > 1) {
+        const int mid = (lo + h) >> 1;
+        if ((long long)offsets[mid] <= a)
+            lo = mid;
+        else
+            h = mid;
+    }
+    return lo;
+}
+
 // structure_of for an atom index a that is uniform across the calling wave:
 // each round the 64 lanes probe 63 evenly spaced offsets of the bracket at
 // once, so a batch of n structures takes ceil(log64 n) dependent loads
@@ -507,15 +523,16 @@ __device__ __forceinline__ int structure_of_wave(const int32_t *offsets, int n_m
 // Exact window ranges of atom a on axis q into its record (axis 0 also
 // writes the type: -1 for a skipped atom, which also raises the device
 // error).  Returns the atom's structure; n_out = the axis's range count.
+// m_known: the atom's structure when the caller knows it, else -1.
 __device__ inline int write_atom_axis(const GridParams &p, long long a, int q, AtomWindow *w,
-                                      int &n_out)
+                                      int &n_out, int m_known = -1)
 {
     const float mu[3] = {p.xyz[3 * a], p.xyz[3 * a + 1], p.xyz[3 * a + 2]};
     const int t = p.types[a];
     const bool ok = atom_valid(mu[0], mu[1], mu[2], t, p.n_sig);
     if (!ok && q == 0)
         raise_error(p.err, PG_E_DEVICE_DATA, a);
-    const int m = structure_of(p.offsets, p.n_mol, a);
+    const int m = m_known >= 0 ? m_known : structure_of(p.offsets, p.n_mol, a);
     if (q == 0)
         w->type = ok ? t : -1;
     AxisRanges R;

@@ -34,9 +34,18 @@ hipError_t launch_plain(const GridParams &p, int out_dtype, hipStream_t s);
 size_t crystal_plane_lds(int form, int H, int W);
 int crystal_window_runs(int H, int W);
 int crystal_prep_blocks(long long n_atoms);
-// z images of one plane the MFMA plane kernel stages (static LDS)
-constexpr int MFMA_BIN_CAP = 2048;
+// Factor slots per atom on one axis of the MFMA form: the 32-voxel tiles
+// that a window of at most wmax voxels (periodic: up to 3 images) can meet.
+int crystal_axis_slots(int N, int wmax, bool periodic);
 size_t crystal_zsort_lds(int D);
+// dynamic LDS of the tile-sort workgroup (K = tile columns x D <= 32768 keys)
+size_t crystal_tsort_lds(int K);
+// planes per wave of the MFMA tile kernels (a workgroup covers two tiles of
+// two such plane groups)
+int crystal_tile_planes(int out_dtype);
+// bytes per factor-slot value of the MFMA form for this output dtype on
+// axis 0 (x) or 1 (y)
+int crystal_slot_bytes(int out_dtype, int axis);
 hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form, int out_dtype,
                           size_t lds, hipStream_t s);
 

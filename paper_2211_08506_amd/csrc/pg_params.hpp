@@ -134,12 +134,25 @@ struct ZEntry {
     float bh, bl;
 };
 
+// One entry of a tile-column list of the MFMA form: a z image of one atom
+// (its z range and the range's float-float base offset o_z - mu_z - n L_z)
+// with the slots of the column's y and x tiles among the atom's factor
+// slots.  zs packs z lo (bits 0-11), z hi (12-23), the y slot (24-27) and
+// the x slot (28-31); the lists are sorted by z lo.
+struct TileEntry {
+    int32_t atom;
+    uint32_t zs;
+    float bh, bl;
+};
+
 // Binned (large-structure) path.  Per atom: its window record; per channel:
 // the stable partition of all atoms by channel (atom index order kept),
 // which lays out every (structure, channel) pair ("run") as one contiguous
 // stretch of the list; per run, the z images sorted by window start and
-// each plane's contiguous range of them; for the MFMA form, the bf16 factor
-// operands in 32-image blocks.
+// each plane's contiguous range of them.  MFMA form: per atom, phi_x and
+// phi_y over each 32-voxel tile its windows meet ("slots", 32 values each,
+// zero outside the windows); per run and 32 x 32 (y, x) tile column, the
+// list of the run's z images whose windows meet the column, in z order.
 struct CrystalParams {
     AtomWindow *table;       // n_atoms window records
     uint32_t *bcount;        // C x nblk atoms per (channel, prep block), then their
@@ -150,12 +163,15 @@ struct CrystalParams {
     ZEntry *zlist;           // entry capacity: run r starts at entry 32 * run_block(r)
     uint32_t *ecount;        // C x n_mol z images per run
     uint32_t *prange;        // C x n_mol x D x 2: first and end image of each plane
-    uint32_t *bmap;          // per operand block: run + 1 (0: unused)
-    uint16_t *xop;           // operand blocks x W x 32 bf16: phi_x of 32 images
-    uint16_t *yop;           // operand blocks x H x 32 bf16: phi_y of 32 images
-    int64_t op_blocks;       // operand block capacity
+    // MFMA form
+    void *xval;              // n_atoms x sx_max x 32 phi_x slot values (bf16 bits or float)
+    void *yval;              // n_atoms x sy_max x 32 phi_y slot values
+    TileEntry *tcl;          // run r's tile-column lists start at entry 32 * run_block(r) * SS
+    uint32_t *zstart;        // C x n_mol x ntc x (D + 1): per list, the first entry
+                             // whose z lo is >= z, for z = 0 .. D
     int32_t nblk;            // prep blocks (PREP_BLOCK atoms each)
-    int32_t bin_cap;         // most z images of one plane the MFMA plane kernel takes
+    int32_t sx_max, sy_max;  // factor slots per atom on x and y (<= 16 each)
+    int32_t ntx, nty;        // 32-voxel tiles along x and y
+    int32_t zwin;            // bound on any z window's length (voxels)
 };
-
 }  // namespace pg

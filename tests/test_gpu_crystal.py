@@ -166,11 +166,13 @@ def test_determinism(pg, dev):
             assert torch.equal(g0, g1), form
 
 
-def test_dense_plane_capacity(pg, dev):
-    """5000 atoms of one channel within 1 A: the FP32 vector form streams a
-    plane's images and has no capacity limit; the MFMA form stages phi_z of
-    at most 2048 z images per plane -- a fuller plane is written as zeros
-    and flagged (structure index), other planes and structures unaffected."""
+@pytest.mark.parametrize("form,dtype,tol", [("window", torch.float32, F32_TOL),
+                                            ("mfma", torch.float32, F32_TOL),
+                                            ("mfma", torch.bfloat16, BF16_TOL)])
+def test_dense_plane_takes_every_image(pg, dev, form, dtype, tol):
+    """5000 atoms of one channel within 1 A (about 5000 z images in each of
+    their planes, one 32 x 32 tile column): every form takes every image of a
+    plane -- no capacity limit, no device error, oracle parity everywhere."""
     rng = np.random.default_rng(35)
     sig = [0.5, 0.5]
     xyz = np.concatenate([rng.uniform(-0.5, 0.5, size=(5000, 3)),
@@ -179,26 +181,47 @@ def test_dense_plane_capacity(pg, dev):
     b = synth.Batch(xyz, types, np.array([0, 5000, 5300], np.int32))
     dims, h, origin = (24, 24, 24), 0.25, (-3, -3, -3)
     ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, dims, h, origin)
-    say("case dense plane form=window")
+    say(f"case dense plane form={form} dtype={dtype}")
     ctx = pg.Context(0)
-    g = run(pg, dev, b, sig, dims, h, origin, torch.float32, "window", ctx=ctx)
-    assert ctx.device_error()[0] == 0
-    check("dense/window", g, ref, F32_TOL)
-    say("case dense plane form=mfma")
+    g = run(pg, dev, b, sig, dims, h, origin, dtype, form, ctx=ctx)
+    assert ctx.device_error() == (0, -1)
+    check(f"dense/{form}/{dtype}", g, ref, tol)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.bfloat16, BF16_TOL), (torch.float32, F32_TOL)])
+def test_full_size_single_channel_cell(pg, dev, dtype, tol):
+    """One periodic 20 A cell of 20000 atoms of a single type at 128^3,
+    0.16 A, under AUTO (the MFMA form): about 3200 z images per plane, all
+    of them in one channel.  Sampled voxels against the oracle, exact
+    support, no device error."""
+    rng = np.random.default_rng(41)
+    n, cell = 20000, 20.0
+    xyz = rng.uniform(0.0, cell, size=(n, 3)).astype(np.float32)
+    xyz[xyz >= np.float32(cell)] = np.float32(0.0)
+    b = synth.Batch(xyz, np.zeros(n, np.int32), np.array([0, n], np.int32))
+    sig = [0.55]
+    dims, h = (128, 128, 128), 0.16
+    say(f"case full-size single-channel cell dtype={dtype}")
+    xyz_d, types_d, offs_d = to_device(b, dev)
     ctx = pg.Context(0)
-    g = run(pg, dev, b, sig, dims, h, origin, torch.float32, "mfma", ctx=ctx)
-    code, first = ctx.device_error()
-    assert code == pg.PG_E_CAPACITY and first == 0
-    got = g.double().cpu().numpy()
-    dropped = 0
-    for z in range(dims[0]):
-        if not got[0, 0, z].any() and ref[0, 0, z].any():
-            dropped += 1                    # a plane above capacity
-        else:
-            assert errors(got[0, 0, z], ref[0, 0, z])[0] <= F32_TOL
-    assert dropped >= 1
-    assert not got[0, 1].any()
-    assert errors(got[1], ref[1])[0] <= F32_TOL
+    desc = pg.make_desc(1, dims, h, (0, 0, 0), sig, 3.0, cell, dtype, "auto")
+    bv = pg.BatchView(xyz_d, types_d, offs_d, offsets_host=b.offsets)
+    out = pg.empty_grid(desc, 1, dev)
+    plan = ctx.plan(desc, bv, out)
+    say(f"plan {plan}")
+    assert plan["form"] == "mfma" and plan["binned"] == 1
+    ctx.forward(desc, bv, out)
+    torch.cuda.synchronize()
+    assert ctx.device_error() == (0, -1)
+    idx = sample_voxels(np.random.default_rng(42), b, tuple(out.shape), (0, 0, 0), h, 6000, 6000)
+    ref = oracle.voxels_fp64(b.xyz, b.types, b.offsets, sig, dims, h, idx, (0, 0, 0), cell=cell)
+    it = torch.tensor(idx, device=dev)
+    got = out[it[:, 0], it[:, 1], it[:, 2], it[:, 3], it[:, 4]].double().cpu().numpy()
+    rel, mx = errors(got, ref)
+    say(f"[single-channel cell/{dtype} sampled {len(idx)}] rel-L2 {rel:.3e} max-abs {mx:.3e}")
+    assert rel <= tol
+    assert np.array_equal(got > 0, ref > 0)
+    assert out.float().sum().item() > 0
 
 
 def test_adjoint_large_structures(pg, dev):
