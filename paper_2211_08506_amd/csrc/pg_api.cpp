@@ -357,7 +357,7 @@ struct Plan {
     // binned-path workspace layout (byte offsets) and sizes
     size_t ws_bcount = 0, ws_mcount = 0, ws_mstart = 0, ws_list = 0;
     size_t ws_zlist = 0, ws_ecount = 0, ws_prange = 0;
-    size_t ws_xval = 0, ws_yval = 0, ws_tcl = 0, ws_zstart = 0;
+    size_t ws_tmask = 0, ws_xval = 0, ws_yval = 0, ws_tcl = 0, ws_zstart = 0;
     long long op_blocks = 0;
     int nblk = 0;
     int sx_max = 0, sy_max = 0, ntx = 0, nty = 0, zwin = 0;
@@ -433,6 +433,8 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
         P.nty = (d->H + 31) / 32;
         if ((long long)P.ntx * P.nty * d->D > 32768)   // the tile sort's LDS key counters
             return PG_E_UNSUPPORTED;
+        if (P.ntx > 32 || P.nty > 32)   // tiles met per axis as 32-bit masks
+            return PG_E_UNSUPPORTED;
         const bool per = d->periodic == PG_CELL_ORTHO;
         P.sx_max = crystal_axis_slots(d->W, window_voxels(d, b, 0, d->W), per);
         P.sy_max = crystal_axis_slots(d->H, window_voxels(d, b, 1, d->H), per);
@@ -444,6 +446,8 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
             return PG_E_UNSUPPORTED;
         // slots: bf16 for bf16 grids, float (split into fp16 pairs in the
         // plane kernel) for fp32 grids
+        P.ws_tmask = off;
+        off += align256((size_t)b->n_atoms * 2 * 4);
         P.ws_xval = off;
         off += align256((size_t)b->n_atoms * P.sx_max * 32 * crystal_slot_bytes(d->out_dtype, 0));
         P.ws_yval = off;
@@ -700,6 +704,7 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         q.zlist = (ZEntry *)(ws + P.ws_zlist);
         q.ecount = (uint32_t *)(ws + P.ws_ecount);
         q.prange = (uint32_t *)(ws + P.ws_prange);
+        q.tmask = P.form == PG_FORM_MFMA ? (uint32_t *)(ws + P.ws_tmask) : nullptr;
         q.xval = ws + P.ws_xval;
         q.yval = ws + P.ws_yval;
         q.tcl = (TileEntry *)(ws + P.ws_tcl);

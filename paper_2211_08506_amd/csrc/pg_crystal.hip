@@ -117,29 +117,10 @@ __device__ __forceinline__ AxisWin axis_win(const AtomWindow &w, int ax)
     return a;
 }
 
-// Factor slot s of an axis: the s-th of the 32-voxel tiles its ranges meet
-// (ascending, each tile once), or -1 past the last.
-__device__ __forceinline__ int slot_tile(const AxisWin &a, int s)
-{
-    int last = -1;
-#pragma unroll
-    for (int r = 0; r < MAX_IMAGES; ++r) {
-        if (r < a.n) {
-            const int t0 = max(a.lo[r] >> 5, last + 1), t1 = a.hi[r] >> 5;
-            if (t1 >= t0) {
-                if (s <= t1 - t0)
-                    return t0 + s;
-                s -= t1 - t0 + 1;
-                last = t1;
-            }
-        }
-    }
-    return -1;
-}
-
 // Factor slots of the MFMA form: per listed atom and axis x or y, per
-// 32-voxel tile its windows meet (ascending), the 32 values phi(32 tile + j),
-// zero outside the windows and past the grid edge.  Eight lanes per (atom,
+// 32-voxel tile its windows meet (ascending: the set bits of its tile mask),
+// the 32 values phi(32 tile + j), zero outside the windows and past the grid
+// edge.  Eight lanes per (atom,
 // axis), four values each per slot, so one wave fills eight atom-axes; the
 // atoms' records are read once.
 template <typename YT, typename XT>
@@ -167,10 +148,9 @@ __global__ void __launch_bounds__(256) cr_slot_kernel(GridParams p, CrystalParam
     XT *outx = (XT *)q.xval + (size_t)a * S * 32;
     YT *outy = (YT *)q.yval + (size_t)a * S * 32;
     const bool box = p.box != 0;
-    for (int s = 0; s < S; ++s) {
-        const int tile = slot_tile(aw, s);
-        if (tile < 0)
-            break;
+    uint32_t mk = q.tmask[2 * a + ax];
+    for (int s = 0; s < S && mk != 0u; ++s, mk &= mk - 1u) {
+        const int tile = __builtin_ctz(mk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int j = j8 + 8 * i, v = 32 * tile + j;
@@ -223,6 +203,16 @@ __global__ void __launch_bounds__(3 * PREP_BLOCK) cr_prep_kernel(GridParams p, C
             sm[al] = m;
     }
     __syncthreads();
+    // MFMA form: the 32-voxel tiles each listed atom's x and y windows meet
+    if (q.tmask && live && ax < 2) {
+        uint32_t mk = 0u;
+        const AtomWindow &w = srec[al];
+#pragma unroll
+        for (int r = 0; r < MAX_IMAGES; ++r)
+            if (r < w.n[ax] && w.hi[ax][r] >= w.lo[ax][r])
+                mk |= (uint32_t)((2ull << (w.hi[ax][r] >> 5)) - (1ull << (w.lo[ax][r] >> 5)));
+        q.tmask[2 * a + ax] = mk;
+    }
     const long long n_live = live_atoms(p) - a0;
     const int nrec = (int)(n_live < PREP_BLOCK ? (n_live > 0 ? n_live : 0) : PREP_BLOCK);
     {
@@ -486,49 +476,51 @@ __global__ void __launch_bounds__(1024) cr_zsort_kernel(GridParams p, CrystalPar
 
 // Items of one channel-partition entry for the tile-column lists: each z
 // range r of the atom (a z image) with each (y tile, x tile) pair its
-// windows meet, enumerated r-major, then y, then x.
-struct ItemWalk {
-    AxisWin wy, wx;
+// windows meet, enumerated r-major, then y, then x, over the atom's tile
+// bit masks; sy and sx count the set bits passed (the factor slots).
+struct MaskWalk {
+    uint32_t my, mx, cy, cx;
     uint32_t z[MAX_IMAGES];
-    int r, sy, sx, ty, tx;
+    int r, sy, sx;
     bool live;
-    __device__ __forceinline__ void settle()
+    __device__ __forceinline__ int next_range(int from) const
     {
-        // skip empty z ranges; live <=> (r, sy, sx) names an item
         int nr = MAX_IMAGES;
 #pragma unroll
         for (int k = MAX_IMAGES - 1; k >= 0; --k)
-            if (k >= r && range_hi(z[k]) >= range_lo(z[k]))
+            if (k >= from && range_hi(z[k]) >= range_lo(z[k]))
                 nr = k;
-        r = nr;
-        live = r < MAX_IMAGES && ty >= 0 && tx >= 0;
+        return nr;
     }
-    __device__ __forceinline__ void start(const ListEntry &e, const AtomWindow &w)
+    __device__ __forceinline__ void start(const ListEntry &e, uint32_t mx_, uint32_t my_)
     {
-        wx = axis_win(w, 0);
-        wy = axis_win(w, 1);
+        mx = cx = mx_;
+        my = cy = my_;
 #pragma unroll
         for (int k = 0; k < MAX_IMAGES; ++k)
             z[k] = e.z[k];
-        r = sy = sx = 0;
-        ty = slot_tile(wy, 0);
-        tx = slot_tile(wx, 0);
-        settle();
+        sy = sx = 0;
+        r = next_range(0);
+        live = r < MAX_IMAGES && mx != 0u && my != 0u;
     }
+    __device__ __forceinline__ int ty() const { return __builtin_ctz(cy); }
+    __device__ __forceinline__ int tx() const { return __builtin_ctz(cx); }
     __device__ __forceinline__ void next()
     {
-        tx = slot_tile(wx, ++sx);
-        if (tx < 0) {
+        cx &= cx - 1u;
+        ++sx;
+        if (cx == 0u) {
+            cx = mx;
             sx = 0;
-            tx = slot_tile(wx, 0);
-            ty = slot_tile(wy, ++sy);
-            if (ty < 0) {
+            cy &= cy - 1u;
+            ++sy;
+            if (cy == 0u) {
+                cy = my;
                 sy = 0;
-                ty = slot_tile(wy, 0);
-                ++r;
+                r = next_range(r + 1);
             }
         }
-        settle();
+        live = r < MAX_IMAGES;
     }
     __device__ __forceinline__ uint32_t zs() const
     {
@@ -568,12 +560,57 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
     const uint32_t pb = min(n, part * wave), pe = min(n, pb + part);
     uint32_t *cw = cnt + (size_t)wave * K;
     const int ntx = q.ntx;
-    for (uint32_t i = pb + lane; i < pe; i += 64) {
-        const ListEntry le = q.list[start + i];
-        ItemWalk iw;
-        iw.start(le, q.table[le.atom]);
+    // the wave's first CHC chunks of 64 entries (and their atoms' tile masks)
+    // stay in registers for both passes; later chunks are read again
+    constexpr int CHC = 4;
+    const int nch = (int)((pe - pb + 63) / 64);
+    ListEntry lec[CHC];
+    uint32_t mxc[CHC], myc[CHC];
+#pragma unroll
+    for (int ch = 0; ch < CHC; ++ch) {
+        const uint32_t i = pb + 64 * ch + lane;
+        lec[ch].atom = -1;
+        if (ch < nch && i < pe)
+            lec[ch] = q.list[start + i];
+    }
+#pragma unroll
+    for (int ch = 0; ch < CHC; ++ch) {
+        mxc[ch] = myc[ch] = 0u;
+        if (lec[ch].atom >= 0) {
+            mxc[ch] = q.tmask[2 * (size_t)lec[ch].atom];
+            myc[ch] = q.tmask[2 * (size_t)lec[ch].atom + 1];
+        }
+    }
+    // chunk ch of the wave's part: the lane's entry (atom -1: none) and masks
+    auto chunk = [&](int ch, ListEntry &le, uint32_t &mx, uint32_t &my) {
+#pragma unroll
+        for (int k = 0; k < CHC; ++k)
+            if (k == ch) {
+                le = lec[k];
+                mx = mxc[k];
+                my = myc[k];
+            }
+        if (ch >= CHC) {
+            const uint32_t i = pb + 64 * ch + lane;
+            le.atom = -1;
+            mx = my = 0u;
+            if (i < pe) {
+                le = q.list[start + i];
+                mx = q.tmask[2 * (size_t)le.atom];
+                my = q.tmask[2 * (size_t)le.atom + 1];
+            }
+        }
+    };
+    for (int ch = 0; ch < nch; ++ch) {
+        ListEntry le;
+        uint32_t mx, my;
+        chunk(ch, le, mx, my);
+        if (le.atom < 0)
+            continue;
+        MaskWalk iw;
+        iw.start(le, mx, my);
         while (iw.live) {
-            atomicAdd(&cw[(iw.ty * ntx + iw.tx) * D + range_lo(iw.zs())], 1u);
+            atomicAdd(&cw[(iw.ty() * ntx + iw.tx()) * D + range_lo(iw.zs())], 1u);
             iw.next();
         }
     }
@@ -611,19 +648,17 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
     while ((1 << kbits) < K)
         ++kbits;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (uint32_t i0 = pb; i0 < pe; i0 += 64) {
-        const uint32_t i = i0 + lane;
-        ItemWalk iw;
-        iw.live = false;
+    for (int ch = 0; ch < nch; ++ch) {
         ListEntry le;
-        le.atom = 0;
-        if (i < pe) {
-            le = q.list[start + i];
-            iw.start(le, q.table[le.atom]);
-        }
+        uint32_t mx, my;
+        chunk(ch, le, mx, my);
+        MaskWalk iw;
+        iw.live = false;
+        if (le.atom >= 0)
+            iw.start(le, mx, my);
         // one item per lane per round; equal keys ranked by lane
         while (__ballot(iw.live) != 0ull) {
-            const uint32_t key = iw.live ? (uint32_t)((iw.ty * ntx + iw.tx) * D + range_lo(iw.zs())) : 0u;
+            const uint32_t key = iw.live ? (uint32_t)((iw.ty() * ntx + iw.tx()) * D + range_lo(iw.zs())) : 0u;
             unsigned long long m = __ballot(iw.live);
             for (int b = 0; b < kbits; ++b) {
                 const unsigned long long mb = __ballot(iw.live && ((key >> b) & 1u));
@@ -668,7 +703,6 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
 // lane; their factor-slot rows are loaded before the first MFMA step.
 // Every entry is taken in list order, so each voxel's sum has a fixed order.
 constexpr int KS = 16;    // entries per bf16 MFMA step
-constexpr int KCH = 64;   // entries per chunk: one list entry per lane
 
 __device__ __forceinline__ int entry_zlo(uint32_t zs) { return (int)(zs & 0xfffu); }
 __device__ __forceinline__ int entry_zhi(uint32_t zs) { return (int)((zs >> 12) & 0xfffu); }
@@ -807,9 +841,11 @@ __device__ __forceinline__ void store_tile(T *out, int H, int W, int y0, int x0,
 // The y slots are float, the x slots bf16.
 constexpr int AST = 24;   // staged row: 16 entries + 8 bf16 of padding (48 B)
 
-template <int ZP>
+template <int ZP, int KCH>
 __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, CrystalParams q)
 {
+    // entries per chunk (one list entry per lane, KCH <= 64), their slot rows
+    // loaded before the chunk's first step
     constexpr int WBUF = 2 * 32 * AST;   // bf16 per wave: staging 2 x 32 x AST >= store 32 x 40
     __shared__ __attribute__((aligned(16))) __bf16 lds[4][WBUF];
     const TileItem it = tile_item<ZP>(p, q);
@@ -902,7 +938,7 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
 // read straight into the operands (no transposition), A scaled by phi_z of
 // each plane in FP32.  Exact FP32 products, FP32 accumulation; per pair of
 // entries one MFMA per plane.
-template <int ZP>
+template <int ZP, int KCH>
 __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalParams q)
 {
     constexpr int PB = 8;   // entry pairs whose operands are loaded together
@@ -961,8 +997,10 @@ __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalP
     }
 }
 
-constexpr int ZP_BF16 = 4;   // planes per wave of the bf16 tile kernel
-constexpr int ZP_F32 = 4;    // planes per wave of the fp32 tile kernel
+constexpr int ZP_BF16 = 4;    // planes per wave of the bf16 tile kernel
+constexpr int KCH_BF16 = 32;  // entries per chunk of the bf16 tile kernel
+constexpr int ZP_F32 = 4;     // planes per wave of the fp32 tile kernel
+constexpr int KCH_F32 = 64;   // entries per chunk of the fp32 tile kernel
 
 // FP32 vector-ALU form: one workgroup (256 threads) per (structure, channel,
 // z); the plane's images are the range [first, end) of the run's z order.
@@ -1223,8 +1261,8 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         const int zp = out_dtype == PG_OUT_F32 ? ZP_F32 : ZP_BF16;
-        k = out_dtype == PG_OUT_F32 ? (const void *)cr_tile_f32_kernel<ZP_F32>
-                                    : (const void *)cr_tile_bf16_kernel<ZP_BF16>;
+        k = out_dtype == PG_OUT_F32 ? (const void *)cr_tile_f32_kernel<ZP_F32, KCH_F32>
+                                    : (const void *)cr_tile_bf16_kernel<ZP_BF16, KCH_BF16>;
         grid = nmc * q.nty * ((q.ntx + 1) / 2) * ((p.D + 2 * zp - 1) / (2 * zp));
     } else {
         const size_t zl = crystal_zsort_lds(p.D);

@@ -164,6 +164,8 @@ struct CrystalParams {
     uint32_t *ecount;        // C x n_mol z images per run
     uint32_t *prange;        // C x n_mol x D x 2: first and end image of each plane
     // MFMA form
+    uint32_t *tmask;         // 2 x n_atoms: 32-voxel tiles the x (even) and y (odd) windows
+                             // meet, as bit masks (H, W <= 1024)
     void *xval;              // n_atoms x sx_max x 32 phi_x slot values (bf16 bits or float)
     void *yval;              // n_atoms x sy_max x 32 phi_y slot values
     TileEntry *tcl;          // run r's tile-column lists start at entry 32 * run_block(r) * SS
