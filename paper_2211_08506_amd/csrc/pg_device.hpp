@@ -344,11 +344,13 @@ __device__ __forceinline__ void store_vec(T *p, const float (&v)[VEC], bool nt)
                 *(unsigned short *)p = s;
             return;
         } else {
+            // pairs rounded in one conversion (element 0 in the low half)
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 #pragma unroll
             for (int k = 0; k < VEC / 2; ++k) {
-                __bf16 lo = (__bf16)v[2 * k], hi = (__bf16)v[2 * k + 1];
-                w[k] = (uint32_t)__builtin_bit_cast(unsigned short, lo) |
-                       ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+                const f2v pr = {v[2 * k], v[2 * k + 1]};
+                w[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, b2v));
             }
         }
     }

@@ -11,9 +11,10 @@
 //      channel whose z-window contains the plane (with weighted channels:
 //      of the atoms with a non-zero weight for the channel, the weights
 //      being staged in LDS too and folded into phi_z);
-//   3. streams the structure's C x D x H x W output plane by plane: each
-//      wave takes whole (c, z) planes, each lane U runs of VEC consecutive x
-//      (16 bytes each), accumulates sum_a phi_z[a][z] phi_y[a][y] phi_x[a][x..]
+//   3. streams the structure's C x D x H x W output: each wave takes whole
+//      (c, z) planes, pass by pass (a pass: U runs of VEC consecutive x, 16
+//      bytes each, per lane; its run indices serve all the wave's planes),
+//      accumulates sum_a phi_z[a][z] phi_y[a][y] phi_x[a][x..]
 //      over the plane's mask in FP32 registers and writes each run once --
 //      zeros included -- with a 16-byte store, so one store instruction of a
 //      wave covers 1 KiB of contiguous output.
@@ -87,236 +88,351 @@ __device__ __forceinline__ void load_row(const float *r, float (&v)[VEC])
     }
 }
 
-template <typename T, int VEC, int U, bool RES, bool SPH>
-__global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
+// One structure's LDS-resident state (steps 1-2).
+struct MolBuf {
+    float *rows;                  // factor rows phi_x | phi_y | phi_z per atom
+    RangeRec *rr;                 // window ranges per (atom, axis)
+    unsigned long long *masks;    // per (channel, z) plane: atoms with a factor there
+    int32_t *atype;               // type per atom, -1 for an invalid atom
+    float *wl;                    // per-atom channel weights (weighted channels)
+    float *dsq;                   // sphere: squared centre offsets beside the rows
+};
+
+__device__ __forceinline__ MolBuf mol_buf(unsigned char *base, const WindowLds &lay)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    MolBuf B;
+    B.rows = (float *)(base + lay.rows);
+    B.rr = (RangeRec *)(base + lay.ranges);
+    B.masks = (unsigned long long *)(base + lay.masks);
+    B.atype = (int32_t *)(base + lay.types);
+    B.wl = (float *)(base + lay.wts);
+    B.dsq = (float *)(base + lay.dsq);
+    return B;
+}
+
+// Barrier between the set-up steps of the group that runs them: the whole
+// workgroup, or a single wave, whose LDS accesses the hardware performs in
+// issue order (so only the compiler has to be kept from reordering them).
+template <bool WG>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (WG) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Steps 1-2 for structure m into B, run by threads t = 0 .. n-1 of the
+// group (the workgroup, or one wave).  The caller synchronises before the
+// state is read by other waves.
+template <bool SPH, bool WG>
+__device__ void mol_setup(const GridParams &p, const MolBuf &B, int m, int t, int n)
+{
     const int C = p.C, D = p.D, H = p.H, W = p.W;
     const int RS = p.row_stride;
     const int W4 = (W + 3) & ~3;
     const int MW = p.mask_words;
     const int WC = p.weights ? C : 0;
-    const WindowLds lay = window_lds_layout(p.a_cap, RS, C, D, MW, WC, SPH);
-    float *rows = (float *)(smem + lay.rows);
-    RangeRec *rr = (RangeRec *)(smem + lay.ranges);
-    unsigned long long *masks = (unsigned long long *)(smem + lay.masks);
-    int32_t *atype = (int32_t *)(smem + lay.types);
-    float *wl = (float *)(smem + lay.wts);
-    float *dsq = (float *)(smem + lay.dsq);   // sphere: squared centre offsets
-
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
     const int planes = C * D;
-    const size_t plane_elems = (size_t)H * W;
-    const size_t mol_elems = (size_t)planes * plane_elems;
-    const int chunks = (int)(plane_elems / VEC);
-    const bool nt = p.nt_store != 0;
+    const int a0 = p.offsets[m];
+    int na = p.offsets[m + 1] - a0;
+    if (na > p.a_cap || na < 0 || a0 < 0 || (long long)a0 + na > p.n_atoms) {
+        // more atoms than the declared capacity (or bad offsets): no atoms,
+        // so the structure's grid is written as zeros; sticky error
+        if (t == 0)
+            raise_error(p.err, na > p.a_cap ? PG_E_CAPACITY : PG_E_DEVICE_DATA, m);
+        na = 0;
+    }
+    float o[3], h[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        o[q] = p.origins ? p.origins[3 * (size_t)m + q] : p.o[q];
+        h[q] = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
+    }
+
+    // ---- 1. window ranges per (atom, axis); clear plane masks
+    for (int i = t; i < planes * MW; i += n)
+        B.masks[i] = 0ull;
+    for (int i = t; i < na * WC; i += n)
+        B.wl[i] = p.weights[(size_t)a0 * C + i];
+    for (int i = t; i < na * 3; i += n) {
+        const int a = i / 3, ax = i - 3 * a;
+        const size_t ga = (size_t)a0 + a;
+        const float x = p.xyz[3 * ga + 0], y = p.xyz[3 * ga + 1], zc = p.xyz[3 * ga + 2];
+        const int ty = p.types[ga];
+        const bool ok = atom_valid(x, y, zc, ty, p.n_sig);
+        RangeRec R;
+        R.n = 0;
+        if (ok) {
+            const float mu = ax == 0 ? x : (ax == 1 ? y : zc);
+            const int N = ax == 0 ? W : (ax == 1 ? H : D);
+            const float oq = ax == 0 ? o[0] : (ax == 1 ? o[1] : o[2]);
+            const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
+            const float Lq = ax == 0 ? p.L[0] : (ax == 1 ? p.L[1] : p.L[2]);
+            AxisRanges ar;
+            axis_ranges(oq, hq, N, mu, p.periodic != 0, Lq, p.rc[ty], p.cut != 0, ar);
+            R.n = ar.n;
+#pragma unroll
+            for (int r = 0; r < MAX_IMAGES; ++r) {
+                R.lo[r] = (int16_t)(r < ar.n ? ar.lo[r] : 0);
+                R.hi[r] = (int16_t)(r < ar.n ? ar.hi[r] : -1);
+                R.bh[r] = r < ar.n ? ar.bh[r] : 0.f;
+                R.bl[r] = r < ar.n ? ar.bl[r] : 0.f;
+            }
+        }
+        B.rr[i] = R;
+        if (ax == 0) {
+            B.atype[a] = ok ? ty : -1;
+            if (!ok)
+                raise_error(p.err, PG_E_DEVICE_DATA, (long long)ga);
+        }
+    }
+    group_sync<WG>();
+
+    // ---- 2. dense 1-D factor rows and (channel, z) atom masks
+    for (int e = t; e < na * RS; e += n) {
+        const int a = e / RS, j = e - a * RS;
+        int ax, i, N;
+        if (j < W4) {
+            ax = 0; i = j; N = W;
+        } else if (j < W4 + H) {
+            ax = 1; i = j - W4; N = H;
+        } else {
+            ax = 2; i = j - W4 - H; N = D;
+        }
+        const int ty = B.atype[a];
+        float v = 0.f, d2 = __builtin_huge_valf();
+        if (ty >= 0 && i < N) {
+            const RangeRec &R = B.rr[3 * a + ax];
+            const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
+            for (int r = 0; r < R.n; ++r) {
+                if (i >= R.lo[r] && i <= R.hi[r]) {
+                    v = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[ty], p.isq2s[ty]);
+                    if constexpr (SPH) {
+                        const float d = offset_at(R.bh[r], R.bl[r], hq, i);
+                        d2 = d * d;
+                    }
+                    if (ax == 2) {
+                        if (WC == 0) {
+                            atomicOr(&B.masks[(size_t)(ty * D + i) * MW + (a >> 6)],
+                                     1ull << (a & 63));
+                        } else {
+                            for (int c = 0; c < C; ++c)
+                                if (B.wl[a * WC + c] != 0.f)
+                                    atomicOr(&B.masks[(size_t)(c * D + i) * MW + (a >> 6)],
+                                             1ull << (a & 63));
+                        }
+                    }
+                }
+            }
+        }
+        B.rows[e] = v;
+        if constexpr (SPH)
+            B.dsq[e] = d2;
+    }
+}
+
+// Plane geometry of step 3.
+struct PlaneGeom {
+    int D, H, W, RS, W4, MW, WC, CW, chunks;
+    float inv_cw;
+    size_t plane_elems;
+    bool nt;
+};
+
+template <int VEC>
+__device__ __forceinline__ PlaneGeom plane_geom(const GridParams &p)
+{
+    PlaneGeom g;
+    g.D = p.D;
+    g.H = p.H;
+    g.W = p.W;
+    g.RS = p.row_stride;
+    g.W4 = (p.W + 3) & ~3;
+    g.MW = p.mask_words;
+    g.WC = p.weights ? p.C : 0;
+    g.plane_elems = (size_t)p.H * p.W;
+    g.chunks = (int)(g.plane_elems / VEC);
+    g.nt = p.nt_store != 0;
     // runs (VEC consecutive x) per row.  A run's row is floor(j / CW); the
     // float estimate (j + 1/2) / CW is within one row of it for every plane
     // the validation admits (fewer than 2^15 rows: three roundings of
     // relative size 2^-24 move a value below 2^15 by less than 2^-8), and
     // one integer comparison on each side makes it exact.
-    const int CW = W / VEC;
-    const float inv_cw = 1.0f / (float)CW;
+    g.CW = p.W / VEC;
+    g.inv_cw = 1.0f / (float)g.CW;
+    return g;
+}
+
+// The lane's U runs j0 + 64 u of one pass over a plane: row, first column,
+// and whether the run exists.  The same for every plane, so computed once
+// per pass and structure.
+template <int U>
+struct PassRuns {
+    int yq[U], xq[U];
+    bool ok[U];
+};
+
+template <int VEC, int U>
+__device__ __forceinline__ PassRuns<U> pass_runs(const PlaneGeom &g, int j0)
+{
+    PassRuns<U> R;
+    const int CW = g.CW;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = j0 + 64 * u;
+        R.ok[u] = j < g.chunks;
+        // run j starts at element j*VEC: row j / CW, column (j % CW) * VEC
+        int yy = (int)(((float)j + 0.5f) * g.inv_cw);
+        yy -= yy * CW > j ? 1 : 0;
+        yy += (yy + 1) * CW <= j ? 1 : 0;
+        R.yq[u] = R.ok[u] ? yy : 0;
+        R.xq[u] = R.ok[u] ? (j - yy * CW) * VEC : 0;
+    }
+    return R;
+}
+
+// acc (+)= gy * phi_x over the runs of one atom; FIRST: the plane's first
+// atom initialises the sums (a product, exactly what an FMA onto zero gives)
+template <int VEC, int U, bool SPH, bool FIRST>
+__device__ __forceinline__ void add_atom(const GridParams &p, const MolBuf &B, const PlaneGeom &g,
+                                         int a, int z, int pc, const PassRuns<U> &R,
+                                         float (&acc)[U][VEC])
+{
+    const float *row = B.rows + a * g.RS;
+    float gz = row[g.W4 + g.H + z];
+    if (g.WC)
+        gz *= B.wl[a * g.WC + pc];
+    float r2z = 0.f;
+    if constexpr (SPH)
+        r2z = p.rc2[B.atype[a]] - B.dsq[a * g.RS + g.W4 + g.H + z];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float gy = row[g.W4 + R.yq[u]] * gz;
+        float fx[VEC];
+        load_row<VEC>(row + R.xq[u], fx);
+        if constexpr (SPH) {
+            // keep x only inside the ball: dx^2 <= rc^2 - dz^2 - dy^2
+            const float r2 = r2z - B.dsq[a * g.RS + g.W4 + R.yq[u]];
+            float dx2[VEC];
+            load_row<VEC>(B.dsq + a * g.RS + R.xq[u], dx2);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k)
+                fx[k] = dx2[k] <= r2 ? fx[k] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            acc[u][k] = FIRST ? gy * fx[k] : __builtin_fmaf(gy, fx[k], acc[u][k]);
+    }
+}
+
+// ---- 3. one wave writes one pass (the lane's U runs R, starting at run j0)
+// of plane pl = (channel, z): sum_a phi_z[a][z] phi_y[a][y] phi_x[a][x..]
+// over the plane's mask in index order, U back-to-back 16-byte stores per
+// lane.  out / tgt: the structure's grid and target (or null); sq: the
+// lane's running sum of squared residuals (residual mode).
+template <typename T, int VEC, int U, bool RES, bool SPH>
+__device__ __forceinline__ void stream_pass(const GridParams &p, const MolBuf &B,
+                                            const PlaneGeom &g, int pl, int j0,
+                                            const PassRuns<U> &R, T *out, const float *tgt,
+                                            float &sq)
+{
+    const int z = pl % g.D;
+    const int pc = pl / g.D;
+    unsigned long long mk[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        mk[w] = (w < g.MW) ? uniform64(B.masks[(size_t)pl * g.MW + w]) : 0ull;
+    // residual mode: the target runs are loaded before the accumulation, so
+    // their latency overlaps it
+    float tv[RES ? U : 1][VEC];
+    if constexpr (RES) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (R.ok[u])
+                load_row<VEC>(tgt + (size_t)pl * g.plane_elems + (size_t)(j0 + 64 * u) * VEC, tv[u]);
+            else
+#pragma unroll
+                for (int k = 0; k < VEC; ++k)
+                    tv[u][k] = 0.f;
+        }
+    }
+    // the first atom of the plane (in index order), taken out of its word
+    int a0 = -1;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        if (a0 < 0 && mk[w]) {
+            a0 = w * 64 + __builtin_ctzll(mk[w]);
+            mk[w] &= mk[w] - 1;
+        }
+    float acc[U][VEC];
+    if (a0 >= 0) {
+        add_atom<VEC, U, SPH, true>(p, B, g, a0, z, pc, R, acc);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            unsigned long long bits = mk[w];
+            while (bits) {
+                const int a = w * 64 + __builtin_ctzll(bits);
+                bits &= bits - 1;
+                add_atom<VEC, U, SPH, false>(p, B, g, a, z, pc, R, acc);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < VEC; ++k)
+                acc[u][k] = 0.f;
+    }
+    T *op = out ? out + (size_t)pl * g.plane_elems : nullptr;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (R.ok[u]) {
+            if constexpr (RES) {
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) {
+                    const float r = acc[u][k] - tv[u][k];
+                    sq = __builtin_fmaf(r, r, sq);
+                    acc[u][k] = 2.f * r;
+                }
+            }
+            if (!RES || op)
+                store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], g.nt);
+        }
+}
+
+// Set-up, then stream, structure by structure.  Each wave takes the planes
+// pl = wave (mod waves) pass by pass (the run indices of a pass serve all
+// of its planes); the fixed assignment keeps the residual mode's
+// per-structure sums in a fixed order.
+template <typename T, int VEC, int U, bool RES, bool SPH>
+__global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const WindowLds lay = window_lds_layout(p.a_cap, p.row_stride, p.C, p.D, p.mask_words,
+                                            p.weights ? p.C : 0, SPH);
+    const MolBuf B = mol_buf(smem, lay);
+    const PlaneGeom g = plane_geom<VEC>(p);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, nwaves = nthr >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int planes = p.C * p.D;
+    const size_t mol_elems = (size_t)planes * g.plane_elems;
 
     for (int m = blockIdx.x; m < p.n_mol; m += gridDim.x) {
-        const int a0 = p.offsets[m];
-        int na = p.offsets[m + 1] - a0;
-        if (na > p.a_cap || na < 0 || a0 < 0 || (long long)a0 + na > p.n_atoms) {
-            // more atoms than the declared capacity (or bad offsets): no
-            // atoms, so the structure's grid is written as zeros; sticky error
-            if (tid == 0)
-                raise_error(p.err, na > p.a_cap ? PG_E_CAPACITY : PG_E_DEVICE_DATA, m);
-            na = 0;
-        }
-        float o[3], h[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            o[q] = p.origins ? p.origins[3 * (size_t)m + q] : p.o[q];
-            h[q] = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
-        }
-
-        // ---- 1. window ranges per (atom, axis); clear plane masks
-        for (int i = tid; i < planes * MW; i += nthr)
-            masks[i] = 0ull;
-        for (int i = tid; i < na * WC; i += nthr)
-            wl[i] = p.weights[(size_t)a0 * C + i];
-        for (int i = tid; i < na * 3; i += nthr) {
-            const int a = i / 3, ax = i - 3 * a;
-            const size_t ga = (size_t)a0 + a;
-            const float x = p.xyz[3 * ga + 0], y = p.xyz[3 * ga + 1], zc = p.xyz[3 * ga + 2];
-            const int t = p.types[ga];
-            const bool ok = atom_valid(x, y, zc, t, p.n_sig);
-            RangeRec R;
-            R.n = 0;
-            if (ok) {
-                const float mu = ax == 0 ? x : (ax == 1 ? y : zc);
-                const int N = ax == 0 ? W : (ax == 1 ? H : D);
-                const float oq = ax == 0 ? o[0] : (ax == 1 ? o[1] : o[2]);
-                const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
-                const float Lq = ax == 0 ? p.L[0] : (ax == 1 ? p.L[1] : p.L[2]);
-                AxisRanges ar;
-                axis_ranges(oq, hq, N, mu, p.periodic != 0, Lq, p.rc[t], p.cut != 0, ar);
-                R.n = ar.n;
-#pragma unroll
-                for (int r = 0; r < MAX_IMAGES; ++r) {
-                    R.lo[r] = (int16_t)(r < ar.n ? ar.lo[r] : 0);
-                    R.hi[r] = (int16_t)(r < ar.n ? ar.hi[r] : -1);
-                    R.bh[r] = r < ar.n ? ar.bh[r] : 0.f;
-                    R.bl[r] = r < ar.n ? ar.bl[r] : 0.f;
-                }
-            }
-            rr[i] = R;
-            if (ax == 0) {
-                atype[a] = ok ? t : -1;
-                if (!ok)
-                    raise_error(p.err, PG_E_DEVICE_DATA, (long long)ga);
-            }
-        }
+        mol_setup<SPH, true>(p, B, m, tid, nthr);
         __syncthreads();
-
-        // ---- 2. dense 1-D factor rows and (channel, z) atom masks
-        for (int e = tid; e < na * RS; e += nthr) {
-            const int a = e / RS, j = e - a * RS;
-            int ax, i, N;
-            if (j < W4) {
-                ax = 0; i = j; N = W;
-            } else if (j < W4 + H) {
-                ax = 1; i = j - W4; N = H;
-            } else {
-                ax = 2; i = j - W4 - H; N = D;
-            }
-            const int t = atype[a];
-            float v = 0.f, d2 = __builtin_huge_valf();
-            if (t >= 0 && i < N) {
-                const RangeRec &R = rr[3 * a + ax];
-                const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
-                for (int r = 0; r < R.n; ++r) {
-                    if (i >= R.lo[r] && i <= R.hi[r]) {
-                        v = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[t],
-                                     p.isq2s[t]);
-                        if constexpr (SPH) {
-                            const float d = offset_at(R.bh[r], R.bl[r], hq, i);
-                            d2 = d * d;
-                        }
-                        if (ax == 2) {
-                            if (WC == 0) {
-                                atomicOr(&masks[(size_t)(t * D + i) * MW + (a >> 6)],
-                                         1ull << (a & 63));
-                            } else {
-                                for (int c = 0; c < C; ++c)
-                                    if (wl[a * WC + c] != 0.f)
-                                        atomicOr(&masks[(size_t)(c * D + i) * MW + (a >> 6)],
-                                                 1ull << (a & 63));
-                            }
-                        }
-                    }
-                }
-            }
-            rows[e] = v;
-            if constexpr (SPH)
-                dsq[e] = d2;
-        }
-        __syncthreads();
-
-        // ---- 3. stream the planes: each lane owns U runs per pass, so a
-        // wave issues U back-to-back 16-byte stores per pass
         // a reversal step may keep no residual grid (out == nullptr)
-        const bool store = !RES || p.out != nullptr;
-        T *out = store ? (T *)p.out + (size_t)m * mol_elems : nullptr;
+        T *out = p.out ? (T *)p.out + (size_t)m * mol_elems : nullptr;
         const float *tgt = RES ? p.target + (size_t)m * mol_elems : nullptr;
         float sq = 0.f;
-        for (int pl = wave; pl < planes; pl += nwaves) {
-            const int z = pl % D;
-            const int pc = pl / D;
-            unsigned long long mk[4];
-#pragma unroll
-            for (int w = 0; w < 4; ++w)
-                mk[w] = (w < MW) ? uniform64(masks[(size_t)pl * MW + w]) : 0ull;
-            T *op = store ? out + (size_t)pl * plane_elems : nullptr;
-            for (int j0 = lane; j0 < chunks; j0 += 64 * U) {
-                int yq[U], xq[U];
-                bool ok[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = j0 + 64 * u;
-                    ok[u] = j < chunks;
-                    // run j starts at element j*VEC: row j / CW, column (j % CW) * VEC
-                    int yy = (int)(((float)j + 0.5f) * inv_cw);
-                    yy -= yy * CW > j ? 1 : 0;
-                    yy += (yy + 1) * CW <= j ? 1 : 0;
-                    yq[u] = ok[u] ? yy : 0;
-                    xq[u] = ok[u] ? (j - yy * CW) * VEC : 0;
-                }
-                float acc[U][VEC];
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < VEC; ++k)
-                        acc[u][k] = 0.f;
-                // residual mode: the target runs are loaded before the
-                // accumulation, so their latency overlaps it
-                float tv[RES ? U : 1][VEC];
-                if constexpr (RES) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (ok[u])
-                            load_row<VEC>(tgt + (size_t)pl * plane_elems + (size_t)(j0 + 64 * u) * VEC,
-                                          tv[u]);
-                        else
-#pragma unroll
-                            for (int k = 0; k < VEC; ++k)
-                                tv[u][k] = 0.f;
-                    }
-                }
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    unsigned long long bits = mk[w];
-                    while (bits) {
-                        const int a = w * 64 + __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const float *row = rows + a * RS;
-                        float gz = row[W4 + H + z];
-                        if (WC)
-                            gz *= wl[a * WC + pc];
-                        float r2z = 0.f;
-                        if constexpr (SPH)
-                            r2z = p.rc2[atype[a]] - dsq[a * RS + W4 + H + z];
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const float gy = row[W4 + yq[u]] * gz;
-                            float fx[VEC];
-                            load_row<VEC>(row + xq[u], fx);
-                            if constexpr (SPH) {
-                                // keep x only inside the ball: dx^2 <= rc^2 - dz^2 - dy^2
-                                const float r2 = r2z - dsq[a * RS + W4 + yq[u]];
-                                float dx2[VEC];
-                                load_row<VEC>(dsq + a * RS + xq[u], dx2);
-#pragma unroll
-                                for (int k = 0; k < VEC; ++k)
-                                    fx[k] = dx2[k] <= r2 ? fx[k] : 0.f;
-                            }
-#pragma unroll
-                            for (int k = 0; k < VEC; ++k)
-                                acc[u][k] = __builtin_fmaf(gy, fx[k], acc[u][k]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) {
-                        if constexpr (RES) {
-#pragma unroll
-                            for (int k = 0; k < VEC; ++k) {
-                                const float r = acc[u][k] - tv[u][k];
-                                sq = __builtin_fmaf(r, r, sq);
-                                acc[u][k] = 2.f * r;
-                            }
-                        }
-                        if (store)
-                            store_vec<T, VEC>(op + (size_t)(j0 + 64 * u) * VEC, acc[u], nt);
-                    }
-            }
+        for (int j0 = lane; j0 < g.chunks; j0 += 64 * U) {
+            const PassRuns<U> R = pass_runs<VEC, U>(g, j0);
+            for (int pl = wave; pl < planes; pl += nwaves)
+                stream_pass<T, VEC, U, RES, SPH>(p, B, g, pl, j0, R, out, tgt, sq);
         }
         if constexpr (RES) {
             // per-lane FP32 partial sums, combined as float-float sums (a

@@ -260,6 +260,65 @@ def test_determinism_across_launch_shapes(pg, dev):
         assert torch.equal(base, g), (blk, pc, un, nt)
 
 
+def _drop_atoms(b, m):
+    """b with structure m emptied (its atoms removed)."""
+    off = b.offsets.astype(np.int64)
+    lo, hi = int(off[m]), int(off[m + 1])
+    keep = np.r_[0:lo, hi:len(b.types)]
+    noff = off.copy()
+    noff[m + 1:] -= hi - lo
+    return synth.Batch(b.xyz[keep].copy(), b.types[keep].copy(), noff.astype(np.int32))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_many_structures_per_workgroup(pg, dev, dtype):
+    """Persistent workgroups that take several structures each (700 > one
+    per CU), across empty structures, invalid atoms and structures over the
+    declared capacity: grids and reported errors are bitwise the same for
+    every workgroup size (one wave streams alone) and persistent grid size,
+    and match the oracle."""
+    say(f"case many structures per workgroup {dtype}")
+    wl = synth.WORKLOADS["mol4096"]
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    tol = F32_TOL if dtype == "f32" else BF16_TOL
+    b = _drop_atoms(wl.batch(700), 261)
+    bad = synth.Batch(b.xyz.copy(), b.types.copy(), b.offsets)
+    bad.xyz[b.offsets[300] + 1, 1] = np.nan      # an invalid atom in a later structure
+    for name, bb, cap in (("plain", b, None), ("invalid", bad, None), ("capacity", b, 24)):
+        grids, errs = [], []
+        for blk, pc in ((512, 1), (1024, 1), (64, 1), (256, 3), (192, 2)):
+            ctx = pg.Context(0)
+            ctx.set_option(pg.PG_OPT_BLOCK, blk)
+            ctx.set_option(pg.PG_OPT_GRID_PER_CU, pc)
+            say(f"  {name}: block {blk} per_cu {pc}")
+            grids.append(run(pg, dev, bb, wl.sigma(), wl.dims, wl.spacing, wl.origin, tdt,
+                             form="window", ctx=ctx, max_atoms=cap))
+            errs.append(ctx.device_error())
+        for g, e in zip(grids[1:], errs[1:]):
+            assert torch.equal(grids[0], g), name
+            assert e == errs[0], name
+        counts = np.diff(bb.offsets)
+        if name == "plain":
+            assert errs[0] == (0, -1)
+        elif name == "invalid":
+            assert errs[0] == (pg.PG_E_DEVICE_DATA, int(b.offsets[300]) + 1)
+        else:
+            assert errs[0] == (pg.PG_E_CAPACITY, int(np.argmax(counts > 24)))
+        g = grids[1]
+        assert not g[261].any()
+        for m in (0, 255, 256, 260, 262, 300, 511, 512, 699):
+            lo, hi = int(bb.offsets[m]), int(bb.offsets[m + 1])
+            if cap is not None and hi - lo > cap:
+                assert not g[m].any()
+                continue
+            keep = np.isfinite(bb.xyz[lo:hi]).all(axis=1)
+            one = synth.Batch(bb.xyz[lo:hi][keep], bb.types[lo:hi][keep],
+                              np.array([0, int(keep.sum())], np.int32))
+            ref = ref_grid(one, wl.sigma(), wl.dims, wl.spacing, wl.origin)
+            rel, mx = errors(g[m:m + 1].double().cpu().numpy(), ref)
+            assert rel <= tol, (name, m, rel, mx)
+
+
 def test_permutation_invariance(pg, dev):
     say("case permutation")
     wl = synth.WORKLOADS["single20"]
