@@ -93,6 +93,20 @@ __device__ __forceinline__ uint16_t bf16_bits(float v)
 // split-fp16 contraction).
 __device__ __forceinline__ void op_store(uint16_t *p, float v) { *p = bf16_bits(v); }
 __device__ __forceinline__ void op_store(float *p, float v) { *p = v; }
+// four consecutive slot values (p aligned to four elements)
+__device__ __forceinline__ void op_store4(uint16_t *p, const float (&v)[4])
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    const f2v lo = {v[0], v[1]}, hi = {v[2], v[3]};
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    *(u2 *)p = u2{__builtin_bit_cast(uint32_t, __builtin_convertvector(lo, b2v)),
+                  __builtin_bit_cast(uint32_t, __builtin_convertvector(hi, b2v))};
+}
+__device__ __forceinline__ void op_store4(float *p, const float (&v)[4])
+{
+    *(float4 *)p = float4{v[0], v[1], v[2], v[3]};
+}
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -120,9 +134,9 @@ __device__ __forceinline__ AxisWin axis_win(const AtomWindow &w, int ax)
 // Factor slots of the MFMA form: per listed atom and axis x or y, per
 // 32-voxel tile its windows meet (ascending: the set bits of its tile mask),
 // the 32 values phi(32 tile + j), zero outside the windows and past the grid
-// edge.  Eight lanes per (atom,
-// axis), four values each per slot, so one wave fills eight atom-axes; the
-// atoms' records are read once.
+// edge.  Eight lanes per (atom, axis), four consecutive values each per slot
+// (the box form walks their five edges once), so one wave fills eight
+// atom-axes; the atoms' records are read once.
 template <typename YT, typename XT>
 __global__ void __launch_bounds__(256) cr_slot_kernel(GridParams p, CrystalParams q)
 {
@@ -151,19 +165,29 @@ __global__ void __launch_bounds__(256) cr_slot_kernel(GridParams p, CrystalParam
     uint32_t mk = q.tmask[2 * a + ax];
     for (int s = 0; s < S && mk != 0u; ++s, mk &= mk - 1u) {
         const int tile = __builtin_ctz(mk);
+        const int v0 = 32 * tile + 4 * j8;
+        float val[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = j8 + 8 * i, v = 32 * tile + j;
-            float val = 0.f;
+        for (int r = 0; r < MAX_IMAGES; ++r) {
+            if (r >= aw.n || aw.hi[r] < v0 || aw.lo[r] > v0 + 3)
+                continue;
+            float f[4];
+            if (box) {
+                box_fixed<4>(bh[r], bl[r], h, v0, isq2s, f);
+            } else {
 #pragma unroll
-            for (int r = 0; r < MAX_IMAGES; ++r)
-                if (r < aw.n && v >= aw.lo[r] && v <= aw.hi[r])
-                    val = factor1d(box, bh[r], bl[r], h, v, inv2s2, isq2s);
-            if (ax == 0)
-                op_store(outx + (size_t)s * 32 + j, val);
-            else
-                op_store(outy + (size_t)s * 32 + j, val);
+                for (int k = 0; k < 4; ++k)
+                    f[k] = gauss1d(offset_at(bh[r], bl[r], h, v0 + k), inv2s2);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (v0 + k >= aw.lo[r] && v0 + k <= aw.hi[r])
+                    val[k] = f[k];
         }
+        if (ax == 0)
+            op_store4(outx + (size_t)s * 32 + 4 * j8, val);
+        else
+            op_store4(outy + (size_t)s * 32 + 4 * j8, val);
     }
 }
 
@@ -778,11 +802,21 @@ __device__ __forceinline__ LaneImage<ZP> lane_image(const GridParams &p, const C
             isq2s = p.isq2s[ti];
             wgt = p.weights[(size_t)te.atom * p.C + c];
         }
+        if (p.box != 0) {
+            // the ZP planes' masses from ZP + 1 shared edges
+            float f[ZP];
+            box_fixed<ZP>(te.bh, te.bl, p.h[2], z0, isq2s, f);
 #pragma unroll
-        for (int k = 0; k < ZP; ++k) {
-            const int z = z0 + k;
-            if (z >= zlo && z <= zhi)
-                li.gz[k] = factor1d(p.box != 0, te.bh, te.bl, p.h[2], z, inv2s2, isq2s) * wgt;
+            for (int k = 0; k < ZP; ++k)
+                if (z0 + k >= zlo && z0 + k <= zhi)
+                    li.gz[k] = f[k] * wgt;
+        } else {
+#pragma unroll
+            for (int k = 0; k < ZP; ++k) {
+                const int z = z0 + k;
+                if (z >= zlo && z <= zhi)
+                    li.gz[k] = gauss1d(offset_at(te.bh, te.bl, p.h[2], z), inv2s2) * wgt;
+            }
         }
         li.yslot = (uint32_t)te.atom * (uint32_t)q.sy_max + ((te.zs >> 24) & 15u);
         li.xslot = (uint32_t)te.atom * (uint32_t)q.sx_max + (te.zs >> 28);
@@ -1011,7 +1045,7 @@ constexpr int KCH_F32 = 64;   // entries per chunk of the fp32 tile kernel
 // 4 x 4 voxels at rows 4 (l / 8), columns 4 (l % 8) of each: for every
 // image in the tile's mask (lowest bit first) it reads 4 phi_y and 4 phi_x
 // values and does 16 FMAs.  Each voxel sums its images in z order, in FP32.
-template <typename T, int TMAX>
+template <typename T, int TMAX, bool BOX>
 __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalParams q)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1031,7 +1065,8 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
     const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
     const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
     const long long eb = 32ll * run_block(q, mc);
-    const bool box = p.box != 0;
+    constexpr bool box = BOX;   // the value form (a separate instance: its
+                                // registers stay out of the point form's)
     const int ly = 4 * (lane >> 3), lx = 4 * (lane & 7);
     float acc[TMAX][4][4];
 #pragma unroll
@@ -1061,19 +1096,31 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
                                     image_weight(p, ze.atom, c);
                     const AtomWindow &w = q.table[ze.atom];
                     uint32_t tx = 0u, ty = 0u;   // tile columns / rows the windows meet
+                    // each of the image's 8 threads takes a contiguous eighth of
+                    // each window (the box form walks its edges once)
                     for (int r = 0; r < w.n[0]; ++r) {
                         const float bh = w.bh[0][r], bl = w.bl[0][r];
                         for (int t = w.lo[0][r] >> 5; t <= (w.hi[0][r] >> 5); ++t)
                             tx |= 1u << t;
-                        for (int v = w.lo[0][r] + part; v <= w.hi[0][r]; v += 8)
-                            gx[k * W32 + v] = factor1d(box, bh, bl, p.h[0], v, inv2s2, isq2s);
+                        const int L8 = (w.hi[0][r] - w.lo[0][r] + 8) >> 3;
+                        const int lo = w.lo[0][r] + part * L8, hi = min(w.hi[0][r], lo + L8 - 1);
+                        if (box)
+                            box_walk<false>(bh, bl, p.h[0], lo, hi, isq2s, 1.f, gx + k * W32);
+                        else
+                            for (int v = lo; v <= hi; ++v)
+                                gx[k * W32 + v] = gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2);
                     }
                     for (int r = 0; r < w.n[1]; ++r) {
                         const float bh = w.bh[1][r], bl = w.bl[1][r];
                         for (int t = w.lo[1][r] >> 5; t <= (w.hi[1][r] >> 5); ++t)
                             ty |= 1u << t;
-                        for (int v = w.lo[1][r] + part; v <= w.hi[1][r]; v += 8)
-                            gy[k * H32 + v] = g * factor1d(box, bh, bl, p.h[1], v, inv2s2, isq2s);
+                        const int L8 = (w.hi[1][r] - w.lo[1][r] + 8) >> 3;
+                        const int lo = w.lo[1][r] + part * L8, hi = min(w.hi[1][r], lo + L8 - 1);
+                        if (box)
+                            box_walk<true>(bh, bl, p.h[1], lo, hi, isq2s, g, gy + k * H32);
+                        else
+                            for (int v = lo; v <= hi; ++v)
+                                gy[k * H32 + v] = g * gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2);
                     }
                     if (part == 0)
                         for (int tr = 0; tr < nty; ++tr)
@@ -1202,6 +1249,21 @@ int crystal_prep_blocks(long long n_atoms)
     return (int)((n_atoms + PREP_BLOCK - 1) / PREP_BLOCK);
 }
 
+// The vector-form instance for a grid type, tiles per wave and value form.
+template <bool BOX>
+static const void *window_kernel_for(int out_dtype, int r)
+{
+    if (out_dtype == PG_OUT_F32)
+        return r == 1 ? (const void *)cr_window_kernel<float, 1, BOX>
+             : r == 2 ? (const void *)cr_window_kernel<float, 2, BOX>
+             : r == 4 ? (const void *)cr_window_kernel<float, 4, BOX>
+             : r == 8 ? (const void *)cr_window_kernel<float, 8, BOX> : nullptr;
+    return r == 1 ? (const void *)cr_window_kernel<__bf16, 1, BOX>
+         : r == 2 ? (const void *)cr_window_kernel<__bf16, 2, BOX>
+         : r == 4 ? (const void *)cr_window_kernel<__bf16, 4, BOX>
+         : r == 8 ? (const void *)cr_window_kernel<__bf16, 8, BOX> : nullptr;
+}
+
 hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form, int out_dtype,
                           size_t lds, hipStream_t s)
 {
@@ -1277,16 +1339,7 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         const int r = crystal_window_runs(p.H, p.W);
-        if (out_dtype == PG_OUT_F32)
-            k = r == 1 ? (const void *)cr_window_kernel<float, 1>
-              : r == 2 ? (const void *)cr_window_kernel<float, 2>
-              : r == 4 ? (const void *)cr_window_kernel<float, 4>
-              : r == 8 ? (const void *)cr_window_kernel<float, 8> : nullptr;
-        else
-            k = r == 1 ? (const void *)cr_window_kernel<__bf16, 1>
-              : r == 2 ? (const void *)cr_window_kernel<__bf16, 2>
-              : r == 4 ? (const void *)cr_window_kernel<__bf16, 4>
-              : r == 8 ? (const void *)cr_window_kernel<__bf16, 8> : nullptr;
+        k = p.box ? window_kernel_for<true>(out_dtype, r) : window_kernel_for<false>(out_dtype, r);
         if (!k)
             return hipErrorInvalidValue;
         grid = nmc * p.D;

@@ -290,6 +290,81 @@ __device__ __forceinline__ float box1d(float l, float r, float isq2s)
     return 0.5f * (erff(b) - erff(a));
 }
 
+// Box form with each edge's error function shared by the two voxels that
+// meet there (N + 1 evaluations for a window of N voxels instead of 2N,
+// §VI-A).  box_edge(e) = erfc(|e| s) is the tail term of edge offset e; a
+// voxel's mass is half the difference of its edges' terms when both edges
+// lie on one side of the atom (from the nearer tail), the direct difference
+// of erf values for the one voxel that holds the centre: bitwise what box1d
+// returns.
+__device__ __forceinline__ float box_edge(float e, float isq2s)
+{
+    return erfcf(fabsf(e * isq2s));
+}
+
+// Box-form masses of the N voxels v0 .. v0+N-1 of one image (the caller
+// keeps those inside its window): N + 1 edge terms, and the direct erf
+// difference once, for the voxel holding the centre, after the walk (so a
+// wave runs that branch once, not once per voxel).
+template <int N>
+__device__ __forceinline__ void box_fixed(float bh, float bl, float h, int v0, float isq2s,
+                                          float (&out)[N])
+{
+    float el = edge_at(bh, bl, h, v0), ql = box_edge(el, isq2s);
+    int ks = -1;
+    float as = 0.f, bs = 0.f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float er = edge_at(bh, bl, h, v0 + k + 1), qr = box_edge(er, isq2s);
+        const float a = el * isq2s, b = er * isq2s;
+        out[k] = a >= 0.f ? 0.5f * (ql - qr) : 0.5f * (qr - ql);
+        if (a < 0.f && b > 0.f) {
+            ks = k;
+            as = a;
+            bs = b;
+        }
+        el = er;
+        ql = qr;
+    }
+    if (ks >= 0) {
+        const float v = 0.5f * (erff(bs) - erff(as));
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k == ks)
+                out[k] = v;
+    }
+}
+
+// The same along voxels lo .. hi of one image's window into dst[lo .. hi]
+// (times scale), for runs of any length.
+template <bool SCALE>
+__device__ __forceinline__ void box_walk(float bh, float bl, float h, int lo, int hi, float isq2s,
+                                         float scale, float *dst)
+{
+    if (lo > hi)
+        return;
+    float el = edge_at(bh, bl, h, lo), ql = box_edge(el, isq2s);
+    int vs = -1;
+    float as = 0.f, bs = 0.f;
+    for (int v = lo; v <= hi; ++v) {
+        const float er = edge_at(bh, bl, h, v + 1), qr = box_edge(er, isq2s);
+        const float a = el * isq2s, b = er * isq2s;
+        const float f = a >= 0.f ? 0.5f * (ql - qr) : 0.5f * (qr - ql);
+        dst[v] = SCALE ? scale * f : f;
+        if (a < 0.f && b > 0.f) {
+            vs = v;
+            as = a;
+            bs = b;
+        }
+        el = er;
+        ql = qr;
+    }
+    if (vs >= 0) {
+        const float f = 0.5f * (erff(bs) - erff(as));
+        dst[vs] = SCALE ? scale * f : f;
+    }
+}
+
 // The value of window element i on one axis: the point sample at the voxel
 // centre, or (box) the voxel's Gaussian mass.
 __device__ __forceinline__ float factor1d(bool box, float bh, float bl, float h, int i,

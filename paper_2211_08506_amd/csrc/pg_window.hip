@@ -110,25 +110,9 @@ __device__ __forceinline__ MolBuf mol_buf(unsigned char *base, const WindowLds &
     return B;
 }
 
-// Barrier between the set-up steps of the group that runs them: the whole
-// workgroup, or a single wave, whose LDS accesses the hardware performs in
-// issue order (so only the compiler has to be kept from reordering them).
-template <bool WG>
-__device__ __forceinline__ void group_sync()
-{
-    if constexpr (WG) {
-        __syncthreads();
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
-// Steps 1-2 for structure m into B, run by threads t = 0 .. n-1 of the
-// group (the workgroup, or one wave).  The caller synchronises before the
-// state is read by other waves.
-template <bool SPH, bool WG>
+// Steps 1-2 for structure m into B, run by the workgroup's threads
+// t = 0 .. n-1; the caller synchronises before the state is read.
+template <bool SPH>
 __device__ void mol_setup(const GridParams &p, const MolBuf &B, int m, int t, int n)
 {
     const int C = p.C, D = p.D, H = p.H, W = p.W;
@@ -153,9 +137,14 @@ __device__ void mol_setup(const GridParams &p, const MolBuf &B, int m, int t, in
         h[q] = p.spacings ? p.spacings[3 * (size_t)m + q] : p.h[q];
     }
 
-    // ---- 1. window ranges per (atom, axis); clear plane masks
+    // ---- 1. window ranges per (atom, axis); clear plane masks and rows
     for (int i = t; i < planes * MW; i += n)
         B.masks[i] = 0ull;
+    for (int i = t; i < na * RS; i += n) {
+        B.rows[i] = 0.f;
+        if constexpr (SPH)
+            B.dsq[i] = __builtin_huge_valf();
+    }
     for (int i = t; i < na * WC; i += n)
         B.wl[i] = p.weights[(size_t)a0 * C + i];
     for (int i = t; i < na * 3; i += n) {
@@ -190,48 +179,57 @@ __device__ void mol_setup(const GridParams &p, const MolBuf &B, int m, int t, in
                 raise_error(p.err, PG_E_DEVICE_DATA, (long long)ga);
         }
     }
-    group_sync<WG>();
+    __syncthreads();
 
-    // ---- 2. dense 1-D factor rows and (channel, z) atom masks
-    for (int e = t; e < na * RS; e += n) {
-        const int a = e / RS, j = e - a * RS;
-        int ax, i, N;
-        if (j < W4) {
-            ax = 0; i = j; N = W;
-        } else if (j < W4 + H) {
-            ax = 1; i = j - W4; N = H;
+    // ---- 2. the 1-D factor rows inside the windows (zero elsewhere), eight
+    // consecutive voxels of one atom and axis per item (the box form walks
+    // their edges once), and the (channel, z) atom masks
+    const int nx = (W + 7) >> 3, ny = (H + 7) >> 3, nz = (D + 7) >> 3, nc = nx + ny + nz;
+    for (int it = t; it < na * nc; it += n) {
+        const int a = it / nc;
+        int c = it - a * nc, ax, N, base;
+        float hq;
+        if (c < nx) {
+            ax = 0; N = W; base = 0; hq = h[0];
+        } else if (c < nx + ny) {
+            ax = 1; c -= nx; N = H; base = W4; hq = h[1];
         } else {
-            ax = 2; i = j - W4 - H; N = D;
+            ax = 2; c -= nx + ny; N = D; base = W4 + H; hq = h[2];
         }
         const int ty = B.atype[a];
-        float v = 0.f, d2 = __builtin_huge_valf();
-        if (ty >= 0 && i < N) {
-            const RangeRec &R = B.rr[3 * a + ax];
-            const float hq = ax == 0 ? h[0] : (ax == 1 ? h[1] : h[2]);
-            for (int r = 0; r < R.n; ++r) {
-                if (i >= R.lo[r] && i <= R.hi[r]) {
-                    v = factor1d(p.box != 0, R.bh[r], R.bl[r], hq, i, p.inv2s2[ty], p.isq2s[ty]);
-                    if constexpr (SPH) {
-                        const float d = offset_at(R.bh[r], R.bl[r], hq, i);
-                        d2 = d * d;
-                    }
-                    if (ax == 2) {
-                        if (WC == 0) {
-                            atomicOr(&B.masks[(size_t)(ty * D + i) * MW + (a >> 6)],
-                                     1ull << (a & 63));
-                        } else {
-                            for (int c = 0; c < C; ++c)
-                                if (B.wl[a * WC + c] != 0.f)
-                                    atomicOr(&B.masks[(size_t)(c * D + i) * MW + (a >> 6)],
-                                             1ull << (a & 63));
-                        }
+        if (ty < 0)
+            continue;
+        const RangeRec &R = B.rr[3 * a + ax];
+        const int v0 = 8 * c, v1 = min(v0 + 7, N - 1);
+        float *row = B.rows + a * RS + base;
+        for (int r = 0; r < R.n; ++r) {
+            const int lo = max((int)R.lo[r], v0), hi = min((int)R.hi[r], v1);
+            if (lo > hi)
+                continue;
+            const float bh = R.bh[r], bl = R.bl[r];
+            if (p.box != 0) {
+                box_walk<false>(bh, bl, hq, lo, hi, p.isq2s[ty], 1.f, row);
+            } else {
+                for (int i = lo; i <= hi; ++i)
+                    row[i] = gauss1d(offset_at(bh, bl, hq, i), p.inv2s2[ty]);
+            }
+            for (int i = lo; i <= hi; ++i) {
+                if constexpr (SPH) {
+                    const float d = offset_at(bh, bl, hq, i);
+                    B.dsq[a * RS + base + i] = d * d;
+                }
+                if (ax == 2) {
+                    if (WC == 0) {
+                        atomicOr(&B.masks[(size_t)(ty * D + i) * MW + (a >> 6)], 1ull << (a & 63));
+                    } else {
+                        for (int ch = 0; ch < C; ++ch)
+                            if (B.wl[a * WC + ch] != 0.f)
+                                atomicOr(&B.masks[(size_t)(ch * D + i) * MW + (a >> 6)],
+                                         1ull << (a & 63));
                     }
                 }
             }
         }
-        B.rows[e] = v;
-        if constexpr (SPH)
-            B.dsq[e] = d2;
     }
 }
 
@@ -423,7 +421,7 @@ __global__ void __launch_bounds__(1024) window_mol_kernel(GridParams p)
     const size_t mol_elems = (size_t)planes * g.plane_elems;
 
     for (int m = blockIdx.x; m < p.n_mol; m += gridDim.x) {
-        mol_setup<SPH, true>(p, B, m, tid, nthr);
+        mol_setup<SPH>(p, B, m, tid, nthr);
         __syncthreads();
         // a reversal step may keep no residual grid (out == nullptr)
         T *out = p.out ? (T *)p.out + (size_t)m * mol_elems : nullptr;
