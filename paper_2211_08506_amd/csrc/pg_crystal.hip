@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(1024) cr_zsort_kernel(GridParams p, CrystalPar
 struct MaskWalk {
     uint32_t my, mx, cy, cx;
     uint32_t z[MAX_IMAGES];
-    int r, sy, sx;
+    int r, sy, sx, sy0;
     bool live;
     __device__ __forceinline__ int next_range(int from) const
     {
@@ -516,14 +516,17 @@ struct MaskWalk {
                 nr = k;
         return nr;
     }
-    __device__ __forceinline__ void start(const ListEntry &e, uint32_t mx_, uint32_t my_)
+    // my_: the y tiles walked (a band of the atom's y mask), sy0_: the atom's
+    // y slots below the band
+    __device__ __forceinline__ void start(const ListEntry &e, uint32_t mx_, uint32_t my_, int sy0_)
     {
         mx = cx = mx_;
         my = cy = my_;
 #pragma unroll
         for (int k = 0; k < MAX_IMAGES; ++k)
             z[k] = e.z[k];
-        sy = sx = 0;
+        sy0 = sy = sy0_;
+        sx = 0;
         r = next_range(0);
         live = r < MAX_IMAGES && mx != 0u && my != 0u;
     }
@@ -540,11 +543,20 @@ struct MaskWalk {
             ++sy;
             if (cy == 0u) {
                 cy = my;
-                sy = 0;
+                sy = sy0;
                 r = next_range(r + 1);
             }
         }
         live = r < MAX_IMAGES;
+    }
+    // z images (non-empty z ranges) of the entry
+    __device__ __forceinline__ int ranges() const
+    {
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < MAX_IMAGES; ++k)
+            n += range_hi(z[k]) >= range_lo(z[k]) ? 1 : 0;
+        return n;
     }
     __device__ __forceinline__ uint32_t zs() const
     {
@@ -564,21 +576,35 @@ struct MaskWalk {
 // counts, a scan over (key, wave), then each wave places its part, equal
 // keys within 64 entries ranked by a match over the key bits.  The scan
 // gives each list's z boundaries directly: zstart[tc][z] = the first entry
-// of key (tc, z), zstart[tc][D] = the list's end.  Dynamic LDS: waves x ntc
-// x D words.
-__global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalParams q)
+// of key (tc, z), zstart[tc][D] = the list's end.
+//
+// A run's tile rows are dealt to G workgroups in bands (G > 1 when runs are
+// few, to spread the sort over the chip): each walks all of the run's
+// entries with the same split over its waves but counts and places only the
+// items of its band's tile columns, after the items of the rows above it
+// (counted from the tile masks), so the lists are the same for any G.
+// Dynamic LDS: waves x (band rows x ntx) x D words.
+__global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalParams q, int G)
 {
     extern __shared__ uint32_t tls[];
     __shared__ uint32_t tsum[1024];
+    __shared__ uint32_t nabove;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nw = blockDim.x >> 6, nt = blockDim.x;
-    const size_t mc = blockIdx.x;
-    const int D = p.D, ntc = q.ntx * q.nty, K = ntc * D;
+    const size_t mc = blockIdx.x / (unsigned)G;
+    const int g = (int)(blockIdx.x % (unsigned)G);
+    // the band's tile rows [ty0, ty1) and its keys ((ty - ty0) ntx + tx) D + z
+    const int ty0 = g * q.nty / G, ty1 = (g + 1) * q.nty / G;
+    const uint32_t rows_above = (uint32_t)((1ull << ty0) - 1ull);
+    const uint32_t band = (uint32_t)((1ull << ty1) - 1ull) & ~rows_above;
+    const int D = p.D, ntc = q.ntx * q.nty, K = (ty1 - ty0) * q.ntx * D;
     uint32_t *cnt = tls;   // [wave][K]: counts, then cursors
     const uint32_t start = q.mstart[mc], n = q.mcount[mc];
     const uint32_t base = (uint32_t)(32ll * run_block(q, mc) * (long long)(q.sx_max * q.sy_max));
     for (int i = tid; i < nw * K; i += nt)
         cnt[i] = 0u;
+    if (tid == 0)
+        nabove = 0u;
     __syncthreads();
     const uint32_t part = (n + nw - 1) / nw;
     const uint32_t pb = min(n, part * wave), pe = min(n, pb + part);
@@ -625,6 +651,7 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
             }
         }
     };
+    uint32_t above = 0u;   // the thread's items in rows above the band
     for (int ch = 0; ch < nch; ++ch) {
         ListEntry le;
         uint32_t mx, my;
@@ -632,12 +659,15 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
         if (le.atom < 0)
             continue;
         MaskWalk iw;
-        iw.start(le, mx, my);
+        iw.start(le, mx, my & band, __popc(my & rows_above));
+        above += (uint32_t)(iw.ranges() * __popc(mx) * __popc(my & rows_above));
         while (iw.live) {
-            atomicAdd(&cw[(iw.ty() * ntx + iw.tx()) * D + range_lo(iw.zs())], 1u);
+            atomicAdd(&cw[((iw.ty() - ty0) * ntx + iw.tx()) * D + range_lo(iw.zs())], 1u);
             iw.next();
         }
     }
+    if (above)
+        atomicAdd(&nabove, above);
     __syncthreads();
     // key totals and their exclusive scan: a contiguous segment of keys per
     // thread, the segment sums scanned across the workgroup
@@ -654,9 +684,9 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
         tsum[tid] += v;
         __syncthreads();
     }
-    uint32_t run = base + tsum[tid] - ssum;
+    uint32_t run = base + nabove + tsum[tid] - ssum;
     for (int k = kb; k < ke; ++k) {
-        const int tc = k / D, z = k - tc * D;
+        const int tc = ty0 * ntx + k / D, z = k % D;
         uint32_t *zs = q.zstart + (mc * ntc + tc) * (size_t)(D + 1);
         zs[z] = run;
         for (int w = 0; w < nw; ++w) {   // counts -> per-wave cursors
@@ -679,10 +709,11 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
         MaskWalk iw;
         iw.live = false;
         if (le.atom >= 0)
-            iw.start(le, mx, my);
+            iw.start(le, mx, my & band, __popc(my & rows_above));
         // one item per lane per round; equal keys ranked by lane
         while (__ballot(iw.live) != 0ull) {
-            const uint32_t key = iw.live ? (uint32_t)((iw.ty() * ntx + iw.tx()) * D + range_lo(iw.zs())) : 0u;
+            const uint32_t key =
+                iw.live ? (uint32_t)(((iw.ty() - ty0) * ntx + iw.tx()) * D + range_lo(iw.zs())) : 0u;
             unsigned long long m = __ballot(iw.live);
             for (int b = 0; b < kbits; ++b) {
                 const unsigned long long mb = __ballot(iw.live && ((key >> b) & 1u));
@@ -1310,7 +1341,10 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
         }
-        const int K = q.ntx * q.nty * p.D;
+        // tile-row bands per run: enough workgroups to spread the sort over
+        // the chip when runs are few
+        const int G = (int)std::max<long long>(1, std::min<long long>(q.nty, (256 + nmc - 1) / nmc));
+        const int K = ((q.nty + G - 1) / G) * q.ntx * p.D;   // keys of the widest band
         const size_t tl = crystal_tsort_lds(K);
         if (tl > 65536) {
             e = hipFuncSetAttribute((const void *)cr_tsort_kernel,
@@ -1318,8 +1352,8 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
             if (e != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL(cr_tsort_kernel, dim3((unsigned)nmc), dim3(64 * crystal_tsort_waves(K)), tl, s,
-                           p, q);
+        hipLaunchKernelGGL(cr_tsort_kernel, dim3((unsigned)(nmc * G)), dim3(64 * crystal_tsort_waves(K)), tl,
+                           s, p, q, G);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         const int zp = out_dtype == PG_OUT_F32 ? ZP_F32 : ZP_BF16;

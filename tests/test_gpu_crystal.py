@@ -113,6 +113,27 @@ def test_ragged_planes_large_cluster(pg, dev, dims):
         assert not got[1].any()
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.bfloat16, BF16_TOL), (torch.float32, F32_TOL)])
+def test_mfma_many_and_few_runs(pg, dev, dtype, tol):
+    """The MFMA form on many runs (40 periodic cells x 8 channels = 320
+    (structure, channel) runs, more than the chip has CUs) and on few (the
+    first 5 cells: 40 runs): both match the oracle, voxel support included,
+    and are bitwise reproducible."""
+    sig = synth.sigma_table(8, 0.3, 0.5)
+    counts = [300 + 7 * i for i in range(40)]
+    b = cell_batch(35, counts, 8.0, 8)
+    dims, h = (16, 24, 32), 0.25
+    ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, dims, h, (0, 0, 0), cell=8.0)
+    m5 = int(b.offsets[5])
+    few = synth.Batch(b.xyz[:m5], b.types[:m5], b.offsets[:6])
+    for name, bb, rr in (("many", b, ref), ("few", few, ref[:5])):
+        say(f"case mfma {name} runs dtype={dtype}")
+        g = run(pg, dev, bb, sig, dims, h, (0, 0, 0), dtype, "mfma", cell=8.0)
+        check(f"runs-{name}/{dtype}", g, rr, tol)
+        again = run(pg, dev, bb, sig, dims, h, (0, 0, 0), dtype, "mfma", cell=8.0)
+        assert torch.equal(g, again), name
+
+
 def test_auto_form_rule(pg, dev):
     """AUTO on large structures: the MFMA form for bf16 and float32 grids
     (the latter on split fp16 factors); small structures keep the one-launch
