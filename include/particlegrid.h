@@ -144,10 +144,11 @@ enum { PG_CUTOFF_CUBE = 0, PG_CUTOFF_SPHERE = 1 };
    image's Gaussian truncated to its own cutoff cube; the cell must keep
    the cubes of distinct images of one atom apart (for every n != 0 with
    |n_j| <= 4: max_alpha |(M n)_alpha| > 2 rc_max), so a voxel sees at
-   most one image of each atom.  An image's position is fl32(mu_alpha +
-   ((n_0 M[alpha][0] + n_1 M[alpha][1]) + n_2 M[alpha][2])) evaluated in
-   double and rounded once; its windows are then decided exactly as for a
-   non-periodic atom.  The library considers for each atom the K images of
+   most one image of each atom.  An image's position is the exact sum
+   mu_alpha + n_0 M[alpha][0] + n_1 M[alpha][1] + n_2 M[alpha][2] rounded
+   once to float32 (nearest, ties to even; found on the GPU from error-free
+   float32 transforms, no FP64); its windows are then decided exactly as
+   for a non-periodic atom.  The library considers for each atom the K images of
    a fixed lattice range (K <= 64, else PG_E_PERIODIC), keeps those whose
    cutoff cube can meet the grid, and runs the non-periodic map on them; the
    workspace is sized for all K.  Invalid atoms are reported by atom index

@@ -11,10 +11,10 @@ both sides is:
     max_alpha |(M n)_alpha| > 2 rc for every n != 0 (check_cell), so each
     voxel sees at most one image of each atom (for an orthorhombic cell this
     is the nearest-image map of the orthorhombic path);
-  * an image's position is fl32(mu_alpha + (n0 M[alpha,0] + n1 M[alpha,1] +
-    n2 M[alpha,2])), evaluated in double left to right and rounded once to
-    float32; its cutoff windows are then decided exactly on that float32
-    position, as for any non-periodic atom.
+  * an image's position is the exact real sum mu_alpha + n0 M[alpha,0] +
+    n1 M[alpha,1] + n2 M[alpha,2] of the float32 inputs, rounded once to
+    the nearest float32 (ties to even); its cutoff windows are then decided
+    exactly on that float32 position, as for any non-periodic atom.
 
 The functions expand every atom into the images that can reach the grid
 (a generous range, found per atom from its fractional coordinates) and pass
@@ -24,6 +24,7 @@ summed back onto their atom.
 from __future__ import annotations
 
 import itertools
+from fractions import Fraction
 
 import numpy as np
 
@@ -35,16 +36,27 @@ def _cell(M) -> np.ndarray:
     return np.asarray(M, np.float64).reshape(3, 3).astype(np.float32).astype(np.float64)
 
 
+def round_f32(x: Fraction) -> np.float32:
+    """The float32 nearest to the rational x, ties to the even significand."""
+    c = np.float32(float(x))          # within one float32 step of the answer
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        key = (abs(Fraction(float(cand)) - x), int(np.float32(cand).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, cand)
+    return np.float32(best[1])
+
+
 def image_position(mu, M, n) -> np.ndarray:
-    """fl32(mu + M n), the lattice sum evaluated in double left to right."""
+    """fl32(mu + M n): the exact lattice sum, rounded once to float32."""
     M = _cell(M)
-    mu = np.asarray(mu, np.float64)
+    mu = np.asarray(mu, np.float32)
     out = np.empty(3, np.float32)
     for a in range(3):
-        t = float(n[0]) * M[a, 0]
-        t = t + float(n[1]) * M[a, 1]
-        t = t + float(n[2]) * M[a, 2]
-        out[a] = np.float32(float(mu[a]) + t)
+        x = Fraction(float(mu[a]))
+        for j in range(3):
+            x += int(n[j]) * Fraction(float(M[a, j]))
+        out[a] = round_f32(x)
     return out
 
 

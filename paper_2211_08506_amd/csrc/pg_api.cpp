@@ -193,7 +193,7 @@ struct Tri {
     TriParams q;
     pg_grid_desc din;
     pg_batch bin;
-    size_t off_types = 0, off_offs = 0, off_grad = 0, off_istart = 0, inner_off = 0;
+    size_t off_types = 0, off_offs = 0, off_grad = 0, off_istart = 0, off_base = 0, inner_off = 0;
     int32_t K_keep = 1;      // most images one atom can keep
 };
 
@@ -208,7 +208,7 @@ int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
     if (!T.on)
         return PG_OK;
     std::memset(&T.q, 0, sizeof T.q);
-    double *M = T.q.M, *Mi = T.q.Minv;
+    double M[9], Mi[9];
     for (int i = 0; i < 9; ++i)
         M[i] = d->cell_matrix[i];
     const double det = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
@@ -224,6 +224,12 @@ int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
     Mi[6] = (M[3] * M[7] - M[4] * M[6]) / det;
     Mi[7] = (M[1] * M[6] - M[0] * M[7]) / det;
     Mi[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+    // the kernels' copies: the cell as given, its inverse as float-float
+    for (int i = 0; i < 9; ++i) {
+        T.q.M[i] = d->cell_matrix[i];
+        T.q.Minv_hi[i] = (float)Mi[i];
+        T.q.Minv_lo[i] = (float)(Mi[i] - (double)T.q.Minv_hi[i]);
+    }
     double rc_max = 0.0;
     T.q.n_sig = n_sig_of(d, b);
     for (int t = 0; t < T.q.n_sig; ++t) {
@@ -319,7 +325,8 @@ int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
     T.off_offs = T.off_types + align256(nk * 4);
     T.off_grad = T.off_offs + align256(((size_t)b->n_mol + 1) * 4);
     T.off_istart = T.off_grad + align256(nk * 12);
-    T.inner_off = T.off_istart + align256(((size_t)b->n_atoms + 1) * 4);
+    T.off_base = T.off_istart + align256(((size_t)b->n_atoms + 1) * 4);
+    T.inner_off = T.off_base + align256((size_t)b->n_atoms * 12);
     return PG_OK;
 }
 
@@ -340,6 +347,8 @@ void tri_bind(Tri &T, const pg_batch *b, void *ws)
     T.q.exp_types = (int32_t *)(w + T.off_types);
     T.q.exp_offsets = (int32_t *)(w + T.off_offs);
     T.q.grad_img = (const float *)(w + T.off_grad);
+    T.q.cand = (float *)(w + T.off_grad);
+    T.q.base = (float *)(w + T.off_base);
     T.q.istart = (int32_t *)(w + T.off_istart);
     T.q.origins = b->origins;
     T.bin.xyz = T.q.exp_xyz;

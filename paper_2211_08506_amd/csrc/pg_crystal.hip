@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(3 * PREP_BLOCK) cr_prep_kernel(GridParams p, C
             cntm[c][j] = 0u;
     }
     const long long a0 = (long long)blockIdx.x * PREP_BLOCK;
-    const long long a1 = min(p.n_atoms, a0 + PREP_BLOCK) - 1;
+    const long long a1 = (a0 + PREP_BLOCK < p.n_atoms ? a0 + PREP_BLOCK : p.n_atoms) - 1;
     // every wave finds the block's first and last structures (64-ary search)
     const int m_first = structure_of_wave(p.offsets, p.n_mol, a0);
     const int m_last = structure_of_wave(p.offsets, p.n_mol, a1);

@@ -95,11 +95,14 @@ struct TriParams {
     int32_t *exp_types;      // n_atoms * K (-1: invalid atom)
     int32_t *exp_offsets;    // n_mol + 1: offsets * K
     const float *grad_img;   // image gradients, in image order
+    float *cand;             // K x n_atoms x 3 candidate image positions (NaN: misses the
+                             // grid); the same memory as grad_img, used before it
+    float *base;             // n_atoms x 3: lattice index of each atom's candidate image 0
     float *grad;             // n_atoms x 3 (may be nullptr)
     int32_t *istart;         // n_atoms + 1: images per atom, then their exclusive scan
     const float *origins;    // per-structure grid origins, or nullptr
-    double M[9];             // cell, row-major: M[3 * alpha + j] = alpha component of vector j
-    double Minv[9];
+    float M[9];              // cell, row-major: M[3 * alpha + j] = alpha component of vector j
+    float Minv_hi[9], Minv_lo[9];   // its inverse as float-float pairs (hi + lo)
     float o[3], h[3];        // grid origin and spacing (x, y, z)
     float rc[PG_MAX_CHANNELS];
     int32_t N[3];            // grid points along x, y, z

@@ -141,3 +141,27 @@ def test_triclinic_graph_replay(pg, dev):
         torch.cuda.synchronize()
         check(f"graph rep {r}", out, ref, F32_TOL)
     assert ctx.device_error()[0] == 0
+
+
+@pytest.mark.parametrize("M", [SHEAR, SKEW], ids=["shear-dyadic", "skew"])
+def test_image_positions_are_the_oracles_bit_for_bit(pg, dev, M):
+    """Image positions are the exact lattice sums rounded once to float32 on
+    both sides.  With one atom per structure a voxel sees at most one image,
+    so the triclinic grid must equal, bit for bit, the non-periodic grid over
+    the oracle's images: a position one ulp off moves its window or its
+    values.  The dyadic shear cell makes exact ties frequent (sums crossing
+    a binade); the skew cell's entries are not dyadic."""
+    rng = np.random.default_rng(64)
+    n = 96
+    f = rng.uniform(-0.3, 1.3, size=(n, 3))
+    xyz = (f @ np.asarray(M, np.float64).T).astype(np.float32)
+    b = synth.Batch(xyz, rng.integers(0, 3, n).astype(np.int32), np.arange(n + 1, dtype=np.int32))
+    sig = synth.sigma_table(3, 0.35, 0.55)
+    dims, h, o = (20, 24, 28), 0.3, (0.5, -0.25, 1.0)
+    rc_max = float(np.max(np.float32(3.0) * np.asarray(sig, np.float32)))
+    xi, ti, oi, _ = triclinic.expand(b.xyz, b.types, b.offsets, M, dims, h, o, rc_max)
+    imgs = synth.Batch(xi, ti, oi.astype(np.int32))
+    say(f"case triclinic image positions {M[0, 1]} ({len(xi)} oracle images)")
+    g_tri = run(pg, dev, b, sig, dims, h, o, M, form="window")
+    g_img = run(pg, dev, imgs, sig, dims, h, o, None, form="window")
+    assert torch.equal(g_tri, g_img)

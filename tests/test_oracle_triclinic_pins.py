@@ -129,3 +129,51 @@ def test_cell_check_rejects_overlapping_image_cubes():
     # n = (-1, 1, 0) gives (-1, 1.5, 0): Chebyshev norm 1.5 <= 2 rc for rc = 0.9
     assert not triclinic.check_cell(thin, 0.9)
     assert triclinic.check_cell(thin, 0.7)
+
+
+# -- image positions: the exact lattice sum rounded once to float32 --------
+
+EDGE = np.array([[2.0 ** -24, 2.0 ** -80, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+@pytest.mark.parametrize("n,want", [
+    ((1, 0, 0), 1.0),                         # 1 + 2^-24: a tie, to the even 1
+    ((3, 0, 0), 1.0 + 2.0 ** -22),            # 1 + 3 2^-24: a tie, to the even neighbour above
+    ((1, 1, 0), 1.0 + 2.0 ** -23),            # just past the tie: up (double arithmetic
+                                              # would round 1 + 2^-24 + 2^-80 to the tie, then down)
+    ((-1, 0, 0), 1.0 - 2.0 ** -24),           # below 1 the step is 2^-24: exact
+    ((0, 0, 0), 1.0),
+])
+def test_image_position_rounds_the_exact_sum_once(n, want):
+    got = triclinic.image_position(np.array([1.0, 0.0, 0.0], np.float32), EDGE, n)
+    assert got[0] == np.float32(want)
+
+
+def test_image_position_exact_when_representable():
+    """Integer-valued coordinates and cell entries below 2^20 with small n:
+    every exact sum is an integer below 2^24, a float32, so rounding is the
+    identity."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        mu = rng.integers(-2 ** 19, 2 ** 19, 3).astype(np.float32)
+        M = rng.integers(-2 ** 19, 2 ** 19, (3, 3)).astype(np.float64)
+        n = rng.integers(-4, 5, 3)
+        want = mu.astype(np.int64) + M.astype(np.int64) @ n
+        got = triclinic.image_position(mu, M, n)
+        np.testing.assert_array_equal(got.astype(np.int64), want)
+
+
+def test_round_f32_is_nearest_with_ties_to_even():
+    """round_f32 against its definition on rationals: no float32 neighbour
+    of the result is nearer, and at a tie the result's significand is even."""
+    from fractions import Fraction
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        x = Fraction(int(rng.integers(-10 ** 12, 10 ** 12)), int(rng.integers(1, 10 ** 6)))
+        r = triclinic.round_f32(x)
+        d = abs(Fraction(float(r)) - x)
+        for nb in (np.nextafter(r, np.float32(np.inf)), np.nextafter(r, np.float32(-np.inf))):
+            dn = abs(Fraction(float(nb)) - x)
+            assert d <= dn
+            if d == dn:
+                assert int(np.float32(r).view(np.uint32)) & 1 == 0
