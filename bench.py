@@ -198,39 +198,62 @@ PAPER_CPU_CONTEXT = [
 ]
 
 
-def cpu_oracle_baseline(units, run_one, seconds, describe, max_threads=None, pool_units=None):
-    """Time the FP64 oracle on a bounded sample: run_one(unit) computes the
-    grids of one unit (one oracle call) and returns how many; units are taken
-    cycling through the list, first on one thread (units), then on P worker
-    threads with one task per unit of pool_units (one structure per task, as
-    data-loader workers would make them; the oracle's C entry points release
-    the GIL, so the threads run in parallel).  P is the process's CPU
-    affinity, capped at the host share of one GPU (16 cores)."""
+def _oracle_call(spec):
+    """One FP64 oracle call of the CPU baseline leg, in this process or in a
+    pool worker: spec = (entry, args, kwargs, grids); returns the grids."""
+    name, a, kw, n = spec
+    import oracle as cpu_oracle
+    if name == "grid":
+        cpu_oracle.grid_fp64(*a, **kw)
+    elif name == "grid_tri":
+        from oracle import triclinic as cpu_triclinic
+        cpu_triclinic.grid_triclinic_fp64(*a, **kw)
+    elif name == "grad":
+        cpu_oracle.grad_fp64(*a, **kw)
+    elif name == "rev":
+        from oracle import reversal as cpu_reversal
+        cpu_reversal.reversal_step(*a, **kw)
+    return n
+
+
+def cpu_oracle_baseline(units, make_spec, seconds, describe, max_procs=None, pool_units=None):
+    """Time the FP64 oracle on a bounded sample: make_spec(unit) describes
+    one oracle call (_oracle_call) over the unit's structures; units are
+    taken cycling through the list, first in this process, then on P worker
+    processes (spawned, so they share nothing with this process's GPU state)
+    with one task per unit of pool_units (a molecule's grid takes about a
+    tenth of a millisecond, so tasks of 16 molecules keep the inter-process
+    traffic small; a crystal cell is a task).  P is the process's CPU affinity,
+    capped at the host share of one GPU (16 cores); the pool is started and
+    its workers have imported the oracle before the clock starts."""
+    import multiprocessing
     t0 = time.perf_counter()
     n1 = i = 0
     while time.perf_counter() - t0 < seconds * 0.6 or i < 1:
-        n1 += run_one(units[i % len(units)])
+        n1 += _oracle_call(make_spec(units[i % len(units)]))
         i += 1
     dt1 = time.perf_counter() - t0
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
-    P = max(1, min(max_threads or CPU_THREADS_MAX, avail))
+    P = max(1, min(max_procs or CPU_THREADS_MAX, avail))
     pool_units = pool_units or units
     nP = i = 0
-    t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(P) as ex:
+    with cf.ProcessPoolExecutor(P, mp_context=multiprocessing.get_context("spawn")) as ex:
+        warm = make_spec(pool_units[0])
+        list(ex.map(_oracle_call, [warm] * P))   # worker start-up and imports, untimed
+        t0 = time.perf_counter()
         while time.perf_counter() - t0 < seconds * 0.4 or i < P:
-            nP += sum(ex.map(run_one, [pool_units[(i + j) % len(pool_units)]
-                                       for j in range(4 * P)]))
+            nP += sum(ex.map(_oracle_call, [make_spec(pool_units[(i + j) % len(pool_units)])
+                                            for j in range(4 * P)], chunksize=2))
             i += 4 * P
-    dtP = time.perf_counter() - t0
-    log(f"[bench] oracle: 1 thread {n1} grids in {dt1:.1f} s; {P} threads {nP} in {dtP:.1f} s")
+        dtP = time.perf_counter() - t0
+    log(f"[bench] oracle: 1 process {n1} grids in {dt1:.1f} s; {P} processes {nP} in {dtP:.1f} s")
     return {"value": n1 / dt1, "unit": "grids/s", "cores": 1, "kind": "oracle",
             "sample": describe(n1, dt1, 1, False),
-            "threads": {"value": nP / dtP, "unit": "grids/s", "cores": P, "affinity": avail,
-                        "sample": describe(nP, dtP, P, True)},
+            "processes": {"value": nP / dtP, "unit": "grids/s", "cores": P, "affinity": avail,
+                          "sample": describe(nP, dtP, P, True)},
             "paper_cpu_context": PAPER_CPU_CONTEXT}
 
 
@@ -553,46 +576,40 @@ def main():
         if kind == "reversal step":
             from oracle import reversal as cpu_reversal
 
-            def run_one(u):
+            def make_spec(u):
                 m, s = u
                 a0, a1 = b.offsets[m], b.offsets[m + s.n_mol]
-                cpu_reversal.reversal_step(x0[a0:a1], s.types, s.offsets, sig, wl.dims,
-                                           wl.spacing, Th[m:m + s.n_mol], lr, wl.origin,
-                                           cutoff_k=wl.cutoff_k, value=value)
-                return s.n_mol
+                return ("rev", (x0[a0:a1], s.types, s.offsets, sig, wl.dims, wl.spacing,
+                                Th[m:m + s.n_mol], lr, wl.origin),
+                        {"cutoff_k": wl.cutoff_k, "value": value}, s.n_mol)
         elif kind == "adjoint":
             Uh = synth.upstream(wl.upstream_seed, wl.grid_shape())
 
-            def run_one(u):
+            def make_spec(u):
                 m, s = u
-                cpu_oracle.grad_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
-                                     Uh[m:m + s.n_mol], wl.origin, cutoff_k=wl.cutoff_k,
-                                     value=value)
-                return s.n_mol
+                return ("grad", (s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
+                                 Uh[m:m + s.n_mol], wl.origin),
+                        {"cutoff_k": wl.cutoff_k, "value": value}, s.n_mol)
         else:
-            def run_one(u):
+            def make_spec(u):
                 s = u[1]
                 if args.triclinic:
-                    from oracle import triclinic as cpu_triclinic
-                    cpu_triclinic.grid_triclinic_fp64(s.xyz, s.types, s.offsets, sig, wl.dims,
-                                                      wl.spacing, cell, wl.origin,
-                                                      cutoff_k=wl.cutoff_k, value=value)
-                    return s.n_mol
-                cpu_oracle.grid_fp64(s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
-                                     wl.origin, cutoff_k=wl.cutoff_k, cell=wl.cell, value=value,
-                                     weights=None if E is None else table[s.types])
-                return s.n_mol
-        pool_units = [(m, b.subset(range(m, m + 1))) for m in range(B)] if chunk > 1 else units
+                    return ("grid_tri", (s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing,
+                                         cell, wl.origin),
+                            {"cutoff_k": wl.cutoff_k, "value": value}, s.n_mol)
+                return ("grid", (s.xyz, s.types, s.offsets, sig, wl.dims, wl.spacing, wl.origin),
+                        {"cutoff_k": wl.cutoff_k, "cell": wl.cell, "value": value,
+                         "weights": None if E is None else table[s.types]}, s.n_mol)
+        pool_units = units
         log(f"[bench] FP64 CPU oracle on a bounded sample (~{args.cpu_seconds:.0f} s)")
         per_unit = "cell" if wl.kind == "crystal" else "molecule"
         cpu = cpu_oracle_baseline(
-            units, run_one, args.cpu_seconds,
+            units, make_spec, args.cpu_seconds,
             lambda n, dt, P, pool: (
                 f"{n} {kind} grids of the {B}-structure batch, {1 if pool else chunk} "
                 f"{per_unit}(s) per oracle call cycling through the batch ({n / B:.2f} passes), "
-                f"dense FP64 {C}x{D}x{H}x{W}, {P} thread(s), {dt:.1f} s"),
-            pool_units=pool_units,
-            max_threads=1 if args.triclinic else None)
+                f"dense FP64 {C}x{D}x{H}x{W}, {P} process(es), {dt:.1f} s"),
+            pool_units=pool_units)
     rec["cpu_baseline"] = cpu
 
     if not args.no_cpu:
