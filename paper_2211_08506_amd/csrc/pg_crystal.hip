@@ -813,9 +813,21 @@ struct LaneImage {
     uint32_t yslot, xslot;
 };
 
+// List entry e, or an empty one (atom -1) past the range.
+__device__ __forceinline__ TileEntry tile_entry(const CrystalParams &q, uint32_t e, uint32_t end)
+{
+    TileEntry te;
+    te.atom = -1;
+    te.zs = 0u;
+    te.bh = te.bl = 0.f;
+    if (e < end)
+        te = q.tcl[e];
+    return te;
+}
+
 template <int ZP>
 __device__ __forceinline__ LaneImage<ZP> lane_image(const GridParams &p, const CrystalParams &q,
-                                                    uint32_t e, uint32_t end, int z0, int c,
+                                                    const TileEntry &te, int z0, int c,
                                                     float inv2s2_c, float isq2s_c)
 {
     LaneImage<ZP> li;
@@ -823,8 +835,7 @@ __device__ __forceinline__ LaneImage<ZP> lane_image(const GridParams &p, const C
     for (int k = 0; k < ZP; ++k)
         li.gz[k] = 0.f;
     li.yslot = li.xslot = 0u;
-    if (e < end) {
-        const TileEntry te = q.tcl[e];
+    if (te.atom >= 0) {
         const int zlo = entry_zlo(te.zs), zhi = min(entry_zhi(te.zs), p.D - 1);
         float inv2s2 = inv2s2_c, isq2s = isq2s_c, wgt = 1.f;
         if (p.weights) {
@@ -934,8 +945,17 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
     typedef float f2 __attribute__((ext_vector_type(2)));
     typedef __bf16 b2 __attribute__((ext_vector_type(2)));
     typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-    for (uint32_t c0 = first; c0 < end; c0 += KCH) {
-        const LaneImage<ZP> li = lane_image<ZP>(p, q, c0 + lane, end, it.z0, it.c, inv2s2_c, isq2s_c);
+    // each lane evaluates one entry of 64 (phi_z at the wave's planes and its
+    // slots), consumed as 64 / KCH chunks of KCH entries
+    static_assert(64 % KCH == 0, "chunks divide a wave's 64 entries");
+    for (uint32_t c64 = first; c64 < end; c64 += 64) {
+      const LaneImage<ZP> li =
+          lane_image<ZP>(p, q, tile_entry(q, c64 + lane, end), it.z0, it.c, inv2s2_c, isq2s_c);
+#pragma unroll 1
+      for (int ch = 0; ch < 64 / KCH; ++ch) {
+        const uint32_t c0 = c64 + (uint32_t)(ch * KCH);
+        if (c0 >= end)
+            break;
         const int nst = (int)((min((uint32_t)KCH, end - c0) + KS - 1) / KS);
         float4 ya[KCH / KS][2];
         b4 xb[KCH / KS][2];
@@ -944,7 +964,7 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
         for (int st = 0; st < KCH / KS; ++st)
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int src = KS * st + 2 * ip + u;
+                const int src = ch * KCH + KS * st + 2 * ip + u;
 #pragma unroll
                 for (int k = 0; k < ZP; ++k)
                     gg[st][u][k] = __shfl(li.gz[k], src, 64);
@@ -954,7 +974,7 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     xb[st][u][r] = (__bf16)0.f;
-                if (st < nst && c0 + (uint32_t)src < end) {
+                if (st < nst && c64 + (uint32_t)src < end) {
                     ya[st][u] = *(const float4 *)(yv + (size_t)ys * 32 + 4 * g);
                     xb[st][u] = *(const b4 *)(xv + (size_t)xs * 32 + 4 * g);
                 }
@@ -986,6 +1006,7 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
         }
+      }
     }
 #pragma unroll
     for (int k = 0; k < ZP; ++k) {
@@ -1023,8 +1044,10 @@ __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalP
 #pragma unroll
         for (int e = 0; e < 16; ++e)
             acc[k][e] = 0.f;
+    static_assert(KCH == 64, "one list entry per lane");
     for (uint32_t c0 = first; c0 < end; c0 += KCH) {
-        const LaneImage<ZP> li = lane_image<ZP>(p, q, c0 + lane, end, it.z0, it.c, inv2s2_c, isq2s_c);
+        const LaneImage<ZP> li =
+            lane_image<ZP>(p, q, tile_entry(q, c0 + lane, end), it.z0, it.c, inv2s2_c, isq2s_c);
         const int npair = (int)((min((uint32_t)KCH, end - c0) + 1) / 2);
         for (int p0 = 0; p0 < npair; p0 += PB) {
             float av[PB], bv[PB], gg[PB][ZP];
