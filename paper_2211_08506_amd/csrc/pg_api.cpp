@@ -453,8 +453,10 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
         const long long n_tcl = 32 * P.op_blocks * ss;
         if (P.sx_max > 16 || P.sy_max > 16 || n_tcl > 0xffffffffLL)   // slots packed in 4 bits
             return PG_E_UNSUPPORTED;
-        // slots: bf16 for bf16 grids, float (split into fp16 pairs in the
-        // plane kernel) for fp32 grids
+        // the tile kernels address slot values by 32-bit byte offsets
+        if ((long long)b->n_atoms * std::max(P.sx_max, P.sy_max) * 32 * 4 > 0xffffffffLL)
+            return PG_E_UNSUPPORTED;
+        // slots: x bf16 for bf16 grids and float for fp32 grids, y float
         P.ws_tmask = off;
         off += align256((size_t)b->n_atoms * 2 * 4);
         P.ws_xval = off;
@@ -548,8 +550,8 @@ int make_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, const
             form = PG_FORM_WINDOW;
         } else {
             // large structures: the MFMA contraction (bf16 factors for bf16
-            // grids, split fp16 factors at the FP32 bar for fp32 grids).  A
-            // measured choice (pg_autotune) overrides.
+            // grids, FP32 factors on the FP32 matrix instruction for fp32
+            // grids).  A measured choice (pg_autotune) overrides.
             form = PG_FORM_MFMA;
             if (ctx) {
                 auto it = ctx->tuning.find(tuning_key(d, b, P.vec));

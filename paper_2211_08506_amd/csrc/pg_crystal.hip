@@ -866,26 +866,50 @@ __device__ __forceinline__ LaneImage<ZP> lane_image(const GridParams &p, const C
     return li;
 }
 
-// A wave's 32 x 32 tile (accumulators: lane l holds column l % 32 of rows
-// 8 (e / 4) + 4 (l / 32) + e % 4) goes through the wave's LDS buffer as T,
-// then out in 16-byte pieces, whole 32-element row segments.  Rows and
+// A wave's 32 x 32 tiles (accumulators: lane l holds column l % 32 of rows
+// 8 (e / 4) + 4 (l / 32) + e % 4) go through the wave's LDS buffer as T, one
+// plane at a time, then out in 16-byte pieces, whole 32-element row
+// segments (no bounds tests when the tile lies inside the plane).  Rows and
 // columns past the plane edge are not written; unaligned rows fall back to
 // element stores.
 template <typename T>
-__device__ __forceinline__ void store_tile(T *out, int H, int W, int y0, int x0, bool nt,
-                                           const f32x16 &acc, T *ls)
+constexpr int tile_lrow() { return 32 + 16 / (int)sizeof(T); }   // padded LDS row (elements)
+
+template <typename T>
+__device__ __forceinline__ void tile_to_lds(const f32x16 &acc, T *ls)
 {
-    constexpr int LROW = 32 + 16 / (int)sizeof(T);   // padded LDS row (elements)
-    constexpr int EPL = 16 / (int)sizeof(T);         // elements per 16-byte piece
-    constexpr int LPR = 32 / EPL;                    // lanes per row
-    constexpr int RPI = 64 / LPR;                    // rows per store instruction
+    constexpr int LROW = tile_lrow<T>();
     const int lane = threadIdx.x & 63;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the buffer's last reads are done
 #pragma unroll
     for (int e = 0; e < 16; ++e)
         ls[(8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)) * LROW + (lane & 31)] = (T)acc[e];
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_to_global(T *out, int H, int W, int y0, int x0, bool nt, const T *ls)
+{
+    constexpr int LROW = tile_lrow<T>();
+    constexpr int EPL = 16 / (int)sizeof(T);         // elements per 16-byte piece
+    constexpr int LPR = 32 / EPL;                    // lanes per row
+    constexpr int RPI = 64 / LPR;                    // rows per store instruction
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
     const bool vec = ((size_t)W * sizeof(T)) % 16 == 0 && ((uintptr_t)out & 15) == 0;
+    if (vec && y0 + 32 <= H && x0 + 32 <= W) {
+        // the whole tile lies inside the plane: every piece is a 16-byte store
+        const int r0 = lane / LPR, cs = EPL * (lane % LPR);
+        const T *src = ls + r0 * LROW + cs;
+        T *dst = out + (size_t)(y0 + r0) * W + x0 + cs;
+#pragma unroll
+        for (int k = 0; k < 32 / RPI; ++k) {
+            const u4 v = *(const u4 *)(src + RPI * k * LROW);
+            if (nt)
+                __builtin_nontemporal_store(v, (u4 *)(dst + (size_t)(RPI * k) * W));
+            else
+                *(u4 *)(dst + (size_t)(RPI * k) * W) = v;
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 32 / RPI; ++k) {
         const int r = RPI * k + lane / LPR, cs = EPL * (lane % LPR);
@@ -895,7 +919,6 @@ __device__ __forceinline__ void store_tile(T *out, int H, int W, int y0, int x0,
         const T *src = ls + r * LROW + cs;
         T *dst = out + (size_t)y * W + x;
         if (vec && x + EPL <= W) {
-            typedef uint32_t u4 __attribute__((ext_vector_type(4)));
             const u4 v = *(const u4 *)src;
             if (nt)
                 __builtin_nontemporal_store(v, (u4 *)dst);
@@ -905,6 +928,25 @@ __device__ __forceinline__ void store_tile(T *out, int H, int W, int y0, int x0,
             for (int u = 0; u < EPL && x + u < W; ++u)
                 dst[u] = src[u];
         }
+    }
+}
+
+// The wave's ZP planes from z0 on (those below D) through ls (32 x
+// tile_lrow<T>() elements).
+template <typename T, int ZP>
+__device__ __forceinline__ void store_tiles(const GridParams &p, const TileItem &it, const f32x16 (&acc)[ZP],
+                                            T *ls)
+{
+#pragma unroll
+    for (int k = 0; k < ZP; ++k) {
+        const int z = it.z0 + k;
+        if (z >= p.D)
+            break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the buffer's last reads are done
+        tile_to_lds<T>(acc[k], ls);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        T *out = (T *)p.out + (((size_t)it.m * p.C + it.c) * p.D + z) * (size_t)p.H * p.W;
+        lds_to_global<T>(out, p.H, p.W, 32 * it.ty, 32 * it.tx, p.nt_store != 0, ls);
     }
 }
 
@@ -922,7 +964,10 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
 {
     // entries per chunk (one list entry per lane, KCH <= 64), their slot rows
     // loaded before the chunk's first step
-    constexpr int WBUF = 2 * 32 * AST;   // bf16 per wave: staging 2 x 32 x AST >= store 32 x 40
+    // bf16 per wave: staging 2 x 32 x AST (phi_x, then one plane's A at a
+    // time) >= one output tile 32 x tile_lrow
+    constexpr int WBUF = 2 * 32 * AST;
+    static_assert(WBUF >= 32 * tile_lrow<__bf16>(), "the output tile fits the staging buffer");
     __shared__ __attribute__((aligned(16))) __bf16 lds[4][WBUF];
     const TileItem it = tile_item<ZP>(p, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -931,11 +976,12 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
     if (it.tx >= q.ntx || it.z0 >= p.D)
         return;
     const float inv2s2_c = p.inv2s2[it.c], isq2s_c = p.isq2s[it.c];
-    uint32_t *As = (uint32_t *)lds[wave], *Bs = (uint32_t *)(lds[wave] + 32 * AST);
+    __bf16 *Bs = lds[wave], *As = lds[wave] + 32 * AST;
     const int ip = lane >> 3, g = lane & 7;   // image pair, row group
+    const int wo = 4 * g * AST + 2 * ip;      // the lane's staged pair, row 4 g
     const int fo = (lane & 31) * AST + 8 * (lane >> 5);
-    const float *yv = (const float *)q.yval;
-    const __bf16 *xv = (const __bf16 *)q.xval;
+    // slot rows by 32-bit byte offsets (the plan keeps each slot array below 4 GiB)
+    const char *ybase = (const char *)q.yval, *xbase = (const char *)q.xval;
     f32x16 acc[ZP];
 #pragma unroll
     for (int k = 0; k < ZP; ++k)
@@ -975,8 +1021,8 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
                 for (int r = 0; r < 4; ++r)
                     xb[st][u][r] = (__bf16)0.f;
                 if (st < nst && c64 + (uint32_t)src < end) {
-                    ya[st][u] = *(const float4 *)(yv + (size_t)ys * 32 + 4 * g);
-                    xb[st][u] = *(const b4 *)(xv + (size_t)xs * 32 + 4 * g);
+                    ya[st][u] = *(const float4 *)(ybase + (ys * 128u + 16u * g));
+                    xb[st][u] = *(const b4 *)(xbase + (xs * 64u + 8u * g));
                 }
             }
 #pragma unroll
@@ -986,10 +1032,10 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const b2 pb = {xb[st][0][r], xb[st][1][r]};
-                Bs[((4 * g + r) * AST + 2 * ip) / 2] = __builtin_bit_cast(uint32_t, pb);
+                *(uint32_t *)(Bs + r * AST + wo) = __builtin_bit_cast(uint32_t, pb);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            const bf16x8 bf = *(const bf16x8 *)((const __bf16 *)Bs + fo);
+            const bf16x8 bf = *(const bf16x8 *)(Bs + fo);
             const float y0[4] = {ya[st][0].x, ya[st][0].y, ya[st][0].z, ya[st][0].w};
             const float y1[4] = {ya[st][1].x, ya[st][1].y, ya[st][1].z, ya[st][1].w};
 #pragma unroll
@@ -997,25 +1043,17 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const f2 pr = {y0[r] * gg[st][0][k], y1[r] * gg[st][1][k]};
-                    As[((4 * g + r) * AST + 2 * ip) / 2] =
-                        __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, b2));
+                    *(uint32_t *)(As + r * AST + wo) = __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, b2));
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                const bf16x8 af = *(const bf16x8 *)((const __bf16 *)As + fo);
+                const bf16x8 af = *(const bf16x8 *)(As + fo);
                 acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, acc[k], 0, 0, 0);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
         }
       }
     }
-#pragma unroll
-    for (int k = 0; k < ZP; ++k) {
-        const int z = it.z0 + k;
-        if (z >= p.D)
-            break;
-        __bf16 *out = (__bf16 *)p.out + (((size_t)it.m * p.C + it.c) * p.D + z) * (size_t)p.H * p.W;
-        store_tile<__bf16>(out, p.H, p.W, 32 * it.ty, 32 * it.tx, p.nt_store != 0, acc[k], lds[wave]);
-    }
+    store_tiles<__bf16, ZP>(p, it, acc, lds[wave]);
 }
 
 // fp32 grids: v_mfma_f32_32x32x2_f32 takes one value of A and one of B per
@@ -1023,12 +1061,18 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
 // l % 32 -- which is one float of that entry's y or x slot: the slots are
 // read straight into the operands (no transposition), A scaled by phi_z of
 // each plane in FP32.  Exact FP32 products, FP32 accumulation; per pair of
-// entries one MFMA per plane.
+// entries one MFMA per plane.  Each lane publishes its entry's phi_z and slot
+// indices in the wave's LDS once per 64 entries; the slot values of the next
+// PB pairs are loaded while the current PB pairs are contracted.
 template <int ZP, int KCH>
 __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalParams q)
 {
-    constexpr int PB = 8;   // entry pairs whose operands are loaded together
-    __shared__ __attribute__((aligned(16))) float lds[4][32 * (32 + 4)];
+    static_assert(KCH == 64, "one list entry per lane");
+    static_assert(ZP == 4, "phi_z of the wave's planes is published as one float4 per entry");
+    constexpr int PB = 8;   // entry pairs per load group
+    __shared__ __attribute__((aligned(16))) float lds[4][32 * tile_lrow<float>()];
+    __shared__ float4 gzs[4][64];   // per wave: phi_z of its 64 entries at its planes
+    __shared__ uint2 sls[4][64];    // per wave: their (y slot, x slot)
     const TileItem it = tile_item<ZP>(p, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t first, end;
@@ -1036,53 +1080,64 @@ __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalP
     if (it.tx >= q.ntx || it.z0 >= p.D)
         return;
     const float inv2s2_c = p.inv2s2[it.c], isq2s_c = p.isq2s[it.c];
-    const int j = lane & 31, hi = lane >> 5;
-    const float *yv = (const float *)q.yval, *xv = (const float *)q.xval;
+    const uint32_t j = lane & 31;
+    const int hi = lane >> 5;
+    // slot rows by 32-bit byte offsets (the plan keeps each slot array below 4 GiB)
+    const char *yb = (const char *)q.yval, *xb = (const char *)q.xval;
     f32x16 acc[ZP];
 #pragma unroll
     for (int k = 0; k < ZP; ++k)
 #pragma unroll
         for (int e = 0; e < 16; ++e)
             acc[k][e] = 0.f;
-    static_assert(KCH == 64, "one list entry per lane");
     for (uint32_t c0 = first; c0 < end; c0 += KCH) {
         const LaneImage<ZP> li =
             lane_image<ZP>(p, q, tile_entry(q, c0 + lane, end), it.z0, it.c, inv2s2_c, isq2s_c);
-        const int npair = (int)((min((uint32_t)KCH, end - c0) + 1) / 2);
-        for (int p0 = 0; p0 < npair; p0 += PB) {
-            float av[PB], bv[PB], gg[PB][ZP];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the last chunk's reads are done
+        gzs[wave][lane] = make_float4(li.gz[0], li.gz[1], li.gz[2], li.gz[3]);
+        sls[wave][lane] = make_uint2(li.yslot, li.xslot);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const int nv = (int)min((uint32_t)KCH, end - c0);   // entries of this chunk
+        const int npair = (nv + 1) / 2;
+        // slot values of pairs p0 .. p0 + PB - 1, loaded without branches (the
+        // entry index is clamped to the wave's 64; entries past the chunk's
+        // have slot indices 0, an allocated slot) and zeroed where used
+        auto load_group = [&](int p0, float (&av)[PB], float (&bv)[PB]) {
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
-                const int src = 2 * (p0 + u) + hi;   // < 64 as p0 + u < 32
-#pragma unroll
-                for (int k = 0; k < ZP; ++k)
-                    gg[u][k] = __shfl(li.gz[k], src, 64);
-                const uint32_t ys = (uint32_t)__shfl((int)li.yslot, src, 64);
-                const uint32_t xs = (uint32_t)__shfl((int)li.xslot, src, 64);
-                av[u] = bv[u] = 0.f;
-                if (p0 + u < npair && c0 + (uint32_t)src < end) {
-                    av[u] = yv[(size_t)ys * 32 + j];
-                    bv[u] = xv[(size_t)xs * 32 + j];
-                }
+                const uint2 sl = sls[wave][min(2 * (p0 + u) + hi, 63)];
+                av[u] = *(const float *)(yb + (sl.x * 128u + 4u * j));
+                bv[u] = *(const float *)(xb + (sl.y * 128u + 4u * j));
             }
+        };
+        auto mma_group = [&](int p0, const float (&av)[PB], const float (&bv)[PB]) {
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
                 if (p0 + u >= npair)
                     break;
-#pragma unroll
-                for (int k = 0; k < ZP; ++k)
-                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u] * gg[u][k], bv[u], acc[k], 0, 0, 0);
+                const int src = 2 * (p0 + u) + hi;   // < 64 as p0 + u < 32
+                const float4 g = gzs[wave][src];
+                const float a = src < nv ? av[u] : 0.f, b = src < nv ? bv[u] : 0.f;
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a * g.x, b, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a * g.y, b, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a * g.z, b, acc[2], 0, 0, 0);
+                acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a * g.w, b, acc[3], 0, 0, 0);
             }
+        };
+        float a0[PB], b0[PB], a1[PB], b1[PB];
+        load_group(0, a0, b0);
+        for (int p0 = 0; p0 < npair; p0 += 2 * PB) {
+            if (p0 + PB < npair)
+                load_group(p0 + PB, a1, b1);
+            mma_group(p0, a0, b0);
+            if (p0 + PB >= npair)
+                break;
+            if (p0 + 2 * PB < npair)
+                load_group(p0 + 2 * PB, a0, b0);
+            mma_group(p0 + PB, a1, b1);
         }
     }
-#pragma unroll
-    for (int k = 0; k < ZP; ++k) {
-        const int z = it.z0 + k;
-        if (z >= p.D)
-            break;
-        float *out = (float *)p.out + (((size_t)it.m * p.C + it.c) * p.D + z) * (size_t)p.H * p.W;
-        store_tile<float>(out, p.H, p.W, 32 * it.ty, 32 * it.tx, p.nt_store != 0, acc[k], lds[wave]);
-    }
+    store_tiles<float, ZP>(p, it, acc, lds[wave]);
 }
 
 constexpr int ZP_BF16 = 4;    // planes per wave of the bf16 tile kernel

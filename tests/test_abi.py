@@ -393,6 +393,25 @@ def test_host_only_plan_wide_plane_takes_window_form():
         lib.pg_destroy(h)
 
 
+def test_plan_mfma_slot_arrays_below_4gib():
+    """The MFMA tile kernels address factor-slot values by 32-bit byte
+    offsets: a batch whose slot array would reach 4 GiB is refused by the
+    MFMA form, and AUTO takes the binned vector form instead."""
+    lib = pg._lib()
+    d = desc_ok(form="mfma", out_dtype="bf16")
+    # 32^3 grid: one 32-voxel slot per atom and axis, 128 bytes per float slot
+    ok = batch_ok(n_mol=4, n_atoms=(1 << 25) - 1024, max_atoms=1000)
+    huge = batch_ok(n_mol=4, n_atoms=(1 << 25) + 1024, max_atoms=1000)
+    info = pg.PlanInfo()
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(ok), 0x10000, ctypes.byref(info)) == pg.PG_OK
+    assert info.form == pg.FORMS["mfma"] and info.binned == 1
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(huge), 0x10000,
+                       ctypes.byref(info)) == pg.PG_E_UNSUPPORTED
+    d = desc_ok(form="auto", out_dtype="bf16")
+    assert lib.pg_plan(None, ctypes.byref(d), ctypes.byref(huge), 0x10000, ctypes.byref(info)) == pg.PG_OK
+    assert info.form == pg.FORMS["window"] and info.binned == 1
+
+
 def test_tuning_table_round_trip_and_plan(tmp_path):
     lib, h = host_ctx()
     try:

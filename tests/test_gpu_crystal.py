@@ -4,8 +4,8 @@ against the FP64 oracle, through the C ABI.
 
 Bars: the FP32 vector form (form="window" on large structures) to the FP32
 bar rel-L2 <= 1e-5; the MFMA form contracts bf16 factors for bf16 grids (BF16
-bar rel-L2 <= 1e-2) and, for float32 grids, factors split into fp16 pairs
-with three products per step (FP32 bar).
+bar rel-L2 <= 1e-2) and FP32 factors on the FP32 matrix instruction for
+float32 grids (FP32 bar).
 """
 import numpy as np
 import pytest
@@ -134,10 +134,51 @@ def test_mfma_many_and_few_runs(pg, dev, dtype, tol):
         assert torch.equal(g, again), name
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.bfloat16, BF16_TOL), (torch.float32, F32_TOL)])
+def test_mfma_other_stream_and_graph_replay(pg, dev, dtype, tol):
+    """The MFMA form's launch sequence (prep, scans, partition, factor
+    slots, tile sort, tile kernel): the eager result matches the oracle, and
+    a run on another caller stream and replays of the captured graph (eager
+    work and synchronisation between them) reproduce it bit for bit."""
+    say(f"case mfma other stream and graph replay dtype={dtype}")
+    sig = synth.sigma_table(3, 0.3, 0.45)
+    b = cell_batch(41, [900, 1500, 600], 10.0, 3)
+    dims, h = (48, 48, 48), 10.0 / 48
+    xyz, types, offs = to_device(b, dev)
+    ctx = pg.Context(0)
+    desc = pg.make_desc(3, dims, h, (0, 0, 0), sig, 3.0, 10.0, dtype, "mfma")
+    bv = pg.BatchView(xyz, types, offs, offsets_host=b.offsets)
+    eager = pg.empty_grid(desc, b.n_mol, dev)
+    ctx.forward(desc, bv, eager)
+    torch.cuda.synchronize()
+    ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, dims, h, (0, 0, 0), cell=10.0)
+    check(f"mfma eager/{dtype}", eager, ref, tol)
+    s = torch.cuda.Stream(dev)
+    other = pg.empty_grid(desc, b.n_mol, dev)
+    other.fill_(float("nan"))
+    s.wait_stream(torch.cuda.current_stream(dev))
+    ctx.forward(desc, bv, other, stream=s)
+    s.synchronize()
+    assert torch.equal(other, eager)
+    ctx.set_option(pg.PG_OPT_GRAPH, 1)
+    try:
+        out = pg.empty_grid(desc, b.n_mol, dev)
+        for rep in range(4):
+            out.fill_(float("nan"))
+            ctx.forward(desc, bv, out)
+            torch.cuda.synchronize()
+            junk = torch.randn(1 << 20, device=dev).sum()      # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), f"replay {rep}"
+            del junk
+    finally:
+        ctx.set_option(pg.PG_OPT_GRAPH, 0)
+    assert ctx.device_error()[0] == 0
+
+
 def test_auto_form_rule(pg, dev):
-    """AUTO on large structures: the MFMA form for bf16 and float32 grids
-    (the latter on split fp16 factors); small structures keep the one-launch
-    window form."""
+    """AUTO on large structures: the MFMA form for bf16 and float32 grids;
+    small structures keep the one-launch window form."""
     sig = synth.sigma_table(3, 0.3, 0.45)
     big = cell_batch(33, [400], 8.0, 3)
     p = plan_of(pg, dev, big, sig, (24, 24, 24), 1 / 3, (0, 0, 0), torch.bfloat16, "auto", 8.0)
