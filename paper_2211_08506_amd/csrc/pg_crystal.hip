@@ -956,19 +956,24 @@ __device__ __forceinline__ void store_tiles(const GridParams &p, const TileItem 
 // bf16 by one conversion) and, once per step, of phi_x go into the wave's
 // LDS buffer as [row][16 entries] (4 bytes per row and pair); the wave then
 // reads its fragments and each plane takes one v_mfma_f32_32x32x16_bf16.
-// The y slots are float, the x slots bf16.
+// The y slots are float, the x slots bf16.  Each lane publishes its entry's
+// phi_z and slot indices in the wave's LDS once per 64 entries; the slot
+// rows of the next step are loaded while the current step is staged and
+// contracted.
 constexpr int AST = 24;   // staged row: 16 entries + 8 bf16 of padding (48 B)
 
 template <int ZP, int KCH>
 __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, CrystalParams q)
 {
-    // entries per chunk (one list entry per lane, KCH <= 64), their slot rows
-    // loaded before the chunk's first step
+    static_assert(KCH == KS, "one step of entries per load group");
+    static_assert(ZP == 4, "phi_z of the wave's planes is published as one float4 per entry");
     // bf16 per wave: staging 2 x 32 x AST (phi_x, then one plane's A at a
     // time) >= one output tile 32 x tile_lrow
     constexpr int WBUF = 2 * 32 * AST;
     static_assert(WBUF >= 32 * tile_lrow<__bf16>(), "the output tile fits the staging buffer");
     __shared__ __attribute__((aligned(16))) __bf16 lds[4][WBUF];
+    __shared__ float4 gzs[4][64];   // per wave: phi_z of its 64 entries at its planes
+    __shared__ uint2 sls[4][64];    // per wave: their (y slot, x slot)
     const TileItem it = tile_item<ZP>(p, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t first, end;
@@ -991,58 +996,49 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
     typedef float f2 __attribute__((ext_vector_type(2)));
     typedef __bf16 b2 __attribute__((ext_vector_type(2)));
     typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-    // each lane evaluates one entry of 64 (phi_z at the wave's planes and its
-    // slots), consumed as 64 / KCH chunks of KCH entries
-    static_assert(64 % KCH == 0, "chunks divide a wave's 64 entries");
     for (uint32_t c64 = first; c64 < end; c64 += 64) {
-      const LaneImage<ZP> li =
-          lane_image<ZP>(p, q, tile_entry(q, c64 + lane, end), it.z0, it.c, inv2s2_c, isq2s_c);
-#pragma unroll 1
-      for (int ch = 0; ch < 64 / KCH; ++ch) {
-        const uint32_t c0 = c64 + (uint32_t)(ch * KCH);
-        if (c0 >= end)
-            break;
-        const int nst = (int)((min((uint32_t)KCH, end - c0) + KS - 1) / KS);
-        float4 ya[KCH / KS][2];
-        b4 xb[KCH / KS][2];
-        float gg[KCH / KS][2][ZP];
-#pragma unroll
-        for (int st = 0; st < KCH / KS; ++st)
+        const LaneImage<ZP> li =
+            lane_image<ZP>(p, q, tile_entry(q, c64 + lane, end), it.z0, it.c, inv2s2_c, isq2s_c);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the last chunk's reads are done
+        gzs[wave][lane] = make_float4(li.gz[0], li.gz[1], li.gz[2], li.gz[3]);
+        sls[wave][lane] = make_uint2(li.yslot, li.xslot);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const int nv = (int)min(64u, end - c64);   // entries of this chunk
+        const int nst = (nv + KS - 1) / KS;
+        // slot rows of the lane's pair in step st, loaded without branches
+        // (entries past the chunk's have slot indices 0, an allocated slot;
+        // they are zeroed where used)
+        auto load_step = [&](int st, float4 (&ya)[2], b4 (&xb)[2]) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int src = ch * KCH + KS * st + 2 * ip + u;
-#pragma unroll
-                for (int k = 0; k < ZP; ++k)
-                    gg[st][u][k] = __shfl(li.gz[k], src, 64);
-                const uint32_t ys = (uint32_t)__shfl((int)li.yslot, src, 64);
-                const uint32_t xs = (uint32_t)__shfl((int)li.xslot, src, 64);
-                ya[st][u] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    xb[st][u][r] = (__bf16)0.f;
-                if (st < nst && c64 + (uint32_t)src < end) {
-                    ya[st][u] = *(const float4 *)(ybase + (ys * 128u + 16u * g));
-                    xb[st][u] = *(const b4 *)(xbase + (xs * 64u + 8u * g));
-                }
+                const uint2 sl = sls[wave][min(KS * st + 2 * ip + u, 63)];
+                ya[u] = *(const float4 *)(ybase + (sl.x * 128u + 16u * g));
+                xb[u] = *(const b4 *)(xbase + (sl.y * 64u + 8u * g));
             }
-#pragma unroll
-        for (int st = 0; st < KCH / KS; ++st) {
-            if (st >= nst)
-                break;
+        };
+        auto mma_step = [&](int st, const float4 (&ya)[2], const b4 (&xb)[2]) {
+            const int e0 = KS * st + 2 * ip;
+            const bool v0 = e0 < nv, v1 = e0 + 1 < nv;
+            const b4 z4 = {(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+            const b4 x0 = v0 ? xb[0] : z4, x1 = v1 ? xb[1] : z4;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const b2 pb = {xb[st][0][r], xb[st][1][r]};
+                const b2 pb = {x0[r], x1[r]};
                 *(uint32_t *)(Bs + r * AST + wo) = __builtin_bit_cast(uint32_t, pb);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             const bf16x8 bf = *(const bf16x8 *)(Bs + fo);
-            const float y0[4] = {ya[st][0].x, ya[st][0].y, ya[st][0].z, ya[st][0].w};
-            const float y1[4] = {ya[st][1].x, ya[st][1].y, ya[st][1].z, ya[st][1].w};
+            const float4 ya0 = v0 ? ya[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 ya1 = v1 ? ya[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float y0[4] = {ya0.x, ya0.y, ya0.z, ya0.w};
+            const float y1[4] = {ya1.x, ya1.y, ya1.z, ya1.w};
+            const float4 g0 = gzs[wave][e0], g1 = gzs[wave][e0 + 1];   // e0 + 1 < 64
+            const float gz0[4] = {g0.x, g0.y, g0.z, g0.w}, gz1[4] = {g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
             for (int k = 0; k < ZP; ++k) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const f2 pr = {y0[r] * gg[st][0][k], y1[r] * gg[st][1][k]};
+                    const f2 pr = {y0[r] * gz0[k], y1[r] * gz1[k]};
                     *(uint32_t *)(As + r * AST + wo) = __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, b2));
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1050,8 +1046,20 @@ __global__ void __launch_bounds__(256) cr_tile_bf16_kernel(GridParams p, Crystal
                 acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, acc[k], 0, 0, 0);
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
+        };
+        // the next step's loads are issued unconditionally (in bounds past the
+        // chunk too), so the wait before each step covers only its own loads
+        float4 ya0[2], ya1[2];
+        b4 xb0[2], xb1[2];
+        load_step(0, ya0, xb0);
+        for (int st = 0; st < nst; st += 2) {
+            load_step(st + 1, ya1, xb1);
+            mma_step(st, ya0, xb0);
+            if (st + 1 >= nst)
+                break;
+            load_step(st + 2, ya0, xb0);
+            mma_step(st + 1, ya1, xb1);
         }
-      }
     }
     store_tiles<__bf16, ZP>(p, it, acc, lds[wave]);
 }
@@ -1124,16 +1132,16 @@ __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalP
                 acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a * g.w, b, acc[3], 0, 0, 0);
             }
         };
+        // the next group's loads are issued unconditionally (in bounds past
+        // the chunk too), so the waits of a group cover only its own loads
         float a0[PB], b0[PB], a1[PB], b1[PB];
         load_group(0, a0, b0);
         for (int p0 = 0; p0 < npair; p0 += 2 * PB) {
-            if (p0 + PB < npair)
-                load_group(p0 + PB, a1, b1);
+            load_group(p0 + PB, a1, b1);
             mma_group(p0, a0, b0);
             if (p0 + PB >= npair)
                 break;
-            if (p0 + 2 * PB < npair)
-                load_group(p0 + 2 * PB, a0, b0);
+            load_group(p0 + 2 * PB, a0, b0);
             mma_group(p0 + PB, a1, b1);
         }
     }
@@ -1141,7 +1149,7 @@ __global__ void __launch_bounds__(256) cr_tile_f32_kernel(GridParams p, CrystalP
 }
 
 constexpr int ZP_BF16 = 4;    // planes per wave of the bf16 tile kernel
-constexpr int KCH_BF16 = 32;  // entries per chunk of the bf16 tile kernel
+constexpr int KCH_BF16 = 16;  // entries per load group of the bf16 tile kernel (one step)
 constexpr int ZP_F32 = 4;     // planes per wave of the fp32 tile kernel
 constexpr int KCH_F32 = 64;   // entries per chunk of the fp32 tile kernel
 
