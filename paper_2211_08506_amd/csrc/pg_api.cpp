@@ -369,23 +369,30 @@ struct Plan {
     size_t ws_tmask = 0, ws_xval = 0, ws_yval = 0, ws_tcl = 0, ws_zstart = 0;
     long long op_blocks = 0;
     int nblk = 0;
-    int sx_max = 0, sy_max = 0, ntx = 0, nty = 0, zwin = 0;
+    int sx_max = 0, sy_max = 0, ntx = 0, nty = 0;
+    int zwin[PG_MAX_CHANNELS] = {};   // per channel: bound on its images' z window lengths
 };
 
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Most voxels of one axis an atom's window can span: floor(2 rc / h) + 1
+// Most voxels of one axis a window of radius rc can span: floor(2 rc / h) + 1
 // centres lie within rc of a point (+2 for rounding), never more than the
 // axis holds; the whole axis without a cutoff.
-int window_voxels(const pg_grid_desc *d, const pg_batch *b, int axis, int N)
+int window_voxels_rc(const pg_grid_desc *d, double rc, int axis, int N)
 {
     if (d->cutoff_k == 0.f)
         return N;
+    return (int)std::min<double>(N, std::floor(2.0 * rc / (double)d->spacing[axis]) + 3.0);
+}
+
+// The same for the widest window of any type.
+int window_voxels(const pg_grid_desc *d, const pg_batch *b, int axis, int N)
+{
     double rc = 0.0;
     for (int t = 0; t < n_sig_of(d, b); ++t)
         rc = std::max(rc, (double)rc_of(d, t));
-    return (int)std::min<double>(N, std::floor(2.0 * rc / (double)d->spacing[axis]) + 3.0);
+    return window_voxels_rc(d, rc, axis, N);
 }
 
 // Binned path: workspace layout (window records | per-block channel counts
@@ -447,7 +454,11 @@ int crystal_plan(const pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, in
         const bool per = d->periodic == PG_CELL_ORTHO;
         P.sx_max = crystal_axis_slots(d->W, window_voxels(d, b, 0, d->W), per);
         P.sy_max = crystal_axis_slots(d->H, window_voxels(d, b, 1, d->H), per);
-        P.zwin = window_voxels(d, b, 2, d->D);
+        // z window bound per channel: a run of an unweighted channel holds
+        // atoms of that type only; weighted channels take any type
+        const int zmax = window_voxels(d, b, 2, d->D);
+        for (int c = 0; c < d->C; ++c)
+            P.zwin[c] = weighted(b) ? zmax : window_voxels_rc(d, rc_of(d, c), 2, d->D);
         // tile-column entries: run r's lists start at entry 32 run_block(r) SS
         const long long ss = (long long)P.sx_max * P.sy_max;
         const long long n_tcl = 32 * P.op_blocks * ss;
@@ -721,7 +732,8 @@ hipError_t launch_forward(pg_ctx *ctx, const pg_grid_desc *d, const Plan &P, Gri
         q.tcl = (TileEntry *)(ws + P.ws_tcl);
         q.zstart = (uint32_t *)(ws + P.ws_zstart);
         q.nblk = P.nblk;
-        q.zwin = P.zwin;
+        for (int c = 0; c < PG_MAX_CHANNELS; ++c)
+            q.zwin[c] = P.zwin[c];
         q.sx_max = P.sx_max;
         q.sy_max = P.sy_max;
         q.ntx = P.ntx;

@@ -753,7 +753,8 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
 // of a bf16 plane; neighbouring planes share their images, so one wave
 // contracts the images of its ZP planes together).  The wave's entries are
 // those of its tile column's list whose z start lies in
-// [z0 - zwin + 1, z0 + ZP - 1] (zwin bounds every z window; an entry whose
+// [z0 - zwin + 1, z0 + ZP - 1] (zwin bounds the z windows of the channel's
+// images: one type's windows for an unweighted channel; an entry whose
 // window misses a plane gets phi_z = 0 there), taken 64 at a time, one per
 // lane; their factor-slot rows are loaded before the first MFMA step.
 // Every entry is taken in list order, so each voxel's sum has a fixed order.
@@ -771,17 +772,22 @@ template <int ZP>
 __device__ __forceinline__ TileItem tile_item(const GridParams &p, const CrystalParams &q)
 {
     const unsigned ntp = (unsigned)(q.ntx + 1) / 2, nzq = (unsigned)(p.D + 2 * ZP - 1) / (2 * ZP);
+    // the run is the fastest index: every stretch of items mixes the runs
+    // (structures of very different density), so no XCD ends on a run of
+    // heavy tiles
     unsigned b = xcd_block();
     TileItem it;
+    const unsigned nmc = (unsigned)p.n_mol * (unsigned)p.C;
+    const unsigned mc = b % nmc;
+    b /= nmc;
     const int zq = (int)(b % nzq);
     b /= nzq;
     const int tp = (int)(b % ntp);
     b /= ntp;
-    it.ty = (int)(b % (unsigned)q.nty);
-    b /= (unsigned)q.nty;
-    it.mc = (size_t)b;
-    it.c = (int)(b / (unsigned)p.n_mol);
-    it.m = (int)(b % (unsigned)p.n_mol);
+    it.ty = (int)b;
+    it.mc = (size_t)mc;
+    it.c = (int)(mc / (unsigned)p.n_mol);
+    it.m = (int)(mc % (unsigned)p.n_mol);
     const int w = (int)(threadIdx.x >> 6);
     it.tx = 2 * tp + (w & 1);
     it.z0 = ZP * (2 * zq + (w >> 1));
@@ -798,7 +804,7 @@ __device__ __forceinline__ void tile_range(const GridParams &p, const CrystalPar
         return;
     const uint32_t *zs =
         q.zstart + (it.mc * (size_t)(q.ntx * q.nty) + it.ty * q.ntx + it.tx) * (size_t)(p.D + 1);
-    first = zs[max(0, it.z0 - q.zwin + 1)];
+    first = zs[max(0, it.z0 - q.zwin[it.c] + 1)];
     end = zs[min(it.z0 + ZP, p.D)];
 }
 
@@ -1172,13 +1178,13 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
     float *gx = (float *)smem;                    // [KC][W32] phi_x
     float *gy = gx + KC * W32;                    // [KC][H32] phi_z(z) phi_y
     uint32_t *tmask = (uint32_t *)(gy + KC * H32);   // [ntiles] images meeting each tile
-    unsigned b = xcd_block();
-    const int z = (int)(b % (unsigned)D);
-    b /= (unsigned)D;
-    const int c = (int)(b % (unsigned)C);
-    const int m = (int)(b / (unsigned)C);
+    // the run is the fastest index (every stretch of planes mixes structures
+    // of very different density), then z
+    const unsigned b = xcd_block(), nmc = (unsigned)p.n_mol * (unsigned)C;
+    const int z = (int)(b / nmc);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const size_t mc = (size_t)c * p.n_mol + m;
+    const size_t mc = b % nmc;
+    const int c = (int)(mc / (unsigned)p.n_mol), m = (int)(mc % (unsigned)p.n_mol);
     const uint32_t first = q.prange[((size_t)mc * D + z) * 2];
     const uint32_t end = q.prange[((size_t)mc * D + z) * 2 + 1];
     const long long eb = 32ll * run_block(q, mc);

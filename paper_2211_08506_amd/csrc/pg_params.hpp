@@ -177,6 +177,7 @@ struct CrystalParams {
     int32_t nblk;            // prep blocks (PREP_BLOCK atoms each)
     int32_t sx_max, sy_max;  // factor slots per atom on x and y (<= 16 each)
     int32_t ntx, nty;        // 32-voxel tiles along x and y
-    int32_t zwin;            // bound on any z window's length (voxels)
+    int32_t zwin[PG_MAX_CHANNELS];   // per channel: bound on the length (voxels) of the z
+                                     // windows of its runs' images
 };
 }  // namespace pg
