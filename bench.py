@@ -53,7 +53,6 @@ METRICS = {
                     "32³×5ch FP32, batch 1024)",
 }
 PEAK_HBM_GBS = 8000.0
-PEAK_BF16_TFLOPS = 2500.0
 WINDOW_SOURCES = ("paper_2211_08506_amd/csrc/pg_window.hip", "paper_2211_08506_amd/csrc/pg_device.hpp",
                   "paper_2211_08506_amd/csrc/pg_params.hpp")
 CPU_THREADS_MAX = 16
@@ -136,28 +135,6 @@ def window_evals(b, wl) -> int:
     for rq in axis_windows(b, wl):
         cnt.append(sum(np.maximum(hi - lo + 1, 0) for lo, hi in rq))
     return int(np.sum(cnt[0] * cnt[1] * cnt[2]))
-
-
-def mfma_dense_flops(b, wl, dense_channels=None):
-    """Flops of the binned plane contraction, as (issued, algorithmic): per
-    (structure, channel, z) bin, the kernel issues 2 x (rows x cols padded
-    to 128-voxel super-tiles) x (bin size padded to the 32-atom step); the
-    algorithmic count is 2 x H x W x (bin size).  dense_channels: a dense
-    embedding lists every atom under each of that many channels."""
-    D, H, W = wl.dims
-    mol = np.searchsorted(b.offsets, np.arange(b.n_atoms), side="right") - 1
-    bins = np.zeros((b.n_mol, wl.n_types, D), np.int64)
-    for lo, hi in axis_windows(b, wl)[2]:
-        n = np.maximum(hi - lo + 1, 0)
-        a = np.repeat(np.arange(b.n_atoms), n)
-        z = np.concatenate([np.arange(l, h + 1) for l, h in zip(lo, hi) if h >= l]) \
-            if n.sum() else np.zeros(0, np.int64)
-        np.add.at(bins, (mol[a], b.types[a], z), 1)
-    if dense_channels:
-        bins = np.repeat(bins.sum(axis=1, keepdims=True), dense_channels, axis=1)
-    k_pad = ((bins + 31) // 32) * 32
-    tiles = ((H + 127) // 128) * ((W + 127) // 128)
-    return int(2 * 128 * 128 * tiles * k_pad.sum()), int(2 * H * W * bins.sum())
 
 
 def parity_stats(got, ref, what):
@@ -478,14 +455,9 @@ def main():
             f"{fill_gbs:.0f} GB/s")
         del out
         if wl.kind == "crystal":
-            kname = ("binned path, whole step: cr_clear, cr_prep, cr_scan, cr_place, cr_zsort, "
-                     + ("cr_operand, " if plan["form"] == "mfma" else "")
-                     + f"cr_{plan['form']}_kernel")
-            flops, alg_flops = mfma_dense_flops(b, wl, C if E is not None else None)
-            extra["mfma_dense_tflops"] = (flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
-                                          if plan["form"] == "mfma" else None)
-            extra["mfma_dense_flops_per_step"] = flops
-            extra["mfma_algorithmic_flops_per_step"] = alg_flops
+            kname = ("binned path, whole step: cr_clear, cr_prep, cr_scan, cr_place, "
+                     + (f"cr_slot, cr_tsort, cr_tile_{'bf16' if esize == 2 else 'f32'}_kernel"
+                        if plan["form"] == "mfma" else "cr_zsort, cr_window_kernel"))
             # the other form / dtype pairs, for the per-shape decision
             for form, dt in (("mfma", torch.bfloat16), ("window", torch.float32),
                              ("window", torch.bfloat16), ("mfma", torch.float32)):
@@ -535,17 +507,6 @@ def main():
             "fill_gbs_same_bytes": fill_gbs,
             "frac_of_fill": achieved / fill_gbs,
         })
-        if wl.kind == "crystal" and plan["form"] == "mfma":
-            # a dense embedding makes the plane contraction the binding
-            # resource: report the bf16 MFMA roofline when it is the larger
-            # fraction (algorithmic flops over the whole step)
-            tflops = alg_flops / (main_res["launch_ms"]["mean"] / 1e3) / 1e12
-            if tflops / PEAK_BF16_TFLOPS > achieved / PEAK_HBM_GBS:
-                rec["roofline"].update({
-                    "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
-                    "algorithmic_flops_per_launch": alg_flops,
-                    "hbm_frac": achieved / PEAK_HBM_GBS})
         kind = "forward"
 
     if wl.kind == "crystal":
