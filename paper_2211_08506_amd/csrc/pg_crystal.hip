@@ -136,12 +136,13 @@ __device__ __forceinline__ AxisWin axis_win(const AtomWindow &w, int ax)
 // the 32 values phi(32 tile + j), zero outside the windows and past the grid
 // edge.  Eight lanes per (atom, axis), four consecutive values each per slot
 // (the box form walks their five edges once), so one wave fills eight
-// atom-axes; the atoms' records are read once.
+// atom-axes; the atoms' records are read once.  wv: the global index of
+// the calling wave among the pass's waves.
 template <typename YT, typename XT>
-__global__ void __launch_bounds__(256) cr_slot_kernel(GridParams p, CrystalParams q)
+__device__ __forceinline__ void slot_wave(const GridParams &p, const CrystalParams &q, long long wv)
 {
     const int lane = threadIdx.x & 63, grp = lane >> 3, j8 = lane & 7;
-    const long long id = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8 + grp;
+    const long long id = wv * 8 + grp;
     const long long a = id >> 1;
     const int ax = (int)(id & 1);
     if (a >= live_atoms(p))
@@ -583,16 +584,16 @@ struct MaskWalk {
 // entries with the same split over its waves but counts and places only the
 // items of its band's tile columns, after the items of the rows above it
 // (counted from the tile masks), so the lists are the same for any G.
-// Dynamic LDS: waves x (band rows x ntx) x D words.
-__global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalParams q, int G)
+// Dynamic LDS: waves x (band rows x ntx) x D words.  blk: the sort's
+// workgroup index (run x G + band).
+__device__ void tsort_block(const GridParams &p, const CrystalParams &q, int G, unsigned blk, uint32_t *tls)
 {
-    extern __shared__ uint32_t tls[];
     __shared__ uint32_t tsum[1024];
     __shared__ uint32_t nabove;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nw = blockDim.x >> 6, nt = blockDim.x;
-    const size_t mc = blockIdx.x / (unsigned)G;
-    const int g = (int)(blockIdx.x % (unsigned)G);
+    const size_t mc = blk / (unsigned)G;
+    const int g = (int)(blk % (unsigned)G);
     // the band's tile rows [ty0, ty1) and its keys ((ty - ty0) ntx + tx) D + z
     const int ty0 = g * q.nty / G, ty1 = (g + 1) * q.nty / G;
     const uint32_t rows_above = (uint32_t)((1ull << ty0) - 1ull);
@@ -612,7 +613,7 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
     const int ntx = q.ntx;
     // the wave's first CHC chunks of 64 entries (and their atoms' tile masks)
     // stay in registers for both passes; later chunks are read again
-    constexpr int CHC = 4;
+    constexpr int CHC = 1;
     const int nch = (int)((pe - pb + 63) / 64);
     ListEntry lec[CHC];
     uint32_t mxc[CHC], myc[CHC];
@@ -742,6 +743,26 @@ __global__ void __launch_bounds__(1024) cr_tsort_kernel(GridParams p, CrystalPar
             }
         }
     }
+}
+
+// The tile sort and the factor-slot pass in one launch: the first n_sort
+// workgroups sort (one per run and band; latency-bound, one per CU), the
+// rest fill factor slots (8 atom-axes per wave) on the capacity the sort
+// leaves free.  The two read only what the prep and partition passes wrote
+// and write disjoint arrays.
+// (At most 64 VGPRs: two 1024-thread workgroups share a CU, so slot
+// workgroups run beside the sort's.)
+template <typename YT, typename XT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+cr_sort_slot_kernel(GridParams p, CrystalParams q, int G,
+                                                            unsigned n_sort)
+{
+    extern __shared__ uint32_t tls[];
+    if (blockIdx.x < n_sort) {
+        tsort_block(p, q, G, blockIdx.x, tls);
+        return;
+    }
+    slot_wave<YT, XT>(p, q, (long long)(blockIdx.x - n_sort) * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------------------
@@ -1419,34 +1440,32 @@ hipError_t launch_crystal(const GridParams &p, const CrystalParams &q, int form,
     const void *k;
     long long grid;
     if (form == PG_FORM_MFMA) {
-        // factor slots of every atom, then the tile-column lists of every run
-        const long long slot_blocks = (2 * p.n_atoms + 31) / 32;
-        if (slot_blocks > 0) {
-            // y slots are float in both forms (phi_z phi_y is formed in FP32);
-            // x slots bf16 for bf16 grids, float for fp32 grids
-            if (out_dtype == PG_OUT_F32)
-                hipLaunchKernelGGL((cr_slot_kernel<float, float>), dim3((unsigned)slot_blocks), dim3(256), 0,
-                                   s, p, q);
-            else
-                hipLaunchKernelGGL((cr_slot_kernel<float, uint16_t>), dim3((unsigned)slot_blocks), dim3(256),
-                                   0, s, p, q);
-            if ((e = hipGetLastError()) != hipSuccess)
-                return e;
-        }
-        // tile-row bands per run: enough workgroups to spread the sort over
-        // the chip when runs are few
+        // the tile-column lists of every run (tile-row bands per run: enough
+        // workgroups to spread the sort over the chip when runs are few) and,
+        // in the same launch, the factor slots of every atom (8 atom-axes per
+        // wave).  y slots are float in both forms (phi_z phi_y is formed in
+        // FP32); x slots bf16 for bf16 grids, float for fp32 grids.
         const int G = (int)std::max<long long>(1, std::min<long long>(q.nty, (256 + nmc - 1) / nmc));
         const int K = ((q.nty + G - 1) / G) * q.ntx * p.D;   // keys of the widest band
         const size_t tl = crystal_tsort_lds(K);
+        const int tw = crystal_tsort_waves(K);
+        const long long slot_waves = (2 * p.n_atoms + 7) / 8;
+        const long long blocks = nmc * G + (slot_waves + tw - 1) / tw;
+        if (blocks > 0x7fffffffLL)
+            return hipErrorInvalidValue;
+        const void *ks = out_dtype == PG_OUT_F32 ? (const void *)cr_sort_slot_kernel<float, float>
+                                                 : (const void *)cr_sort_slot_kernel<float, uint16_t>;
         if (tl > 65536) {
-            e = hipFuncSetAttribute((const void *)cr_tsort_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl);
+            e = hipFuncSetAttribute(ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl);
             if (e != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL(cr_tsort_kernel, dim3((unsigned)(nmc * G)), dim3(64 * crystal_tsort_waves(K)), tl,
-                           s, p, q, G);
-        if ((e = hipGetLastError()) != hipSuccess)
+        GridParams ps = p;
+        CrystalParams qs = q;
+        int Gs = G;
+        unsigned n_sort = (unsigned)(nmc * G);
+        void *sargs[] = {&ps, &qs, &Gs, &n_sort};
+        if ((e = hipLaunchKernel(ks, dim3((unsigned)blocks), dim3(64 * tw), sargs, tl, s)) != hipSuccess)
             return e;
         const int zp = out_dtype == PG_OUT_F32 ? ZP_F32 : ZP_BF16;
         k = out_dtype == PG_OUT_F32 ? (const void *)cr_tile_f32_kernel<ZP_F32, KCH_F32>
