@@ -152,6 +152,14 @@ __device__ __forceinline__ void image_range(float o, float h, int N, float mu, i
     const float lim_lo = -4.f, lim_hi = (float)N + 4.f;
     float flo = fminf(fmaxf(ceilf(f - r), lim_lo), lim_hi);
     float fhi = fminf(fmaxf(floorf(f + r), lim_lo), lim_hi);
+    // an image whose estimated window lies two or more indices outside the
+    // grid is empty (the estimate of an image that can reach the grid is
+    // within one index): no exact test needed -- most periodic images
+    if (fhi <= -2.f || flo >= (float)N + 1.f) {
+        lo_out = 0;
+        hi_out = -1;
+        return;
+    }
     int lo = (int)flo, hi = (int)fhi;
     const int ilo = -4, ihi = N + 4;
     for (int it = 0; it < 8 && lo > ilo && side(o, h, lo - 1, mu, n, L, rc) >= 0; ++it)
