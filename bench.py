@@ -6,9 +6,10 @@
 A step is one pass of the forward hot path over one batch: inputs are
 staged in HBM once, then each step runs the per-atom window bounds and 1-D
 factors, the accumulation and the dense write of the whole B x C x D x H x W
-grid (for molecules one persistent window-kernel launch replayed from a
-captured HIP graph; for large periodic cells the binned path's four set-up
-kernels and one plane kernel, also replayed from a graph).  Rank 0 prints
+grid (for molecules one persistent window-kernel launch, launched directly:
+the library replays graphs only for sequences of several kernels; for large
+periodic cells the binned path's set-up kernels and its plane kernel,
+replayed from a captured HIP graph).  Rank 0 prints
 one JSON line on stdout; progress goes to stderr.
 
 Workloads (synth.WORKLOADS):
@@ -508,6 +509,9 @@ def main():
             "frac_of_fill": achieved / fill_gbs,
         })
         kind = "forward"
+        if not args.no_graph and plan["form"] == "window" and not plan["binned"]:
+            # the library launches its one-kernel molecule form directly
+            launch = "direct launch (one kernel; the graph option replays only multi-kernel steps)"
 
     if wl.kind == "crystal":
         shape = "triclinic (sheared) cells of edge" if args.triclinic else "cubic cells of"

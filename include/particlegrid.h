@@ -291,7 +291,9 @@ int pg_tuning_save(const pg_ctx *ctx, const char *path);
 int pg_tuning_load(pg_ctx *ctx, const char *path);
 
 /* Options: PG_OPT_GRAPH (0/1, default 0) -- replay captured HIP graphs for
-   repeated identical forward calls.  PG_OPT_BLOCK, PG_OPT_GRID_PER_CU,
+   repeated identical forward calls whose launch sequence has several
+   kernels (a forward on the one-kernel molecule window form is launched
+   directly, which costs less than a replay).  PG_OPT_BLOCK, PG_OPT_GRID_PER_CU,
    PG_OPT_UNROLL, PG_OPT_NT_STORE -- override the window form's workgroup
    size (64..1024, a multiple of 64), persistent workgroups per CU (1..64),
    16-byte output runs per lane per pass (1, 2 or 4) and non-temporal

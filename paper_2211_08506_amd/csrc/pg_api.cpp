@@ -808,7 +808,11 @@ int forward_impl(pg_ctx *ctx, const pg_grid_desc *d, const pg_batch *b, void *ou
         return PG_E_WORKSPACE;
     GridParams p;
     fill_params(p, ctx, d, b, P, out, ws);
-    const bool graph = allow_graph && ctx->use_graph && b->n_mol > 0;
+    // the molecule window form is one kernel: replaying a graph of it costs
+    // more than launching it (measured 8 us per call), so it is launched
+    // directly under the graph option too
+    const bool single = !P.crystal && P.form == PG_FORM_WINDOW;
+    const bool graph = allow_graph && ctx->use_graph && b->n_mol > 0 && !single;
     return run_launches(ctx, graph, graph ? graph_key(d, b, P, out, ws, ws_bytes) : std::string(),
                         s, [&](hipStream_t st) {
                             GridParams q = p;
