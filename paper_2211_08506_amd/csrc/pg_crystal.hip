@@ -1282,12 +1282,15 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
             if (t >= ntiles)
                 break;
             const int y = 32 * (t / ntx) + ly, x = 32 * (t % ntx) + lx;
-            uint32_t mk = tmask[t];
+            // the tile's mask is the same for the whole wave: its walk and the
+            // rows' offsets run on the scalar unit
+            uint32_t mk = (uint32_t)__builtin_amdgcn_readfirstlane((int)tmask[t]);
+            const float *gyl = gy + y, *gxl = gx + x;
             while (mk) {
                 const int k = __builtin_ctz(mk);
                 mk &= mk - 1u;
-                const float4 g4 = *(const float4 *)(gy + k * H32 + y);
-                const float4 f4 = *(const float4 *)(gx + k * W32 + x);
+                const float4 g4 = *(const float4 *)(gyl + k * H32);
+                const float4 f4 = *(const float4 *)(gxl + k * W32);
                 const float gr[4] = {g4.x, g4.y, g4.z, g4.w}, fr[4] = {f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
