@@ -86,13 +86,30 @@ def test_periodic_cells(pg, dev, dims, h):
         check(f"periodic{dims}/{form}/{dt}", g, ref, tol)
 
 
+def test_periodic_small_grid_in_large_cell(pg, dev):
+    """A 28 x 24 x 20 grid at 0.41 A inside 24 A periodic cells, its origin
+    offset so that it crosses the cell faces on y and z: most of an atom's
+    candidate lattice images lie far outside the grid and are dropped by the
+    window search's float estimate before its exact tests.  Every form
+    matches the oracle, support voxel for voxel."""
+    sig = synth.sigma_table(3, 0.3, 0.45)
+    b = cell_batch(37, [500, 350], 24.0, 3)
+    dims, h, origin = (20, 24, 28), 0.41, (7.0, -3.0, 20.5)
+    ref = oracle.grid_fp64(b.xyz, b.types, b.offsets, sig, dims, h, origin, cell=24.0)
+    assert ref[:, :, :, :3].sum() > 0 and ref[:, :, -3:].sum() > 0   # images across the faces
+    for form, dt, tol in CASES:
+        say(f"case small grid in large cell form={form} dtype={dt}")
+        g = run(pg, dev, b, sig, dims, h, origin, dt, form, cell=24.0)
+        check(f"subgrid/{form}/{dt}", g, ref, tol)
+
+
 @pytest.mark.parametrize("dims", [(20, 37, 45), (6, 150, 140), (9, 16, 200), (4, 300, 320)])
 def test_ragged_planes_large_cluster(pg, dev, dims):
     """Non-periodic clusters of 300-700 atoms on planes that are not whole
-    tiles: 16-voxel runs and 128 x 128 MFMA super-tiles with ragged tails,
-    several super-tiles per plane, an empty structure in the batch.  At
-    300 x 320 the float operand blocks exceed the LDS staging budget, so the
-    operand kernel writes them in place."""
+    32 x 32 tiles: ragged tile rows and columns (partial tiles stored with
+    bounds tests, partial factor slots), many tiles per plane, an empty
+    structure in the batch; planes wider than 32 tiles are refused by the
+    vector form and served by the MFMA form."""
     sig = synth.sigma_table(4, 0.35, 0.6)
     b = cell_batch(32, [300, 0, 700], 6.0, 4, lo=-3.0)
     h = 0.17

@@ -349,15 +349,18 @@ def test_integer_translation_shifts_grid_bitwise(pg, dev):
     assert torch.equal(a, c)
 
 
-def test_graph_replay_matches_eager(pg, dev):
-    """Captured-graph replays, with eager work and synchronisation between
-    them, each reproduce the eager result bit for bit."""
-    say("case graph replay")
+@pytest.mark.parametrize("form", ["window", "plain"])
+def test_graph_replay_matches_eager(pg, dev, form):
+    """With the graph option on, repeated calls -- the one-kernel window form
+    launched directly, the multi-kernel plain form replayed from its captured
+    graph -- with eager work and synchronisation between them each reproduce
+    the eager result bit for bit."""
+    say(f"case graph replay form={form}")
     wl = synth.WORKLOADS["mol256"]
     b = wl.batch(128)
     xyz, types, offs = to_device(b, dev)
     ctx = pg.Context(0)
-    desc = pg.make_desc(5, wl.dims, wl.spacing, wl.origin, wl.sigma(), 3.0, None, torch.bfloat16)
+    desc = pg.make_desc(5, wl.dims, wl.spacing, wl.origin, wl.sigma(), 3.0, None, torch.bfloat16, form)
     bv = pg.BatchView(xyz, types, offs)
     eager = pg.empty_grid(desc, b.n_mol, dev)
     ctx.forward(desc, bv, eager)
