@@ -193,7 +193,8 @@ struct Tri {
     TriParams q;
     pg_grid_desc din;
     pg_batch bin;
-    size_t off_types = 0, off_offs = 0, off_grad = 0, off_istart = 0, off_base = 0, inner_off = 0;
+    size_t off_types = 0, off_offs = 0, off_grad = 0, off_istart = 0, off_base = 0, off_bsum = 0,
+           inner_off = 0;
     int32_t K_keep = 1;      // most images one atom can keep
 };
 
@@ -326,7 +327,8 @@ int tri_setup(const pg_grid_desc *d, const pg_batch *b, Tri &T)
     T.off_grad = T.off_offs + align256(((size_t)b->n_mol + 1) * 4);
     T.off_istart = T.off_grad + align256(nk * 12);
     T.off_base = T.off_istart + align256(((size_t)b->n_atoms + 1) * 4);
-    T.inner_off = T.off_base + align256((size_t)b->n_atoms * 12);
+    T.off_bsum = T.off_base + align256((size_t)b->n_atoms * 12);
+    T.inner_off = T.off_bsum + align256(((size_t)b->n_atoms / 256 + 2) * 4);
     return PG_OK;
 }
 
@@ -350,6 +352,7 @@ void tri_bind(Tri &T, const pg_batch *b, void *ws)
     T.q.cand = (float *)(w + T.off_grad);
     T.q.base = (float *)(w + T.off_base);
     T.q.istart = (int32_t *)(w + T.off_istart);
+    T.q.bsum = (uint32_t *)(w + T.off_bsum);
     T.q.origins = b->origins;
     T.bin.xyz = T.q.exp_xyz;
     T.bin.types = T.q.exp_types;

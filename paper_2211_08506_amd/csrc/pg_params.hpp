@@ -99,7 +99,9 @@ struct TriParams {
                              // grid); the same memory as grad_img, used before it
     float *base;             // n_atoms x 3: lattice index of each atom's candidate image 0
     float *grad;             // n_atoms x 3 (may be nullptr)
-    int32_t *istart;         // n_atoms + 1: images per atom, then their exclusive scan
+    int32_t *istart;         // n_atoms + 1: each atom's first image (in its 256-atom block,
+                             // then global), istart[n_atoms] = the image count
+    uint32_t *bsum;          // per 256-atom block: its images, then their exclusive scan
     const float *origins;    // per-structure grid origins, or nullptr
     float M[9];              // cell, row-major: M[3 * alpha + j] = alpha component of vector j
     float Minv_hi[9], Minv_lo[9];   // its inverse as float-float pairs (hi + lo)

@@ -15,10 +15,14 @@
 //   tri_base    one thread per atom: the lattice index of its first candidate;
 //   tri_pos     one thread per (atom, candidate image): the position, or NaN
 //               for an image that misses the grid, in a candidate buffer;
-//   tri_count   one thread per atom counts its kept images;
-//   tri_scan    one workgroup: exclusive scan of the counts (image start of
-//               each atom) and the image batch's CSR bounds;
-//   tri_write   one thread per atom copies its kept images.
+//   tri_count   one thread per atom counts its kept images; each 256-atom
+//               block scans its counts (the atoms' starts within the block)
+//               and writes its total;
+//   tri_scan    one workgroup: exclusive scan of the block totals and the
+//               image batch's CSR bounds;
+//   tri_write   one thread per atom: its global start (block start + start
+//               within the block, kept for the gradient pass) and its kept
+//               images.
 // Images a test keeps but that miss the grid just have empty windows.  The
 // coordinate gradient of an atom is the sum of its images' gradients (each
 // image is a translate of the atom), summed in image order.
@@ -215,27 +219,46 @@ __global__ void __launch_bounds__(256) tri_pos_kernel(TriParams q, DeviceError *
     c[2] = keep ? pos[2] : 0.f;
 }
 
-// One thread per atom: its kept images, counted from the candidates.
+// One thread per atom: its kept images, counted from the candidates, and
+// their exclusive scan within the 256-atom block (wave scans by shuffles,
+// then the waves' totals); the block's total goes to bsum.
 __global__ void __launch_bounds__(256) tri_count_kernel(TriParams q)
 {
-    const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= q.n_atoms)
-        return;
-    int n = 0;
-    for (int k = 0; k < q.K; ++k)
-        n += __builtin_isnan(q.cand[3 * ((size_t)k * q.n_atoms + a)]) ? 0 : 1;
-    q.istart[a] = n;
+    __shared__ uint32_t wsum[4];
+    const long long a = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t n = 0;
+    if (a < q.n_atoms)
+        for (int k = 0; k < q.K; ++k)
+            n += __builtin_isnan(q.cand[3 * ((size_t)k * q.n_atoms + a)]) ? 0u : 1u;
+    uint32_t inc = n;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)inc, d, 64);
+        if (lane >= d)
+            inc += v;
+    }
+    if (lane == 63)
+        wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0u;
+    for (int i = 0; i < w; ++i)
+        before += wsum[i];
+    if (a < q.n_atoms)
+        q.istart[a] = (int32_t)(before + inc - n);
+    if (threadIdx.x == 255)
+        q.bsum[blockIdx.x] = before + inc;
 }
 
-// one workgroup: istart[0..n) counts -> exclusive scan, istart[n] = total;
-// exp_offsets[m] = istart[offsets[m]]
+// one workgroup: the block totals -> their exclusive scan (each block's
+// first image), istart[n] = total; exp_offsets[m] = the global start of
+// atom offsets[m] (its start within its block + the block's start)
 __global__ void __launch_bounds__(1024) tri_scan_kernel(TriParams q, DeviceError *err)
 {
     __shared__ unsigned long long part[1024];
     const int t = threadIdx.x;
-    const long long n = q.n_atoms;
-    const unsigned long long total =
-        workgroup_exclusive_scan((const uint32_t *)q.istart, (uint32_t *)q.istart, n, part);
+    const long long n = q.n_atoms, nb = (n + 255) / 256;
+    const unsigned long long total = workgroup_exclusive_scan(q.bsum, q.bsum, nb, part);
     if (t == 1023) {
         q.istart[n] = (int32_t)total;
         // more kept images than the host bound (not expected: the bound is
@@ -247,20 +270,20 @@ __global__ void __launch_bounds__(1024) tri_scan_kernel(TriParams q, DeviceError
     for (long long m = t; m <= (long long)q.n_mol; m += 1024) {
         long long om = q.offsets[m];       // device data: clamp into [0, n]
         om = om < 0 ? 0 : (om > n ? n : om);
-        q.exp_offsets[m] = q.istart[om];
+        q.exp_offsets[m] = om == n ? q.istart[n] : (int32_t)(q.istart[om] + q.bsum[om >> 8]);
     }
 }
 
-// One thread per atom: its kept images, in k order, from istart[a] on.
+// One thread per atom: its kept images, in k order, from its global start on.
 __global__ void __launch_bounds__(256) tri_write_kernel(TriParams q)
 {
     const long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= q.n_atoms)
         return;
-    long long j = q.istart[a];
-    const long long j_end = q.istart[a + 1];
+    long long j = (long long)q.istart[a] + q.bsum[a >> 8];
+    q.istart[a] = (int32_t)j;   // the global start, for the gradient pass
     const int t = q.types[a];
-    for (int k = 0; k < q.K && j < j_end; ++k) {
+    for (int k = 0; k < q.K; ++k) {
         const float *c = q.cand + 3 * ((size_t)k * q.n_atoms + a);
         if (!__builtin_isnan(c[0])) {
             q.exp_xyz[3 * j + 0] = c[0];
