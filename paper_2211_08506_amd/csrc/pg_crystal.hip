@@ -5,33 +5,32 @@
 // take this path.  Set-up, all on the GPU and free of order-dependent
 // atomics in anything that reaches the output:
 //   prep:    three threads per atom (one per axis): exact window ranges
-//            (nearest periodic images included) into the atom's record, and
+//            (nearest periodic images included) into the atom's record,
 //            counts of the atom per (channel, structure) and per (channel,
-//            prep block);
+//            prep block), and (MFMA form) the 32-voxel tiles its x and y
+//            windows meet;
 //   scan:    exclusive scans of both count arrays in channel-major order;
 //   place:   a stable partition of all atoms by channel (ballot ranks within
 //            a block): channel c's atoms in index order, so each (structure,
-//            channel) pair -- a "run" -- is one contiguous stretch of the list;
-//   zsort:   per run, the atoms' z images sorted stably by window start, so
-//            each plane's images are one contiguous range of that order.
-// Then one of two plane forms, one workgroup per (structure, channel, z
-// plane[, 128 x 128 super-tile]):
+//            channel) pair -- a "run" -- is one contiguous stretch of the list.
+// Then one of two plane forms:
 //   mfma:    the plane is a product of two factor matrices (separability of
 //            the Gaussian and of the cube cutoff, Sec. III-A / IV-C):
-//            G[y][x] = sum_k phi_z^k(z) phi_y^k(y) phi_x^k(x).  An operand
-//            kernel writes phi_y and phi_x of every image once, in 32-image
-//            blocks laid out as the matrix cores read them; the plane kernel
-//            stages each block's rows of its super-tile in LDS once per
-//            workgroup (phi_y scaled by phi_z of the plane on the way), two
-//            blocks ahead of the contraction.  bf16 grids contract bf16
-//            operands on v_mfma_f32_32x32x16_bf16; fp32 grids split the
-//            operands into fp16 hi/lo pairs and take three
-//            v_mfma_f32_32x32x16_f16 per step (FP32 accuracy); FP32
-//            accumulation in both;
-//   window:  the same sum in FP32 on the vector ALUs -- per 32-image step the
-//            images' dense factor rows go to LDS with a bit mask of the
-//            images meeting each 32 x 32 tile, and each lane accumulates a
-//            4 x 4 block of voxels over its tile's images.
+//            G[y][x] = sum_k phi_z^k(z) phi_y^k(y) phi_x^k(x).  One launch
+//            sorts every run's z images into per-32 x 32-tile-column lists
+//            (ordered by z start) and, beside it, writes each atom's phi_x
+//            and phi_y over the 32-voxel tiles its windows meet ("factor
+//            slots"); the tile kernels then contract, per 32 x 32 tile and 4
+//            planes, the entries of the tile column's list (block-sparse K):
+//            bf16 grids on v_mfma_f32_32x32x16_bf16 (A = phi_z phi_y formed in
+//            FP32 and rounded to bf16 once), fp32 grids on
+//            v_mfma_f32_32x32x2_f32 with FP32 operands; FP32 accumulation;
+//   window:  per run, the atoms' z images sorted stably by window start (each
+//            plane's images one contiguous range), then the same sum in FP32
+//            on the vector ALUs, one workgroup per (structure, channel, z):
+//            per 32-image step the images' dense factor rows go to LDS with a
+//            bit mask of the images meeting each 32 x 32 tile, and each lane
+//            accumulates a 4 x 4 block of voxels over its tile's images.
 // Both forms sum each voxel's atoms in an order fixed by the input alone
 // (z-window start, then list order), so results are bitwise reproducible.
 #include <type_traits>
@@ -89,8 +88,8 @@ __device__ __forceinline__ uint16_t bf16_bits(float v)
     return __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
-// Slot value storage: bf16 bits (the bf16 contraction) or float (the
-// split-fp16 contraction).
+// Slot value storage: bf16 bits (x slots of the bf16 contraction) or float
+// (y slots, and x slots of the fp32 contraction).
 __device__ __forceinline__ void op_store(uint16_t *p, float v) { *p = bf16_bits(v); }
 __device__ __forceinline__ void op_store(float *p, float v) { *p = v; }
 // four consecutive slot values (p aligned to four elements)

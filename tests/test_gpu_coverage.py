@@ -4,7 +4,7 @@ The library promises to write every element of `out` (zeros included), so
 callers need not clear it.  Each case fills the output with NaN, runs the
 forward map through the C ABI, and requires no NaN to remain and a second
 run to give the same bits.  Shapes are ragged (not multiples of the vector
-width, the wave or the 128 x 128 MFMA super-tile) and include structures
+width, the wave or the 32 x 32 MFMA tile) and include structures
 without atoms.  That each element is written exactly once is what the HBM
 write counters show for the headline kernel (WRITE_SIZE equals the output
 size), not something an output can reveal.

@@ -199,9 +199,9 @@ def test_step_binned_cells(pg, dev):
     off = np.array([0, 400, 700], np.int32)
     xyz = rng.uniform(0, 8.0, size=(700, 3)).astype(np.float32)
     b = synth.Batch(xyz, rng.integers(0, 3, 700).astype(np.int32), off)
-    # the binned FP32 window form: exact FP32 products, so the residual is
-    # held to the FP32 bar (the split-fp16 MFMA form is accurate to a few
-    # 1e-6 relative in G', which a residual much smaller than G' magnifies)
+    # the binned FP32 window form: the residual is held to the FP32 bar on
+    # the vector form (a residual much smaller than G' magnifies any
+    # relative error in G')
     say("case reversal step periodic cells, binned window form")
     step_case(pg, dev, b, sig, (40, 40, 40), 0.21, (0, 0, 0), "window", cell=8.0, lr=0.005)
 

@@ -204,10 +204,11 @@ def test_weighted_binned_path(pg, dev, form, dtype, tol):
 
 @pytest.mark.parametrize("scale", [1e-6, 1e5])
 def test_weighted_split_mfma_weight_range(pg, dev, scale):
-    """The split-fp16 MFMA form for float32 grids scales each plane by a
-    power of two chosen from its largest |phi_z w|: weights of 1e-6 or 1e5
-    (beyond fp16's range once multiplied out), mixed in sign and spread over
-    three decades within a channel, stay at the FP32 bar."""
+    """The MFMA form for float32 grids with weights of 1e-6 or 1e5 (far from
+    1 once multiplied into phi_z), mixed in sign and spread over three
+    decades within a channel: FP32 operands and accumulation keep the
+    result at the FP32 bar (a check kept from an earlier fp16-split operand
+    form, whose per-plane power-of-two scaling it guarded)."""
     rng = np.random.default_rng(29)
     off = np.array([0, 400, 700], np.int32)
     xyz = rng.uniform(0, 8, size=(700, 3)).astype(np.float32)
