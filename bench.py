@@ -6,10 +6,10 @@
 A step is one pass of the forward hot path over one batch: inputs are
 staged in HBM once, then each step runs the per-atom window bounds and 1-D
 factors, the accumulation and the dense write of the whole B x C x D x H x W
-grid (for molecules one persistent window-kernel launch, launched directly:
-the library replays graphs only for sequences of several kernels; for large
-periodic cells the binned path's set-up kernels and its plane kernel,
-replayed from a captured HIP graph).  Rank 0 prints
+grid (for molecules one persistent window-kernel launch; for large periodic
+cells the binned path's set-up kernels and its plane kernel), launched
+directly: replaying captured HIP graphs (--graph) measured slower on MI355X
+for every sequence here.  Rank 0 prints
 one JSON line on stdout; progress goes to stderr.
 
 Workloads (synth.WORKLOADS):
@@ -259,7 +259,9 @@ def main():
     ap.add_argument("--parity-structures", type=int, default=64,
                     help="structures of the timed output compared with the FP64 oracle "
                          "(all of them for the crystal workload)")
-    ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured HIP graphs (the library's graph option) instead of direct "
+                         "launches; direct launches measured faster on MI355X")
     ap.add_argument("--save-tuning", default=None, help="write the tuning table to this path")
     ap.add_argument("--tuning", default=None, help="load this tuning table (instead of the shipped one)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -318,8 +320,8 @@ def main():
     log(f"[bench] {b.n_atoms} atoms, {evals} atom-voxel evaluations per pass")
 
     ctx = pg.Context(0, tuning=args.tuning or "shipped")
-    ctx.set_option(pg.PG_OPT_GRAPH, 0 if args.no_graph else 1)
-    launch = "direct launch" if args.no_graph else "HIP graph"
+    ctx.set_option(pg.PG_OPT_GRAPH, 1 if args.graph else 0)
+    launch = "HIP graph" if args.graph else "direct launches"
     extra = {}
     value = args.value
     metric = METRICS[wl.name] + (" [box form]" if value == "box" else "") + \
@@ -457,7 +459,7 @@ def main():
         del out
         if wl.kind == "crystal":
             kname = ("binned path, whole step: cr_clear, cr_prep, cr_scan, cr_place, "
-                     + (f"cr_slot, cr_tsort, cr_tile_{'bf16' if esize == 2 else 'f32'}_kernel"
+                     + (f"cr_sort_slot, cr_tile_{'bf16' if esize == 2 else 'f32'}_kernel"
                         if plan["form"] == "mfma" else "cr_zsort, cr_window_kernel"))
             # the other form / dtype pairs, for the per-shape decision
             for form, dt in (("mfma", torch.bfloat16), ("window", torch.float32),
@@ -509,7 +511,7 @@ def main():
             "frac_of_fill": achieved / fill_gbs,
         })
         kind = "forward"
-        if not args.no_graph and plan["form"] == "window" and not plan["binned"]:
+        if args.graph and plan["form"] == "window" and not plan["binned"]:
             # the library launches its one-kernel molecule form directly
             launch = "direct launch (one kernel; the graph option replays only multi-kernel steps)"
 
