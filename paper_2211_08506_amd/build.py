@@ -38,8 +38,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=
 # Host-side AddressSanitizer + UndefinedBehaviorSanitizer (the runtime's
 # validation, planning, workspace sizing and tuning-file parser; the device
 # code is built as usual).  For CPU-only test runs: the library then needs
-# the clang sanitizer runtime preloaded (see run_sanitized_tests in
-# oracle/build.py's neighbour, tests/sanitize.sh).
+# the clang sanitizer runtime preloaded, as tests/sanitize.sh does.
 SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all",
             "-Xarch_host", "-shared-libsan"]
