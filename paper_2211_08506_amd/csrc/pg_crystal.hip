@@ -1220,61 +1220,122 @@ __global__ void __launch_bounds__(256) cr_window_kernel(GridParams p, CrystalPar
             for (int e = 0; e < 4; ++e)
                 acc[i][rr][e] = 0.f;
 
+    // The thread's image of each step (image tid / 8 of the step, an eighth
+    // of its windows per thread).  Point form: its z-list entry is loaded one
+    // step ahead, at the start of the previous step's factor pass, and the
+    // first two x and y window ranges of its atom (an atom has a second
+    // range near a periodic boundary) during the previous step's
+    // accumulation, so a factor pass waits on global memory only for a
+    // third range.  The loads take indices clamped into the plane's range,
+    // so they need no branch.  The box form, whose edge walk needs more
+    // registers, loads them at the start of each factor pass.
+    constexpr bool PRE = !BOX;
+    const int kimg = tid >> 3, part = tid & 7;
+    struct Ranges2 {
+        int n[2], lo[2][2], hi[2][2];   // [axis][range]
+        float bh[2][2], bl[2][2];
+    };
+    auto entry_at = [&](uint32_t k0n) -> ZEntry {
+        return q.zlist[eb + min(k0n + (uint32_t)kimg, end - 1u)];
+    };
+    auto ranges2 = [&](const ZEntry &ze) -> Ranges2 {
+        const AtomWindow &w = q.table[ze.atom];
+        Ranges2 r;
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            r.n[ax] = w.n[ax];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                r.lo[ax][j] = w.lo[ax][j];
+                r.hi[ax][j] = w.hi[ax][j];
+                r.bh[ax][j] = w.bh[ax][j];
+                r.bl[ax][j] = w.bl[ax][j];
+            }
+        }
+        return r;
+    };
+    ZEntry ze{};
+    Ranges2 rg{};
+    if (PRE && first < end) {
+        ze = entry_at(first);
+        rg = ranges2(ze);
+    }
     for (uint32_t k0 = first; k0 < end; k0 += KC) {
         const int kn = (int)min((uint32_t)KC, end - k0);
+        ZEntry ze_next{};
+        if (PRE)
+            ze_next = entry_at(k0 + KC);   // in flight through this factor pass
+        else
+            ze = entry_at(k0);
         typedef uint32_t u4 __attribute__((ext_vector_type(4)));
         for (int i = tid; i < 8 * (W32 + H32); i += blockDim.x)
             ((u4 *)gx)[i] = u4{0u, 0u, 0u, 0u};
         for (int i = tid; i < ntiles; i += blockDim.x)
             tmask[i] = 0u;
         __syncthreads();
-        {
-            const int k = tid >> 3, part = tid & 7;
-            if (k < kn) {
-                const ZEntry ze = q.zlist[eb + k0 + k];
-                if (z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
-                    const int ti = image_type(p, q, ze.atom, c);
-                    const float inv2s2 = p.inv2s2[ti], isq2s = p.isq2s[ti];
-                    const float g = factor1d(box, ze.bh, ze.bl, p.h[2], z, inv2s2, isq2s) *
-                                    image_weight(p, ze.atom, c);
-                    const AtomWindow &w = q.table[ze.atom];
-                    uint32_t tx = 0u, ty = 0u;   // tile columns / rows the windows meet
-                    // each of the image's 8 threads takes a contiguous eighth of
-                    // each window (the box form walks its edges once)
-                    for (int r = 0; r < w.n[0]; ++r) {
-                        const float bh = w.bh[0][r], bl = w.bl[0][r];
-                        for (int t = w.lo[0][r] >> 5; t <= (w.hi[0][r] >> 5); ++t)
-                            tx |= 1u << t;
-                        const int L8 = (w.hi[0][r] - w.lo[0][r] + 8) >> 3;
-                        const int lo = w.lo[0][r] + part * L8, hi = min(w.hi[0][r], lo + L8 - 1);
-                        if (box)
-                            box_walk<false>(bh, bl, p.h[0], lo, hi, isq2s, 1.f, gx + k * W32);
-                        else
-                            for (int v = lo; v <= hi; ++v)
-                                gx[k * W32 + v] = gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2);
-                    }
-                    for (int r = 0; r < w.n[1]; ++r) {
-                        const float bh = w.bh[1][r], bl = w.bl[1][r];
-                        for (int t = w.lo[1][r] >> 5; t <= (w.hi[1][r] >> 5); ++t)
-                            ty |= 1u << t;
-                        const int L8 = (w.hi[1][r] - w.lo[1][r] + 8) >> 3;
-                        const int lo = w.lo[1][r] + part * L8, hi = min(w.hi[1][r], lo + L8 - 1);
-                        if (box)
-                            box_walk<true>(bh, bl, p.h[1], lo, hi, isq2s, g, gy + k * H32);
-                        else
-                            for (int v = lo; v <= hi; ++v)
-                                gy[k * H32 + v] = g * gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2);
-                    }
-                    if (part == 0)
-                        for (int tr = 0; tr < nty; ++tr)
-                            if ((ty >> tr) & 1u)
-                                for (int tc = 0; tc < ntx; ++tc)
-                                    if ((tx >> tc) & 1u)
-                                        atomicOr(&tmask[tr * ntx + tc], 1u << k);
-                }
+        if (kimg < kn && z >= range_lo(ze.range) && z <= range_hi(ze.range)) {
+            const int k = kimg;
+            const int ti = image_type(p, q, ze.atom, c);
+            const float inv2s2 = p.inv2s2[ti], isq2s = p.isq2s[ti];
+            const float g = factor1d(box, ze.bh, ze.bl, p.h[2], z, inv2s2, isq2s) *
+                            image_weight(p, ze.atom, c);
+            const AtomWindow &w = q.table[ze.atom];
+            uint32_t tx = 0u, ty = 0u;   // tile columns / rows the windows meet
+            // each of the image's 8 threads takes a contiguous eighth of
+            // each window (the box form walks its edges once)
+            auto row_x = [&](int wlo, int whi, float bh, float bl) {
+                for (int t = wlo >> 5; t <= (whi >> 5); ++t)
+                    tx |= 1u << t;
+                const int L8 = (whi - wlo + 8) >> 3;
+                const int lo = wlo + part * L8, hi = min(whi, lo + L8 - 1);
+                if (box)
+                    box_walk<false>(bh, bl, p.h[0], lo, hi, isq2s, 1.f, gx + k * W32);
+                else
+                    for (int v = lo; v <= hi; ++v)
+                        gx[k * W32 + v] = gauss1d(offset_at(bh, bl, p.h[0], v), inv2s2);
+            };
+            auto row_y = [&](int wlo, int whi, float bh, float bl) {
+                for (int t = wlo >> 5; t <= (whi >> 5); ++t)
+                    ty |= 1u << t;
+                const int L8 = (whi - wlo + 8) >> 3;
+                const int lo = wlo + part * L8, hi = min(whi, lo + L8 - 1);
+                if (box)
+                    box_walk<true>(bh, bl, p.h[1], lo, hi, isq2s, g, gy + k * H32);
+                else
+                    for (int v = lo; v <= hi; ++v)
+                        gy[k * H32 + v] = g * gauss1d(offset_at(bh, bl, p.h[1], v), inv2s2);
+            };
+            if (PRE) {
+                // a listed image meets the grid on every axis: at least one range each
+                row_x(rg.lo[0][0], rg.hi[0][0], rg.bh[0][0], rg.bl[0][0]);
+                if (rg.n[0] > 1)
+                    row_x(rg.lo[0][1], rg.hi[0][1], rg.bh[0][1], rg.bl[0][1]);
+                for (int r = 2; r < rg.n[0]; ++r)
+                    row_x(w.lo[0][r], w.hi[0][r], w.bh[0][r], w.bl[0][r]);
+                row_y(rg.lo[1][0], rg.hi[1][0], rg.bh[1][0], rg.bl[1][0]);
+                if (rg.n[1] > 1)
+                    row_y(rg.lo[1][1], rg.hi[1][1], rg.bh[1][1], rg.bl[1][1]);
+                for (int r = 2; r < rg.n[1]; ++r)
+                    row_y(w.lo[1][r], w.hi[1][r], w.bh[1][r], w.bl[1][r]);
+            } else {
+                for (int r = 0; r < w.n[0]; ++r)
+                    row_x(w.lo[0][r], w.hi[0][r], w.bh[0][r], w.bl[0][r]);
+                for (int r = 0; r < w.n[1]; ++r)
+                    row_y(w.lo[1][r], w.hi[1][r], w.bh[1][r], w.bl[1][r]);
             }
+            if (part == 0)
+                for (int tr = 0; tr < nty; ++tr)
+                    if ((ty >> tr) & 1u)
+                        for (int tc = 0; tc < ntx; ++tc)
+                            if ((tx >> tc) & 1u)
+                                atomicOr(&tmask[tr * ntx + tc], 1u << k);
         }
         __syncthreads();
+        // the next step's ranges, in flight through the accumulation
+        if (PRE) {
+            ze = ze_next;
+            rg = ranges2(ze);
+        }
 #pragma unroll
         for (int i = 0; i < TMAX; ++i) {
             const int t = wave + 4 * i;
