@@ -71,8 +71,9 @@ def check(name, g, ref, tol):
 @pytest.mark.parametrize("dims,h", [((24, 24, 24), 1.0 / 3.0), ((40, 40, 40), 0.21)])
 def test_periodic_cells(pg, dev, dims, h):
     """Cells of 400 and 300 atoms (above the window kernel's capacity) with
-    the grid equal to the cell and larger than the cell (atoms seen through
-    up to three images per axis)."""
+    the grid equal to the cell and larger than the cell (atoms near a face
+    seen through two images per axis; a third needs a grid exactly
+    2L - 2rc wide)."""
     sig = synth.sigma_table(3, 0.3, 0.45)
     b = cell_batch(31, [400, 300], 8.0, 3)
     b.xyz[0] = [0.01, 7.99, 4.0]               # atoms at the faces
